@@ -1,0 +1,784 @@
+/*
+ * setd_oracle.c -- plain FP64 CPU oracle for the stochastic exponential-time-
+ * differencing (SETD) pseudo-spectral step of Johnsrud & Rana, "Efficient
+ * Pseudo-spectral Algorithms for Statistical Field Theories" (arXiv 2511.22510).
+ *
+ * TEST INFRASTRUCTURE.  This file is the slow, obviously-correct reference that
+ * the GPU library is checked against.  Only the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg may load it; the product path never does, and
+ * it shares no code, header or table with the GPU library.
+ *
+ * Everything is double precision.  Arrays are full (unpruned) spectra in FFT
+ * order: a real field keeps the half spectrum N0 x .. x (N_{d-1}/2+1) of the
+ * real-to-complex transform, a complex field the whole N0 x .. x N_{d-1} array.
+ * Complex numbers cross the C ABI as interleaved (re, im) doubles.
+ *
+ * Readings of the paper taken here where it is silent or inconsistent:
+ *  - DFT sign and scale (App. A): forward X_a = sum_n x_n e^{-2 pi i a.n/N},
+ *    inverse x_n = N^-d sum_a X_a e^{+2 pi i a.n/N}.  The printed discrete pair
+ *    has the opposite sign to the continuous one and an inverse without 1/N^d;
+ *    the field/lattice mapping of App. A needs the 1/N^d.  The sign does not
+ *    change any model here (c(k) even, |grad h|^2 and the noise symmetric).
+ *  - Dealiasing (Sec. 4, step 1) is the 2/3 truncation rule: a mode is kept
+ *    iff 3|a_i| < N_i on every axis; it masks F and the updated state.
+ *  - Noise amplitude (Sec. 4, step 3; Eq. SETD1; App. A):
+ *    G_a = prod_i (N_i^2/L_i)^{1/2} sqrt(2 D_a h phi1(2 Re(c_a) h)), which is
+ *    the printed (N^2/L)^{d/2} sqrt(D/c (e^{2ch}-1)) written without the 0/0
+ *    at c = 0 and with Re(c) for complex c (the variance of int e^{c(h-s)} dW).
+ *  - SETD2 weights (Eq. SETD2): [(1+x)e^x-1-2x]/(c^2 h) = h(phi1+phi2) and
+ *    [1+x-e^x]/(c^2 h) = -h phi2 with x = c h; phi1, phi2 by Taylor series for
+ *    |x| < 1 (replacing the "use Euler-Maruyama for small c" advice of Sec. 4)
+ *    and closed forms otherwise.  The first SETD2 step uses F_{-1} = F_0.
+ *  - Fourier-space noise (App. B): Philox4x32-10 (Salmon et al., SC'11) keyed
+ *    by the seed, counter (element index, step, realization, tag), two 53-bit
+ *    uniforms, Box-Muller.  Complex modes get (z1 + i z2)/sqrt2, self-conjugate
+ *    modes of a real field get z1, a conjugate pair on the a_d in {0, N_d/2}
+ *    planes draws once at the smaller linear index and the partner takes the
+ *    conjugate.  Masked modes draw nothing.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Problem statement (Sec. 4, Eq. general_fourier; App. A lattice)           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int ndim;              /* 1..3                                          */
+    int n[3];              /* points per axis, powers of two                */
+    double dx;             /* lattice spacing; L_i = n_i dx                 */
+    int complex_field;     /* 0 real order parameter, 1 complex             */
+    double c0[2], c2[2], c4[2]; /* c(k) = c0 + c2 k^2 + c4 k^4 (re, im)     */
+    int nl;                /* 0 -u phi^3, 1 -u k^2 phi^3, 2 KPZ, 3 CGL, 4 none */
+    double nl_par[2];      /* u | lambda | beta                             */
+    double noise_D;        /* D in D(k) = D k^kpow                          */
+    int noise_kpow;        /* 0 or 2                                        */
+    double h;              /* time step                                     */
+    int order;             /* 1 SETD1, 2 SETD2                              */
+    int realizations;
+    uint64_t seed;
+    int dealias;           /* 0 none, 1 the 2/3 rule                        */
+    int ic_kind;           /* 0 zero, 1 Gaussian per site                   */
+    double ic_sigma;
+} orc_desc;
+
+enum { NL_PHI3 = 0, NL_PHI3_CONS = 1, NL_KPZ = 2, NL_CGL = 3, NL_NONE = 4 };
+
+/* ------------------------------------------------------------------------ */
+/* Textbook radix-2 FFT, one line at a time                                 */
+/* ------------------------------------------------------------------------ */
+
+/* twiddle tables exp(sign 2 pi i k / n), k < n/2, one per (n, sign) */
+typedef struct { int n; int sign; cplx* w; } twtab;
+static twtab g_tw[32];
+static int g_ntw = 0;
+
+static const cplx* twiddles(int n, int sign)
+{
+    int i;
+    for (i = 0; i < g_ntw; i++)
+        if (g_tw[i].n == n && g_tw[i].sign == sign) return g_tw[i].w;
+    cplx* w = (cplx*)malloc(sizeof(cplx) * (size_t)(n / 2 + 1));
+    for (int k = 0; k <= n / 2; k++) {
+        double ang = sign * 2.0 * M_PI * (double)k / (double)n;
+        w[k] = cos(ang) + I * sin(ang);
+    }
+    if (g_ntw < 32) {
+        g_tw[g_ntw].n = n; g_tw[g_ntw].sign = sign; g_tw[g_ntw].w = w; g_ntw++;
+    }
+    return w;
+}
+
+/* in place, unscaled: x_k <- sum_m x_m exp(sign 2 pi i k m / n) */
+static void fft_line(cplx* x, int n, int sign, const cplx* w)
+{
+    /* bit-reversal permutation */
+    for (int i = 1, j = 0; i < n; i++) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) { cplx t = x[i]; x[i] = x[j]; x[j] = t; }
+    }
+    /* butterflies of growing length */
+    for (int len = 2; len <= n; len <<= 1) {
+        int half = len / 2, step = n / len;
+        for (int i = 0; i < n; i += len)
+            for (int k = 0; k < half; k++) {
+                cplx u = x[i + k];
+                cplx v = x[i + k + half] * w[k * step];
+                x[i + k] = u + v;
+                x[i + k + half] = u - v;
+            }
+    }
+}
+
+static int is_pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
+
+/* N-dimensional complex FFT, row-major shape n[0..ndim).  sign = -1 forward
+   (unscaled), sign = +1 inverse (scaled by 1/prod n). */
+static void fftn(cplx* x, int ndim, const int* n, int sign)
+{
+    size_t total = 1;
+    for (int d = 0; d < ndim; d++) total *= (size_t)n[d];
+    for (int ax = 0; ax < ndim; ax++) {
+        size_t inner = 1, outer = 1;
+        for (int d = ax + 1; d < ndim; d++) inner *= (size_t)n[d];
+        for (int d = 0; d < ax; d++) outer *= (size_t)n[d];
+        int len = n[ax];
+        const cplx* w = twiddles(len, sign);
+        long nlines = (long)(outer * inner);
+#pragma omp parallel
+        {
+            cplx* tmp = (cplx*)malloc(sizeof(cplx) * (size_t)len);
+#pragma omp for schedule(static)
+            for (long l = 0; l < nlines; l++) {
+                size_t o = (size_t)l / inner, i = (size_t)l % inner;
+                cplx* base = x + o * (size_t)len * inner + i;
+                for (int m = 0; m < len; m++) tmp[m] = base[(size_t)m * inner];
+                fft_line(tmp, len, sign, w);
+                for (int m = 0; m < len; m++) base[(size_t)m * inner] = tmp[m];
+            }
+            free(tmp);
+        }
+    }
+    if (sign > 0) {
+        double s = 1.0 / (double)total;
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < (long)total; i++) x[i] *= s;
+    }
+}
+
+/* real -> half spectrum: complex FFT of the real data, keep a_d in [0, N_d/2] */
+static void rfftn(const double* xr, cplx* out, int ndim, const int* n, cplx* work)
+{
+    size_t total = 1;
+    for (int d = 0; d < ndim; d++) total *= (size_t)n[d];
+    for (size_t i = 0; i < total; i++) work[i] = xr[i];
+    fftn(work, ndim, n, -1);
+    int nl = n[ndim - 1], nh = nl / 2 + 1;
+    size_t rows = total / (size_t)nl;
+    for (size_t r = 0; r < rows; r++)
+        for (int j = 0; j < nh; j++) out[r * nh + j] = work[r * nl + j];
+}
+
+/* half spectrum -> real: Hermitian extension X_a = conj(X_{-a}) for the
+   missing a_d > N_d/2, complex inverse FFT, real part. */
+static void irfftn(const cplx* in, double* xr, int ndim, const int* n, cplx* work)
+{
+    size_t total = 1;
+    for (int d = 0; d < ndim; d++) total *= (size_t)n[d];
+    int nl = n[ndim - 1], nh = nl / 2 + 1;
+    size_t rows = total / (size_t)nl;
+    for (size_t r = 0; r < rows; r++) {
+        /* row index r = multi-index (j_0..j_{d-2}); its negation */
+        size_t rem = r, neg = 0, mul = 1;
+        for (int d = ndim - 2; d >= 0; d--) {
+            size_t j = rem % (size_t)n[d]; rem /= (size_t)n[d];
+            size_t jn = (j == 0) ? 0 : (size_t)n[d] - j;
+            neg += jn * mul; mul *= (size_t)n[d];
+        }
+        for (int j = 0; j < nl; j++) {
+            if (j < nh) work[r * nl + j] = in[r * nh + j];
+            else work[r * nl + j] = conj(in[neg * nh + (size_t)(nl - j)]);
+        }
+    }
+    fftn(work, ndim, n, +1);
+    for (size_t i = 0; i < total; i++) xr[i] = creal(work[i]);
+}
+
+/* exported transforms, interleaved complex */
+int orc_fftn(double* data, int ndim, const int* n, int sign)
+{
+    if (ndim < 1 || ndim > 3) return -1;
+    for (int d = 0; d < ndim; d++) if (!is_pow2(n[d])) return -1;
+    fftn((cplx*)data, ndim, n, sign < 0 ? -1 : +1);
+    return 0;
+}
+
+int orc_rfftn(const double* x, double* out, int ndim, const int* n)
+{
+    if (ndim < 1 || ndim > 3) return -1;
+    size_t total = 1;
+    for (int d = 0; d < ndim; d++) { if (!is_pow2(n[d]) || n[d] < 2) return -1; total *= (size_t)n[d]; }
+    cplx* work = (cplx*)malloc(sizeof(cplx) * total);
+    rfftn(x, (cplx*)out, ndim, n, work);
+    free(work);
+    return 0;
+}
+
+int orc_irfftn(const double* in, double* x, int ndim, const int* n)
+{
+    if (ndim < 1 || ndim > 3) return -1;
+    size_t total = 1;
+    for (int d = 0; d < ndim; d++) { if (!is_pow2(n[d]) || n[d] < 2) return -1; total *= (size_t)n[d]; }
+    cplx* work = (cplx*)malloc(sizeof(cplx) * total);
+    irfftn((const cplx*)in, x, ndim, n, work);
+    free(work);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller          */
+/* ------------------------------------------------------------------------ */
+void orc_philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* two standard normals from one Philox block with counter (e, n, r, tag) */
+void orc_normal_pair(uint64_t seed, uint32_t e, uint32_t n, uint32_t r, uint32_t tag,
+                     double* z1, double* z2)
+{
+    uint32_t ctr[4] = { e, n, r, tag };
+    uint32_t key[2] = { (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
+    uint32_t x[4];
+    orc_philox(ctr, key, x);
+    /* 53-bit integers from the word pairs, mapped to the open interval (0,1) */
+    uint64_t m1 = ((uint64_t)x[0] << 21) | (uint64_t)(x[1] >> 11);
+    uint64_t m2 = ((uint64_t)x[2] << 21) | (uint64_t)(x[3] >> 11);
+    double u1 = ((double)m1 + 0.5) * 0x1p-53;
+    double u2 = ((double)m2 + 0.5) * 0x1p-53;
+    double rad = sqrt(-2.0 * log(u1));
+    *z1 = rad * cos(2.0 * M_PI * u2);
+    *z2 = rad * sin(2.0 * M_PI * u2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* ETD functions phi1(x) = (e^x-1)/x, phi2(x) = (e^x-1-x)/x^2  (Eq. SETD1/2) */
+/* ------------------------------------------------------------------------ */
+static cplx cexpm1_(cplx x)
+{
+    double a = creal(x), b = cimag(x);
+    double s = sin(0.5 * b);
+    return (expm1(a) * cos(b) - 2.0 * s * s) + I * (exp(a) * sin(b));
+}
+
+static void phi12(cplx x, cplx* p1, cplx* p2)
+{
+    if (cabs(x) < 1.0) {
+        /* Taylor series: phi1 = sum x^k/(k+1)!, phi2 = sum x^k/(k+2)! */
+        cplx s1 = 0, s2 = 0, xk = 1;
+        double f1 = 1.0, f2 = 2.0;   /* (k+1)!, (k+2)! at k = 0 */
+        for (int k = 0; k < 24; k++) {
+            s1 += xk / f1;
+            s2 += xk / f2;
+            xk *= x;
+            f1 *= (double)(k + 2);
+            f2 *= (double)(k + 3);
+        }
+        *p1 = s1; *p2 = s2;
+    } else {
+        cplx em = cexpm1_(x);
+        *p1 = em / x;
+        *p2 = (em - x) / (x * x);
+    }
+}
+
+void orc_phi12(double xr, double xi, double* out4)
+{
+    cplx p1, p2;
+    phi12(xr + I * xi, &p1, &p2);
+    out4[0] = creal(p1); out4[1] = cimag(p1);
+    out4[2] = creal(p2); out4[3] = cimag(p2);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Simulation state                                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    orc_desc d;
+    int r_first, R;            /* realizations [r_first, r_first + R)        */
+    int nh[3];                 /* spectral shape                            */
+    size_t nspec, nreal;
+    cplx* phi;                 /* R x nspec                                 */
+    cplx* fprev;               /* R x nspec                                 */
+    int have_prev;
+    int64_t step;
+    /* per-mode data (Sec. 4 step 3), computed once */
+    double* k2;                /* |k|^2                                     */
+    int* kidx;                 /* signed index per axis, 3 per mode         */
+    unsigned char* mask;
+    cplx* E; cplx* wa; cplx* wb; double* G;
+    cplx* pref;                /* prefactor of the transformed nonlinearity */
+    /* observables */
+    cplx* snap; int64_t snap_step; int have_snap;
+    double* acc; double acc_count; int nbins;
+    /* scratch */
+    cplx* work; cplx* work2; double* rwork; double* rwork2; cplx* F;
+} orc_sim;
+
+static size_t prod(const int* n, int d) { size_t p = 1; for (int i = 0; i < d; i++) p *= (size_t)n[i]; return p; }
+
+/* signed wavenumber index for FFT-order position j on an axis of length n */
+static int signed_idx(int j, int n) { return (j < n / 2) ? j : j - n; }
+
+/* linear index in the spectral array of FFT-order multi-index j */
+static size_t lin_index(const orc_sim* s, const int* j)
+{
+    size_t e = 0;
+    for (int d = 0; d < s->d.ndim; d++) e = e * (size_t)s->nh[d] + (size_t)j[d];
+    return e;
+}
+
+static void unlin(const orc_sim* s, size_t e, int* j)
+{
+    for (int d = s->d.ndim - 1; d >= 0; d--) { j[d] = (int)(e % (size_t)s->nh[d]); e /= (size_t)s->nh[d]; }
+}
+
+static int isqrt_ceil(long m)
+{
+    if (m <= 0) return 0;
+    long s = (long)floor(sqrt((double)m));
+    while (s * s > m) s--;
+    while ((s + 1) * (s + 1) <= m) s++;
+    return (s * s == m) ? (int)s : (int)(s + 1);
+}
+
+void orc_destroy(orc_sim* s);
+
+orc_sim* orc_create_subset(const orc_desc* d, int r_first, int r_count)
+{
+    if (d->ndim < 1 || d->ndim > 3) return NULL;
+    for (int i = 0; i < d->ndim; i++) if (!is_pow2(d->n[i]) || d->n[i] < 4) return NULL;
+    if (d->order != 1 && d->order != 2) return NULL;
+    if (!(d->h > 0) || !(d->dx > 0)) return NULL;
+    if (d->realizations < 1 || r_first < 0 || r_count < 1 || r_first + r_count > d->realizations) return NULL;
+    orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
+    s->d = *d;
+    s->r_first = r_first; s->R = r_count;
+    for (int i = 0; i < d->ndim; i++) s->nh[i] = d->n[i];
+    if (!d->complex_field) s->nh[d->ndim - 1] = d->n[d->ndim - 1] / 2 + 1;
+    s->nspec = prod(s->nh, d->ndim);
+    s->nreal = prod(d->n, d->ndim);
+    size_t R = (size_t)r_count;
+    s->phi = (cplx*)calloc(R * s->nspec, sizeof(cplx));
+    s->fprev = (cplx*)calloc(R * s->nspec, sizeof(cplx));
+    s->k2 = (double*)malloc(sizeof(double) * s->nspec);
+    s->kidx = (int*)malloc(sizeof(int) * 3 * s->nspec);
+    s->mask = (unsigned char*)malloc(s->nspec);
+    s->E = (cplx*)malloc(sizeof(cplx) * s->nspec);
+    s->wa = (cplx*)malloc(sizeof(cplx) * s->nspec);
+    s->wb = (cplx*)malloc(sizeof(cplx) * s->nspec);
+    s->G = (double*)malloc(sizeof(double) * s->nspec);
+    s->pref = (cplx*)malloc(sizeof(cplx) * s->nspec);
+    s->work = (cplx*)malloc(sizeof(cplx) * s->nreal);
+    s->work2 = (cplx*)malloc(sizeof(cplx) * s->nreal);
+    s->rwork = (double*)malloc(sizeof(double) * s->nreal);
+    s->rwork2 = (double*)malloc(sizeof(double) * s->nreal);
+    s->F = (cplx*)malloc(sizeof(cplx) * s->nspec);
+    if (!s->phi || !s->fprev || !s->k2 || !s->kidx || !s->mask || !s->E || !s->wa || !s->wb ||
+        !s->G || !s->pref || !s->work || !s->work2 || !s->rwork || !s->rwork2 || !s->F) {
+        orc_destroy(s);
+        return NULL;
+    }
+
+    /* lattice (App. A): L_i = N_i dx, dk_i = 2 pi / L_i; noise lattice factor */
+    double lat = 1.0;
+    for (int i = 0; i < d->ndim; i++) {
+        double L = d->n[i] * d->dx;
+        lat *= sqrt((double)d->n[i] * (double)d->n[i] / L);
+    }
+    double h = d->h;
+    int maxsq = 0;
+    for (int i = 0; i < d->ndim; i++) maxsq += (d->n[i] / 2) * (d->n[i] / 2);
+    s->nbins = isqrt_ceil(maxsq) + 1;
+    s->acc = (double*)calloc((size_t)2 * (size_t)s->nbins, sizeof(double));
+
+    for (size_t e = 0; e < s->nspec; e++) {
+        int j[3] = { 0, 0, 0 };
+        unlin(s, e, j);
+        double k2 = 0.0;
+        int keep = 1;
+        for (int i = 0; i < d->ndim; i++) {
+            int a = signed_idx(j[i], d->n[i]);
+            s->kidx[3 * e + i] = a;
+            double dk = 2.0 * M_PI / (d->n[i] * d->dx);
+            k2 += (dk * a) * (dk * a);
+            if (d->dealias && 3 * abs(a) >= d->n[i]) keep = 0;
+        }
+        for (int i = d->ndim; i < 3; i++) s->kidx[3 * e + i] = 0;
+        s->k2[e] = k2;
+        s->mask[e] = (unsigned char)keep;
+        /* c(k) and the coefficients of Sec. 4 step 3 */
+        cplx c = (d->c0[0] + I * d->c0[1]) + (d->c2[0] + I * d->c2[1]) * k2 +
+                 (d->c4[0] + I * d->c4[1]) * k2 * k2;
+        cplx x = c * h, p1, p2;
+        phi12(x, &p1, &p2);
+        s->E[e] = cexp(x);
+        if (d->order == 1) { s->wa[e] = h * p1; s->wb[e] = 0; }
+        else { s->wa[e] = h * (p1 + p2); s->wb[e] = -h * p2; }
+        double Da = d->noise_D * (d->noise_kpow == 2 ? k2 : 1.0);
+        cplx q1, q2;
+        phi12(2.0 * creal(x) + 0.0 * I, &q1, &q2);
+        double var = 2.0 * Da * h * creal(q1);
+        s->G[e] = lat * sqrt(var > 0 ? var : 0.0);
+        /* model prefactors of the transformed nonlinearity (Sec. 5) */
+        switch (d->nl) {
+        case NL_PHI3: s->pref[e] = -d->nl_par[0]; break;
+        case NL_PHI3_CONS: s->pref[e] = -d->nl_par[0] * k2; break;
+        case NL_KPZ: s->pref[e] = 0.5 * d->nl_par[0]; break;
+        case NL_CGL: s->pref[e] = -(1.0 + I * d->nl_par[0]); break;
+        default: s->pref[e] = 0; break;
+        }
+    }
+
+    /* initial condition (per site, Philox tag 1), forward FFT and mask */
+    for (int rr = 0; rr < r_count; rr++) {
+        uint32_t r = (uint32_t)(r_first + rr);
+        cplx* ph = s->phi + (size_t)rr * s->nspec;
+        if (d->ic_kind == 1) {
+            if (d->complex_field) {
+                for (size_t nidx = 0; nidx < s->nreal; nidx++) {
+                    double z1, z2;
+                    orc_normal_pair(d->seed, (uint32_t)nidx, 0u, r, 1u, &z1, &z2);
+                    s->work2[nidx] = d->ic_sigma * (z1 + I * z2);
+                }
+                fftn(s->work2, d->ndim, d->n, -1);
+                for (size_t e = 0; e < s->nspec; e++) ph[e] = s->mask[e] ? s->work2[e] : 0;
+            } else {
+                for (size_t nidx = 0; nidx < s->nreal; nidx++) {
+                    double z1, z2;
+                    orc_normal_pair(d->seed, (uint32_t)nidx, 0u, r, 1u, &z1, &z2);
+                    s->rwork[nidx] = d->ic_sigma * z1;
+                }
+                rfftn(s->rwork, ph, d->ndim, d->n, s->work);
+                for (size_t e = 0; e < s->nspec; e++) if (!s->mask[e]) ph[e] = 0;
+            }
+        }
+    }
+    s->have_prev = 0;
+    s->step = 0;
+    return s;
+}
+
+orc_sim* orc_create(const orc_desc* d) { return orc_create_subset(d, 0, d ? d->realizations : 0); }
+
+void orc_destroy(orc_sim* s)
+{
+    if (!s) return;
+    free(s->phi); free(s->fprev); free(s->k2); free(s->kidx); free(s->mask);
+    free(s->E); free(s->wa); free(s->wb); free(s->G); free(s->pref);
+    free(s->work); free(s->work2); free(s->rwork); free(s->rwork2); free(s->F);
+    free(s->snap); free(s->acc);
+    free(s);
+}
+
+size_t orc_nspec(const orc_sim* s) { return s->nspec; }
+int64_t orc_step_index(const orc_sim* s) { return s->step; }
+int orc_nbins(const orc_sim* s) { return s->nbins; }
+
+/* ------------------------------------------------------------------------ */
+/* Step 1 of Sec. 4: F_a = M_a pref_a FFT[N(IFFT[phi])]                      */
+/* ------------------------------------------------------------------------ */
+static void nonlinear_term(orc_sim* s, const cplx* ph, cplx* F)
+{
+    const orc_desc* d = &s->d;
+    size_t ns = s->nspec, nr = s->nreal;
+    if (d->nl == NL_NONE) { for (size_t e = 0; e < ns; e++) F[e] = 0; return; }
+    if (d->complex_field) {
+        for (size_t e = 0; e < nr; e++) s->work2[e] = ph[e];
+        fftn(s->work2, d->ndim, d->n, +1);
+        for (size_t e = 0; e < nr; e++) {
+            cplx A = s->work2[e];
+            if (d->nl == NL_CGL) s->work2[e] = (creal(A) * creal(A) + cimag(A) * cimag(A)) * A;
+            else s->work2[e] = A * A * A;   /* phi^3 on a complex field */
+        }
+        fftn(s->work2, d->ndim, d->n, -1);
+        for (size_t e = 0; e < ns; e++) F[e] = s->mask[e] ? s->pref[e] * s->work2[e] : 0;
+        return;
+    }
+    if (d->nl == NL_KPZ) {
+        /* |grad h|^2 = sum_j (IFFT[i k_j h_a])^2, Nyquist derivative set to 0 */
+        for (size_t e = 0; e < nr; e++) s->rwork2[e] = 0;
+        for (int ax = 0; ax < d->ndim; ax++) {
+            double dk = 2.0 * M_PI / (d->n[ax] * d->dx);
+            for (size_t e = 0; e < ns; e++) {
+                int a = s->kidx[3 * e + ax];
+                int nyq = (2 * abs(a) == d->n[ax]);
+                F[e] = nyq ? 0 : (I * dk * a) * ph[e];
+            }
+            irfftn(F, s->rwork, d->ndim, d->n, s->work);
+            for (size_t e = 0; e < nr; e++) s->rwork2[e] += s->rwork[e] * s->rwork[e];
+        }
+    } else {
+        irfftn(ph, s->rwork, d->ndim, d->n, s->work);
+        for (size_t e = 0; e < nr; e++) { double p = s->rwork[e]; s->rwork2[e] = p * p * p; }
+    }
+    rfftn(s->rwork2, F, d->ndim, d->n, s->work);
+    for (size_t e = 0; e < ns; e++) F[e] = s->mask[e] ? s->pref[e] * F[e] : 0;
+}
+
+/* Step 2 of Sec. 4 with App. B: eta_a for realization r at step n */
+static cplx noise_eta(const orc_sim* s, size_t e, int64_t n, uint32_t r)
+{
+    const orc_desc* d = &s->d;
+    const double rs2 = 0.70710678118654752440;
+    double z1, z2;
+    if (!s->mask[e]) return 0;
+    if (d->complex_field) {
+        orc_normal_pair(d->seed, (uint32_t)e, (uint32_t)n, r, 0u, &z1, &z2);
+        return (z1 + I * z2) * rs2;
+    }
+    int j[3] = { 0, 0, 0 };
+    unlin(s, e, j);
+    int last = d->ndim - 1;
+    int ad = j[last];
+    if (ad > 0 && 2 * ad < d->n[last]) {
+        orc_normal_pair(d->seed, (uint32_t)e, (uint32_t)n, r, 0u, &z1, &z2);
+        return (z1 + I * z2) * rs2;
+    }
+    /* a_d in {0, N_d/2}: the conjugate partner -a on this plane */
+    int jp[3] = { 0, 0, 0 };
+    for (int i = 0; i < last; i++) jp[i] = (j[i] == 0) ? 0 : d->n[i] - j[i];
+    jp[last] = ad;
+    size_t ep = lin_index(s, jp);
+    if (ep == e) {
+        orc_normal_pair(d->seed, (uint32_t)e, (uint32_t)n, r, 0u, &z1, &z2);
+        return z1;
+    }
+    if (e < ep) {
+        orc_normal_pair(d->seed, (uint32_t)e, (uint32_t)n, r, 0u, &z1, &z2);
+        return (z1 + I * z2) * rs2;
+    }
+    orc_normal_pair(d->seed, (uint32_t)ep, (uint32_t)n, r, 0u, &z1, &z2);
+    return conj((z1 + I * z2) * rs2);
+}
+
+/* the additive noise term G_a eta_a of step n for all realizations */
+int orc_noise_xi(orc_sim* s, int64_t n, double* xi_out)
+{
+    cplx* xi = (cplx*)xi_out;
+    for (int rr = 0; rr < s->R; rr++)
+        for (size_t e = 0; e < s->nspec; e++)
+            xi[(size_t)rr * s->nspec + e] = s->G[e] * noise_eta(s, e, n, (uint32_t)(s->r_first + rr));
+    return 0;
+}
+
+/* Steps 3-4 of Sec. 4 (Eq. SETD1 / SETD2) with a given noise term */
+static void update(orc_sim* s, int rr, const cplx* xi)
+{
+    cplx* ph = s->phi + (size_t)rr * s->nspec;
+    cplx* fp = s->fprev + (size_t)rr * s->nspec;
+    const cplx* F = s->F;
+    int first = !s->have_prev;
+    for (size_t e = 0; e < s->nspec; e++) {
+        if (!s->mask[e]) { ph[e] = 0; fp[e] = 0; continue; }
+        cplx Fp = (s->d.order == 2 && !first) ? fp[e] : F[e];
+        cplx v = s->E[e] * ph[e] + s->wa[e] * F[e] + xi[e];
+        if (s->d.order == 2) v += s->wb[e] * Fp;
+        ph[e] = v;
+        fp[e] = F[e];
+    }
+}
+
+static int step_once(orc_sim* s, const cplx* xi_all)
+{
+    cplx* xi = (cplx*)malloc(sizeof(cplx) * s->nspec);
+    for (int rr = 0; rr < s->R; rr++) {
+        cplx* ph = s->phi + (size_t)rr * s->nspec;
+        nonlinear_term(s, ph, s->F);
+        if (xi_all) memcpy(xi, xi_all + (size_t)rr * s->nspec, sizeof(cplx) * s->nspec);
+        else
+            for (size_t e = 0; e < s->nspec; e++)
+                xi[e] = s->G[e] * noise_eta(s, e, s->step, (uint32_t)(s->r_first + rr));
+        update(s, rr, xi);
+    }
+    free(xi);
+    s->have_prev = 1;
+    s->step += 1;
+    return 0;
+}
+
+int orc_step(orc_sim* s, int64_t nsteps)
+{
+    for (int64_t i = 0; i < nsteps; i++) step_once(s, NULL);
+    return 0;
+}
+
+int orc_step_xi(orc_sim* s, const double* xi)
+{
+    return step_once(s, (const cplx*)xi);
+}
+
+/* which: 0 state phi_a, 1 previous nonlinear term F_{n-1} */
+int orc_get(const orc_sim* s, int which, int rr, double* out)
+{
+    if (rr < 0 || rr >= s->R) return -1;
+    const cplx* src = (which == 0 ? s->phi : s->fprev) + (size_t)rr * s->nspec;
+    memcpy(out, src, sizeof(cplx) * s->nspec);
+    return 0;
+}
+
+/* setting the state restarts the SETD2 history (F_{-1} = F_0 again) */
+int orc_set(orc_sim* s, int rr, const double* in)
+{
+    if (rr < 0 || rr >= s->R) return -1;
+    cplx* dst = s->phi + (size_t)rr * s->nspec;
+    const cplx* src = (const cplx*)in;
+    for (size_t e = 0; e < s->nspec; e++) dst[e] = s->mask[e] ? src[e] : 0;
+    s->have_prev = 0;
+    return 0;
+}
+
+int orc_set_step(orc_sim* s, int64_t n) { s->step = n; return 0; }
+
+/* per-mode coefficient arrays (interleaved complex unless noted)
+   which: 0 E, 1 wa, 2 wb, 3 G (real), 4 k^2 (real), 5 mask (real 0/1), 6 pref */
+int orc_coef(const orc_sim* s, int which, double* out)
+{
+    for (size_t e = 0; e < s->nspec; e++) {
+        switch (which) {
+        case 0: out[2 * e] = creal(s->E[e]); out[2 * e + 1] = cimag(s->E[e]); break;
+        case 1: out[2 * e] = creal(s->wa[e]); out[2 * e + 1] = cimag(s->wa[e]); break;
+        case 2: out[2 * e] = creal(s->wb[e]); out[2 * e + 1] = cimag(s->wb[e]); break;
+        case 3: out[e] = s->G[e]; break;
+        case 4: out[e] = s->k2[e]; break;
+        case 5: out[e] = s->mask[e]; break;
+        case 6: out[2 * e] = creal(s->pref[e]); out[2 * e + 1] = cimag(s->pref[e]); break;
+        default: return -1;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Observables (Sec. 5, App. C)                                             */
+/* ------------------------------------------------------------------------ */
+/* weight of a stored mode in sums over the full spectrum */
+static double mode_weight(const orc_sim* s, size_t e)
+{
+    if (s->d.complex_field) return 1.0;
+    int j[3] = { 0, 0, 0 };
+    unlin(s, e, j);
+    int last = s->d.ndim - 1;
+    int ad = j[last];
+    return (ad > 0 && 2 * ad < s->d.n[last]) ? 2.0 : 1.0;
+}
+
+static int shell_of(const orc_sim* s, size_t e)
+{
+    long m = 0;
+    for (int i = 0; i < s->d.ndim; i++) { long a = s->kidx[3 * e + i]; m += a * a; }
+    return isqrt_ceil(m);
+}
+
+/* kinds: 0 S(k) by shell, 1 width, 2 snapshot, 3 two-time C(k,n,n_w),
+   4 step index, 5 accumulate S(k), 6 mean of accumulated S(k) */
+int orc_observe(orc_sim* s, int kind, double* out, size_t cap, size_t* len)
+{
+    const orc_desc* d = &s->d;
+    int nb = s->nbins;
+    double vol = 1.0;   /* prod L_i / N_i^2 */
+    for (int i = 0; i < d->ndim; i++) vol *= (d->n[i] * d->dx) / ((double)d->n[i] * (double)d->n[i]);
+    if (kind == 0 || kind == 5) {
+        if (kind == 0 && cap < (size_t)2 * nb) return -1;
+        double* sum = (double*)calloc((size_t)nb, sizeof(double));
+        double* cnt = (double*)calloc((size_t)nb, sizeof(double));
+        for (size_t e = 0; e < s->nspec; e++) {
+            if (!s->mask[e]) continue;
+            double w = mode_weight(s, e);
+            int b = shell_of(s, e);
+            double acc = 0;
+            for (int rr = 0; rr < s->R; rr++) {
+                cplx v = s->phi[(size_t)rr * s->nspec + e];
+                acc += creal(v) * creal(v) + cimag(v) * cimag(v);
+            }
+            sum[b] += w * vol * acc / s->R;
+            cnt[b] += w;
+        }
+        if (kind == 0) {
+            for (int b = 0; b < nb; b++) { out[b] = cnt[b] > 0 ? sum[b] / cnt[b] : 0; out[nb + b] = cnt[b]; }
+            *len = (size_t)2 * nb;
+        } else {
+            for (int b = 0; b < nb; b++) { s->acc[b] += cnt[b] > 0 ? sum[b] / cnt[b] : 0; s->acc[nb + b] = cnt[b]; }
+            s->acc_count += 1;
+            if (cap >= 1) { out[0] = s->acc_count; *len = 1; } else *len = 0;
+        }
+        free(sum); free(cnt);
+        return 0;
+    }
+    if (kind == 6) {
+        if (cap < (size_t)2 * nb) return -1;
+        for (int b = 0; b < nb; b++) {
+            out[b] = s->acc_count > 0 ? s->acc[b] / s->acc_count : 0;
+            out[nb + b] = s->acc[nb + b];
+        }
+        *len = (size_t)2 * nb;
+        return 0;
+    }
+    if (kind == 1) {
+        /* width with l = L via Parseval: var = N^{-2d} sum_{a != 0} |h_a|^2 */
+        if (cap < 1) return -1;
+        double tot = 0, nn = (double)s->nreal;
+        for (int rr = 0; rr < s->R; rr++)
+            for (size_t e = 1; e < s->nspec; e++) {
+                cplx v = s->phi[(size_t)rr * s->nspec + e];
+                tot += mode_weight(s, e) * (creal(v) * creal(v) + cimag(v) * cimag(v));
+            }
+        out[0] = sqrt(tot / (nn * nn) / s->R);
+        *len = 1;
+        return 0;
+    }
+    if (kind == 2) {
+        if (!s->snap) s->snap = (cplx*)malloc(sizeof(cplx) * (size_t)s->R * s->nspec);
+        memcpy(s->snap, s->phi, sizeof(cplx) * (size_t)s->R * s->nspec);
+        s->snap_step = s->step; s->have_snap = 1;
+        if (cap >= 1) { out[0] = (double)s->step; *len = 1; } else *len = 0;
+        return 0;
+    }
+    if (kind == 3) {
+        if (!s->have_snap || cap < (size_t)3 * nb) return -1;
+        double* re = (double*)calloc((size_t)nb, sizeof(double));
+        double* im = (double*)calloc((size_t)nb, sizeof(double));
+        double* cnt = (double*)calloc((size_t)nb, sizeof(double));
+        for (size_t e = 0; e < s->nspec; e++) {
+            if (!s->mask[e]) continue;
+            double w = mode_weight(s, e);
+            int b = shell_of(s, e);
+            cplx acc = 0;
+            for (int rr = 0; rr < s->R; rr++)
+                acc += s->phi[(size_t)rr * s->nspec + e] * conj(s->snap[(size_t)rr * s->nspec + e]);
+            acc *= vol / s->R;
+            if (w == 2.0) { re[b] += 2.0 * creal(acc); }      /* a and -a: 2 Re */
+            else { re[b] += creal(acc); im[b] += cimag(acc); }
+            cnt[b] += w;
+        }
+        for (int b = 0; b < nb; b++) {
+            out[b] = cnt[b] > 0 ? re[b] / cnt[b] : 0;
+            out[nb + b] = cnt[b] > 0 ? im[b] / cnt[b] : 0;
+            out[2 * nb + b] = cnt[b];
+        }
+        *len = (size_t)3 * nb;
+        free(re); free(im); free(cnt);
+        return 0;
+    }
+    if (kind == 4) {
+        if (cap < 1) return -1;
+        out[0] = (double)s->step;
+        *len = 1;
+        return 0;
+    }
+    return -1;
+}

@@ -1,0 +1,246 @@
+"""Pins of the oracle's time stepping against closed forms of the paper:
+noise-free decay and the exact Ornstein-Uhlenbeck variance of the linear theory
+(Sec. 5 Model A/B linear theory; I1 of Sec. 2), conservation in Model B, the
+CGL travelling wave (Sec. 5 CGL) and the homogeneous Model A ODE at the
+schemes' orders (Eq. SETD1/SETD2), the transformed nonlinearities (Sec. 5),
+and the strong order on one Brownian path (Sec. 3)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2511_22510_amd import workloads as W
+
+
+def test_noise_free_decay_is_exact():
+    p = W.model_a([16, 16], r=0.5, u=0.0, T=0.0, nl="none", h=0.05, order=1, ic_kind=1, ic_sigma=1.0)
+    s = O.Sim(p)
+    phi0 = s.get(0)
+    E = s.coef(0)
+    s.step(40)
+    expect = phi0 * E**40
+    assert np.max(np.abs(s.get(0) - expect)) <= 40 * 4e-16 * np.max(np.abs(phi0))
+    # SETD2 with F = 0 is the same map
+    p2 = dict(p, order=2)
+    s2 = O.Sim(p2)
+    s2.step(40)
+    assert np.max(np.abs(s2.get(0) - expect)) <= 40 * 4e-16 * np.max(np.abs(phi0))
+
+
+@pytest.mark.parametrize("model", ["A", "B"])
+def test_linear_theory_variance_is_exact_for_any_h(model):
+    """For u = 0 SETD1 samples the OU transition exactly, so from phi = 0 the
+    mode variance after t = n h is (N^2/L)^d D_a (e^{2 c t} - 1)/c for every h;
+    at large t this is the steady state D/(r + k^2) times (N^2/L)^d."""
+    r, T, h = 0.7, 0.3, 0.25
+    n = [16, 16]
+    mk = W.model_a if model == "A" else W.model_b
+    p = mk(n, r=r, u=0.0, T=T, nl="none", h=h, order=1, ic_kind=0, realizations=200,
+           dealias=0, seed=11, dx=1.3)
+    s = O.Sim(p)
+    nsteps = 6
+    s.step(nsteps)
+    phi = s.get_all()
+    k2 = s.coef(4)
+    c = -(r + k2) if model == "A" else -k2 * (r + k2)
+    D = T if model == "A" else T * k2
+    L = 16 * 1.3
+    lat = (16**2 / L) ** 2
+    t = nsteps * h
+    with np.errstate(divide="ignore", invalid="ignore"):
+        var = lat * np.where(c != 0, D * np.expm1(2 * c * t) / c, 2 * D * t)
+    emp = np.mean(np.abs(phi) ** 2, axis=0)
+    # mean |phi_a|^2 over 200 realizations; chi^2-like relative error ~ 1/sqrt(200)
+    # (complex modes) or sqrt(2/200) (real modes): pool modes of equal k^2.
+    keys = np.round(k2, 10)
+    zs = []
+    for kk in np.unique(keys):
+        sel = (keys == kk) & (var > 0)
+        if not np.any(sel):
+            continue
+        ratio = emp[sel] / var[sel]
+        m = ratio.size * 200
+        zs.append((ratio.mean() - 1) / np.sqrt(2.0 / m))
+    zs = np.array(zs)
+    # Bonferroni over shells at family-wise alpha ~ 1e-3
+    assert np.max(np.abs(zs)) < 4.5, zs
+
+
+def test_model_b_conserves_the_zero_mode():
+    p = W.model_b([32, 32], u=1.0, T=0.05, h=0.01, order=2, ic_kind=1, ic_sigma=0.3, dealias=1)
+    s = O.Sim(p)
+    a0 = s.get(0)[0, 0]
+    s.step(30)
+    assert abs(s.get(0)[0, 0] - a0) <= 1e-13 * max(1.0, abs(a0))
+
+
+def _cgl_plane_wave_error(h, order, T=1.0, q_index=2, N=32, dx=0.5, alpha=0.5, beta=-1.2):
+    L = N * dx
+    q = 2 * np.pi * q_index / L
+    R = np.sqrt(1 - q**2)
+    Omega = alpha * q**2 + beta * (1 - q**2)
+    p = W.cgl([N], alpha=alpha, beta=beta, T=0.0, h=h, order=order, ic_kind=0, dealias=1, dx=dx)
+    s = O.Sim(p)
+    x = np.arange(N) * dx
+    A0 = R * np.exp(1j * q * x)
+    s.set(0, O.fftn(A0))
+    nsteps = int(round(T / h))
+    s.step(nsteps)
+    A = O.fftn(s.get(0), inverse=True)
+    exact = R * np.exp(1j * (q * x - Omega * nsteps * h))
+    return np.max(np.abs(A - exact))
+
+
+@pytest.mark.parametrize("order,expect", [(1, 2.0), (2, 4.0)])
+def test_cgl_travelling_wave_converges_at_scheme_order(order, expect):
+    errs = [_cgl_plane_wave_error(h, order) for h in (0.1, 0.05, 0.025)]
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(abs(r_ - expect) < 0.25 * expect for r_ in ratios), (errs, ratios)
+
+
+@pytest.mark.parametrize("order,expect", [(1, 2.0), (2, 4.0)])
+def test_homogeneous_model_a_logistic_ode(order, expect):
+    """A uniform field obeys d phi/dt = -r phi - u phi^3; with r = -1, u = 1:
+    phi(t)^2 = 1 / (1 + (1/phi0^2 - 1) e^{-2t})."""
+    N, phi0, T = 8, 0.2, 1.0
+    errs = []
+    for h in (0.1, 0.05, 0.025):
+        p = W.model_a([N, N], r=-1.0, u=1.0, T=0.0, h=h, order=order, ic_kind=0, dealias=1)
+        s = O.Sim(p)
+        st = np.zeros(W.spectral_shape(p), dtype=complex)
+        st[0, 0] = phi0 * N * N
+        s.set(0, st)
+        nsteps = int(round(T / h))
+        s.step(nsteps)
+        got = s.get(0)[0, 0].real / (N * N)
+        exact = 1.0 / np.sqrt(1 + (1 / phi0**2 - 1) * np.exp(-2 * nsteps * h))
+        errs.append(abs(got - exact))
+        # nothing leaks out of the k = 0 mode
+        rest = s.get(0).copy()
+        rest[0, 0] = 0
+        assert np.max(np.abs(rest)) < 1e-12
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(abs(r_ - expect) < 0.25 * expect for r_ in ratios), (errs, ratios)
+
+
+def _first_F(p, state):
+    """F_0 of the first SETD2 step: the stored previous nonlinear term."""
+    s = O.Sim(dict(p, order=2, T=0.0, noise_D=0.0, ic_kind=0))
+    s.set(0, state)
+    s.step(1)
+    return s.get(0, which=1)
+
+
+def test_phi_cubed_spectrum():
+    """cos^3 = (3 cos + cos 3)/4  ->  F = -u FFT[phi^3] on modes m and 3m."""
+    N, m, A, u = 32, 3, 0.7, 1.3
+    p = W.model_a([N, N], u=u, dealias=1)
+    x = np.arange(N)
+    phi = A * np.cos(2 * np.pi * m * x / N)[None, :] * np.ones((N, 1))
+    F = _first_F(p, O.rfftn(phi))
+    expect = np.zeros_like(F)
+    expect[0, m] = -u * 3 * A**3 / 4 * N * N / 2
+    expect[0, 3 * m] = -u * A**3 / 4 * N * N / 2
+    assert np.max(np.abs(F - expect)) < 1e-11 * N * N
+
+
+def test_model_b_spectrum_carries_k_squared():
+    N, m, A, u, dx = 32, 2, 0.5, 1.0, 0.8
+    p = W.model_b([N, N], u=u, dealias=1, dx=dx)
+    x = np.arange(N)
+    phi = A * np.cos(2 * np.pi * m * x / N)[:, None] * np.ones((1, N))
+    F = _first_F(p, O.rfftn(phi))
+    dk = 2 * np.pi / (N * dx)
+    expect = np.zeros_like(F)
+    for mm, amp in [(m, 3 * A**3 / 4), (3 * m, A**3 / 4)]:
+        k2 = (dk * mm) ** 2
+        expect[mm, 0] += -u * k2 * amp * N * N / 2
+        expect[N - mm, 0] += -u * k2 * amp * N * N / 2
+    assert np.max(np.abs(F - expect)) < 1e-11 * N * N
+
+
+def test_kpz_gradient_squared_spectrum():
+    """|grad(A cos k.x)|^2 = A^2 k^2 (1 - cos 2k.x)/2, times lambda/2."""
+    N, m1, m2, A, lam, dx = 32, 1, 2, 0.9, 3.0, 1.0
+    p = W.kpz([N, N], lam=lam, dealias=1, dx=dx)
+    x0, x1 = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    h = A * np.cos(2 * np.pi * (m1 * x0 + m2 * x1) / N)
+    F = _first_F(p, O.rfftn(h))
+    dk = 2 * np.pi / (N * dx)
+    k2 = dk**2 * (m1**2 + m2**2)
+    expect = np.zeros_like(F)
+    expect[0, 0] = lam / 2 * A**2 * k2 / 2 * N * N
+    expect[2 * m1, 2 * m2] = -lam / 2 * A**2 * k2 / 4 * N * N
+    assert np.max(np.abs(F - expect)) < 1e-11 * N * N
+
+
+def test_cgl_two_mode_cubic_spectrum():
+    """|A|^2 A for A = a e^{ik1x} + b e^{ik2x} lands on k1, k2, 2k1-k2, 2k2-k1."""
+    N, beta = 32, -1.2
+    a, b = 0.3 + 0.2j, -0.1 + 0.4j
+    k1, k2 = 2, 5
+    p = W.cgl([N], beta=beta, dealias=0)
+    x = np.arange(N)
+    A = a * np.exp(2j * np.pi * k1 * x / N) + b * np.exp(2j * np.pi * k2 * x / N)
+    F = _first_F(p, O.fftn(A))
+    pre = -(1 + 1j * beta) * N
+    expect = np.zeros(N, dtype=complex)
+    expect[k1] += pre * (abs(a) ** 2 + 2 * abs(b) ** 2) * a
+    expect[k2] += pre * (2 * abs(a) ** 2 + abs(b) ** 2) * b
+    expect[(2 * k1 - k2) % N] += pre * a * a * np.conj(b)
+    expect[(2 * k2 - k1) % N] += pre * b * b * np.conj(a)
+    assert np.max(np.abs(F - expect)) < 1e-12 * N
+
+
+def _aggregate(E_f, xis, m):
+    """Exact coarse noise of m fine steps on one Brownian path (I1 is additive):
+    xi_c = sum_j E_f^{m-1-j} xi_f(j)."""
+    out = np.zeros_like(xis[0])
+    for j in range(m):
+        out = out + E_f ** (m - 1 - j) * xis[j]
+    return out
+
+
+def _run_on_path(p, h_fine, m, n_coarse, fine_noise, E_f):
+    s = O.Sim(dict(p, h=h_fine * m))
+    for c in range(n_coarse):
+        s.step_xi(_aggregate(E_f, fine_noise[c * m:(c + 1) * m], m))
+    return s.get_all()
+
+
+def test_linear_coarse_equals_fine_on_one_brownian_path():
+    """u = 0: the SETD1 map is the exact OU flow, so a coarse run fed the
+    aggregated fine noise reproduces the fine run to rounding."""
+    p = W.model_a([16, 16], r=0.5, u=0.0, T=0.2, nl="none", order=1, ic_kind=1, ic_sigma=0.5,
+                  realizations=2, seed=21)
+    hf, m, nc = 0.01, 8, 5
+    fine = O.Sim(dict(p, h=hf))
+    E_f = fine.coef(0)
+    noise = [fine.noise_xi(j) for j in range(m * nc)]
+    for j in range(m * nc):
+        fine.step_xi(noise[j])
+    coarse = _run_on_path(p, hf, m, nc, noise, E_f)
+    ref = fine.get_all()
+    assert np.max(np.abs(coarse - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_strong_order_one_with_additive_noise(order):
+    """Sec. 3: with additive noise SETD1/SETD2 converge strongly at order 1.
+    Reference: the finest step on the same Brownian path."""
+    p = W.model_a([8, 8], r=1.0, u=1.0, T=0.5, order=order, ic_kind=1, ic_sigma=0.5,
+                  realizations=16, seed=5, dealias=1)
+    h_ref, T = 0.5 / 64, 2.0
+    nf = int(round(T / h_ref))
+    fine = O.Sim(dict(p, h=h_ref))
+    E_f = fine.coef(0)
+    noise = [fine.noise_xi(j) for j in range(nf)]
+    for j in range(nf):
+        fine.step_xi(noise[j])
+    ref = fine.get_all()
+    errs = []
+    for m in (32, 16, 8):
+        got = _run_on_path(p, h_ref, m, nf // m, noise, E_f)
+        errs.append(np.mean(np.sqrt(np.sum(np.abs(got - ref) ** 2, axis=(1, 2)))))
+    hs = np.array([32, 16, 8]) * h_ref
+    slope = np.polyfit(np.log(hs), np.log(errs), 1)[0]
+    assert 0.75 < slope < 1.35 if order == 1 else slope > 0.75, (errs, slope)

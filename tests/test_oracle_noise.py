@@ -1,0 +1,105 @@
+"""Pins of the oracle's Fourier-space noise (Sec. 4 step 2, App. A, App. B) and
+of its initial condition."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2511_22510_amd import workloads as W
+
+
+def _eta(p, n=0):
+    s = O.Sim(p)
+    G = s.coef(3)
+    xi = s.noise_xi(n)[0]
+    eta = np.where(G > 0, xi / np.where(G > 0, G, 1), 0)
+    return s, eta, G
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (16, 8), (8, 4, 8)])
+def test_hermitian_structure_and_count(shape):
+    """App. B: interior modes complex, the a_d in {0, N/2} planes conjugate-paired,
+    self-conjugate points real; the number of real deviates equals prod N_i."""
+    p = W.model_a(list(shape), dealias=0, ic_kind=0, T=1.0, r=1.0)
+    s, eta, G = _eta(p, n=3)
+    n = shape
+    nd = len(shape)
+    draws = 0
+    for idx in np.ndindex(eta.shape):
+        ad = idx[-1]
+        if 0 < ad < n[-1] // 2:
+            draws += 2
+            continue
+        partner = tuple((-idx[i]) % n[i] for i in range(nd - 1)) + (ad,)
+        if partner == idx:
+            assert eta[idx].imag == 0.0
+            draws += 1
+        else:
+            assert eta[partner] == np.conj(eta[idx])
+            draws += 1  # one real deviate per stored member of a pair
+    assert draws == int(np.prod(shape))
+
+
+def test_noise_is_real_white_noise_in_real_space():
+    """App. A sanity check: a unit-variance Hermitian eta_a is, after the inverse
+    transform, real noise with per-site variance N^-d."""
+    shape = (32, 32)
+    p = W.model_a(list(shape), dealias=0, ic_kind=0, T=1.0, r=1.0)
+    s = O.Sim(p)
+    G = s.coef(3)
+    vals = []
+    for n in range(40):
+        eta = s.noise_xi(n)[0] / G
+        x = O.irfftn(eta, shape)
+        vals.append(x.reshape(-1))
+    v = np.concatenate(vals) * np.sqrt(np.prod(shape))
+    assert abs(v.mean()) < 5 / np.sqrt(v.size)
+    assert abs(v.var() - 1.0) < 5 * np.sqrt(2.0 / v.size)
+
+
+def test_complex_noise_moments():
+    """Eq. random-number: eta = A + iB with A, B ~ N(0, 1/2)."""
+    p = W.cgl([32, 32], dealias=0, ic_kind=0, T=1.0)
+    s = O.Sim(p)
+    G = s.coef(3)
+    eta = np.concatenate([(s.noise_xi(n)[0] / G).reshape(-1) for n in range(8)])
+    m = eta.size
+    assert abs(np.mean(eta.real**2) - 0.5) < 5 * np.sqrt(0.5 / m)
+    assert abs(np.mean(eta.imag**2) - 0.5) < 5 * np.sqrt(0.5 / m)
+    assert abs(np.mean(eta.real * eta.imag)) < 5 * np.sqrt(0.25 / m)
+    assert abs(np.mean(eta**2)) < 5 * np.sqrt(1.0 / m)   # <eta eta> = 0
+
+
+def test_masked_modes_draw_nothing():
+    p = W.model_a([32, 32], dealias=1, ic_kind=0, T=1.0, r=1.0)
+    s, eta, G = _eta(p)
+    mask = s.coef(5)
+    assert np.all(eta[mask == 0] == 0)
+    K = (32 - 1) // 3
+    assert int(mask.sum()) == (2 * K + 1) * (K + 1)
+
+
+def test_kept_mode_counts():
+    for n, expect in [(512, 58311), (1024, 233586)]:
+        K = (n - 1) // 3
+        p = W.model_b([n, n], ic_kind=0)
+        s = O.Sim(p)
+        assert int(s.coef(5).sum()) == expect == (2 * K + 1) * (K + 1)
+    p = W.cgl([32, 32, 32], ic_kind=0)
+    K = 31 // 3
+    assert int(O.Sim(p).coef(5).sum()) == (2 * K + 1) ** 3
+
+
+def test_initial_condition_is_per_site_philox():
+    """phi_n = sigma z1(ctr = (site, 0, r, 1)), then forward FFT (no mask here)."""
+    p = W.model_a([16, 8], dealias=0, ic_kind=1, ic_sigma=0.1, seed=5, realizations=3)
+    s = O.Sim(p)
+    for r in range(3):
+        x = O.irfftn(s.get(r), (16, 8)).reshape(-1)
+        for site in [0, 1, 37, 127]:
+            z1, _ = O.normal_pair(5, site, 0, r, 1)
+            assert x[site] == pytest.approx(0.1 * z1, abs=1e-15)
+    pc = W.cgl([8, 8], dealias=0, ic_kind=1, ic_sigma=0.01, seed=9)
+    sc = O.Sim(pc)
+    A = O.fftn(sc.get(0), inverse=True).reshape(-1)
+    z1, z2 = O.normal_pair(9, 13, 0, 0, 1)
+    assert A[13] == pytest.approx(0.01 * complex(z1, z2), abs=1e-16)
