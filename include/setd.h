@@ -1,0 +1,241 @@
+/*
+ * setd.h -- C ABI of the MI355X (gfx950) SETD pseudo-spectral integrator.
+ *
+ * The library advances stochastic field theories written in Fourier space as
+ *     d phi_a/dt = c(k_a) phi_a + F_a[phi] + sqrt(2 D(k_a)) eta_a(t)
+ * (Johnsrud & Rana, arXiv 2511.22510, Sec. 4 Eq. general_fourier) with the
+ * stochastic exponential-time-differencing schemes SETD1 (Sec. 2 Eq. SETD1) and
+ * SETD2 (Sec. 2 Eq. SETD2), evaluating F_a pseudo-spectrally (Sec. 4, the
+ * algorithm box), drawing the noise directly in Fourier space (App. B) with the
+ * lattice normalisation of App. A, and dealiasing by the 2/3 truncation rule.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns a setd_status.  No call aborts; setd_last_error()
+ *    gives a text for the last failing call of the calling thread.
+ *  - Device memory and HIP streams belong to the caller.  The library only
+ *    borrows the workspace and stream handed to setd_plan_bind /
+ *    setd_server_create and never frees them.
+ *  - Fields cross the boundary as host arrays of interleaved (re, im) doubles
+ *    in FFT order: a real field as its real-to-complex half spectrum
+ *    n[0] x .. x (n[d-1]/2 + 1), a complex field as the full n[0] x .. x n[d-1]
+ *    spectrum.  Modes removed by dealiasing are zero on output and ignored on
+ *    input.
+ *  - DFT convention: forward X_a = sum_n x_n e^{-2 pi i a.n/N} (unscaled),
+ *    inverse x_n = N^-d sum_a X_a e^{+2 pi i a.n/N}.
+ *  - Work is queued on the bound stream; setd_step returns before the GPU has
+ *    finished.  setd_observe, setd_get_field and setd_set_field synchronise
+ *    the stream.
+ */
+#ifndef SETD_H
+#define SETD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SETD_OK = 0,
+    SETD_E_INVAL = -1,        /* bad argument or descriptor                      */
+    SETD_E_NOMEM = -2,        /* workspace / arena too small                     */
+    SETD_E_DEVICE = -3,       /* a HIP call failed                               */
+    SETD_E_NONFINITE = -4,    /* a realization produced NaN/Inf (Sec. 2 warns of
+                                 blow-up of explicit schemes); data still returned */
+    SETD_E_BUSY = -5,         /* job not finished yet                            */
+    SETD_E_UNSUPPORTED = -6,  /* valid physics this build does not run           */
+    SETD_E_STATE = -7         /* call out of order (e.g. step before bind)       */
+} setd_status;
+
+/* Nonlinear term F_a (Sec. 5).  The prefactor acts in Fourier space. */
+typedef enum {
+    SETD_NL_PHI3 = 0,         /* Model A, Eq. modelA:   F = -u FFT[phi^3]             */
+    SETD_NL_PHI3_CONS = 1,    /* Model B, Eq. modelB:   F = -u k^2 FFT[phi^3]         */
+    SETD_NL_KPZ = 2,          /* KPZ, Eq. kpz_fourier:  F = lambda/2 FFT[|grad h|^2],
+                                 gradient taken spectrally (2D real fields only)     */
+    SETD_NL_CGL = 3,          /* CGL, Eq. cgle:         F = -(1 + i beta) FFT[|A|^2 A] */
+    SETD_NL_NONE = 4          /* linear theory, F = 0                                */
+} setd_nonlin;
+
+/* Observables (Sec. 5 and App. C), accumulated in FP64 on the device. */
+typedef enum {
+    SETD_OBS_SK = 0,          /* equal-time S(k, t) = (L/N^2)^d <|phi_a|^2> over
+                                 realizations, averaged over shells ceil|a| = j
+                                 (App. C shells k - dk < |q| <= k; needs equal
+                                 n[i]).  out: [mean_j (nbins), count_j (nbins)]     */
+    SETD_OBS_WIDTH = 1,       /* interface width w(t) with l = L (Sec. 5 KPZ),
+                                 sqrt of the ensemble mean real-space variance.
+                                 out: [w]                                           */
+    SETD_OBS_SNAPSHOT = 2,    /* store the current state as the reference time t'
+                                 of the two-time correlation.  out: [step]          */
+    SETD_OBS_TWOTIME = 3,     /* C(k, t, t') = (L/N^2)^d <phi_a(t) conj phi_a(t')>,
+                                 shell averaged.  out: [Re (nbins), Im (nbins),
+                                 count (nbins)]                                     */
+    SETD_OBS_STEP = 4,        /* out: [step index n, non-finite flag]               */
+    SETD_OBS_SK_ACCUM = 5,    /* add the current shell S(k) to a running FP64 sum.
+                                 out: [number of samples accumulated]               */
+    SETD_OBS_SK_MEAN = 6      /* time mean of the accumulated S(k).
+                                 out: [mean_j (nbins), count_j (nbins)]             */
+} setd_obs_kind;
+
+/*
+ * Problem statement (Sec. 4 Eq. general_fourier; lattice of App. A):
+ *   lattice n[0..ndim) points, spacing dx, L_i = n[i] dx, k_i = 2 pi a_i / L_i;
+ *   c(k) = c0 + c2 k^2 + c4 k^4 (complex, {re, im}); D(k) = noise_D k^noise_kpow.
+ * Model A: c0 = -r, c2 = -1, kpow 0, nl PHI3, nl_par[0] = u.
+ * Model B: c2 = -r, c4 = -1, kpow 2, nl PHI3_CONS, nl_par[0] = u.
+ * KPZ:     c2 = -nu, kpow 0, nl KPZ, nl_par[0] = lambda.
+ * CGL:     c0 = 1, c2 = -(1 + i alpha), complex_field 1, nl CGL, nl_par[0] = beta.
+ */
+typedef struct {
+    int ndim;                 /* 2 or 3                                            */
+    int n[3];                 /* points per axis, powers of two in [8, 1024]       */
+    double dx;                /* lattice spacing (> 0)                             */
+    int complex_field;        /* 0: real order parameter (R2C); 1: complex (C2C)   */
+    double c0[2], c2[2], c4[2];
+    int nl;                   /* setd_nonlin                                       */
+    double nl_par[2];         /* u | lambda | beta                                 */
+    double noise_D;           /* >= 0                                              */
+    int noise_kpow;           /* 0 or 2                                            */
+    double h;                 /* time step (> 0)                                   */
+    int order;                /* 1 = SETD1, 2 = SETD2                              */
+    int precision;            /* 32: complex64 state and transforms, coefficients
+                                 evaluated in FP64 and rounded; 64: complex128     */
+    int realizations;         /* independent noise realizations in one plan (>= 1) */
+    uint64_t seed;            /* Philox4x32-10 key                                 */
+    int dealias;              /* 0: none; 1: 2/3 rule, keep 3|a_i| < n[i]          */
+    int ic_kind;              /* 0: phi = 0; 1: i.i.d. N(0, ic_sigma^2) per site
+                                 (complex fields: ic_sigma (z1 + i z2))             */
+    double ic_sigma;
+} setd_desc;
+
+/* Derived sizes of a plan (filled by setd_plan_info). */
+typedef struct {
+    size_t workspace_bytes;   /* device bytes setd_plan_bind needs                 */
+    size_t spectral_len;      /* complex values per realization crossing the ABI   */
+    size_t kept_modes;        /* stored (non-dealiased) modes per realization      */
+    int nbins;                /* shell bins of the S(k) and two-time observables   */
+    int passes_per_step;      /* kernel launches per time step                     */
+    double alg_bytes_per_step;/* HBM bytes one step must move (all realizations)   */
+    double site_updates_per_step; /* prod n[i] * realizations                      */
+} setd_plan_info_t;
+
+typedef struct setd_plan setd_plan;
+typedef struct setd_server setd_server;
+typedef int64_t setd_job;
+
+/*
+ * Validate *desc and prepare a plan (host work only, no device memory).
+ * Errors: SETD_E_INVAL for ndim not in {2,3}, n[i] not a power of two in
+ * [8, 1024], order not in {1,2}, h <= 0, dx <= 0, noise_D < 0, noise_kpow not
+ * in {0,2}, precision not in {32,64}, realizations < 1, a complex c(k) on a
+ * real field, ic_kind not in {0,1}; SETD_E_UNSUPPORTED for KPZ outside 2D real
+ * fields, PHI3/PHI3_CONS on complex fields or CGL on real fields.
+ * *out is owned by the caller and released with setd_plan_destroy.
+ */
+setd_status setd_plan_create(const setd_desc* desc, setd_plan** out);
+
+/* Device bytes the plan needs (state, SETD2 history, transform intermediates,
+   coefficient and twiddle tables, FP64 observable accumulators). */
+setd_status setd_plan_workspace(const setd_plan* plan, size_t* bytes);
+
+setd_status setd_plan_info(const setd_plan* plan, setd_plan_info_t* info);
+
+/*
+ * Bind caller-owned device memory dev_ws[0, bytes) (bytes >= the workspace
+ * size, 256-byte aligned) and a hipStream_t (NULL = the null stream).  Queues
+ * the FP64 coefficient table (Sec. 4 step 3), twiddle tables and the initial
+ * condition on the stream.  May be called once per plan.
+ * Errors: SETD_E_INVAL (null/misaligned pointer), SETD_E_NOMEM (too small),
+ * SETD_E_STATE (already bound), SETD_E_DEVICE.
+ */
+setd_status setd_plan_bind(setd_plan* plan, void* dev_ws, size_t bytes, void* hip_stream);
+
+/*
+ * Queue nsteps time steps (Sec. 4 algorithm box with Eq. SETD1/SETD2) of every
+ * realization on the bound stream; asynchronous.  Step n draws its noise with
+ * Philox counter (mode, n, realization, 0).  nsteps >= 0; the step index must
+ * stay below 2^32.  Errors: SETD_E_STATE (not bound), SETD_E_INVAL.
+ */
+setd_status setd_step(setd_plan* plan, int64_t nsteps);
+
+/*
+ * Compute observable `kind` (setd_obs_kind) in FP64 on the device and copy
+ * it to host_out[0, cap); *len receives the number of doubles written.
+ * Synchronises the stream.  Returns SETD_E_NONFINITE (after writing the
+ * output) if any realization has produced a non-finite value.
+ * Errors: SETD_E_INVAL (cap too small, unknown kind, SETD_OBS_TWOTIME before
+ * a snapshot, shells on unequal n[i]), SETD_E_STATE, SETD_E_DEVICE.
+ */
+setd_status setd_observe(setd_plan* plan, int kind, double* host_out, size_t cap, size_t* len);
+
+/* Copy realization r's spectral state phi_a (layout above) into host_out,
+   cap >= 2 * spectral_len doubles.  Synchronises the stream. */
+setd_status setd_get_field(setd_plan* plan, int realization, double* host_out, size_t cap);
+
+/* Overwrite realization r's spectral state from host_in (len >= 2 *
+   spectral_len doubles); dealiased modes are dropped.  Restarts that
+   realization's SETD2 history (its next step uses F_{n-1} = F_n).
+   Synchronises the stream. */
+setd_status setd_set_field(setd_plan* plan, int realization, const double* host_in, size_t len);
+
+/* Copy realization r's previous nonlinear term F_{n-1} (SETD2 history, layout
+   above, already multiplied by the model prefactor) into host_out. */
+setd_status setd_get_history(setd_plan* plan, int realization, double* host_out, size_t cap);
+
+/* Set the step index n of every realization (checkpoint restart); the next
+   step draws noise for step n. */
+setd_status setd_set_step(setd_plan* plan, int64_t step);
+
+/* Release a plan (not the caller's device memory or stream). */
+setd_status setd_plan_destroy(setd_plan* plan);
+
+/*
+ * Serving.  A server owns a scheduler thread that admits submitted jobs into
+ * the caller's device arena dev_arena[0, bytes) by their workspace footprint,
+ * keeps their fields resident, and advances all admitted jobs together:
+ * realizations of jobs with the same lattice class share one launch per pass,
+ * and newly admitted jobs join the next scheduler tick (continuous batching).
+ * A job's trajectory does not depend on what else is running.
+ */
+setd_status setd_server_create(void* dev_arena, size_t bytes, void* hip_stream, setd_server** out);
+
+/* Queue a job: a copy of *desc advanced nsteps steps.  *out receives its id.
+   Errors: SETD_E_INVAL/UNSUPPORTED as setd_plan_create, SETD_E_NOMEM if the job
+   could never fit the arena. */
+setd_status setd_submit(setd_server* server, const setd_desc* desc, int64_t nsteps, setd_job* out);
+
+/* *done = 1 once the job has finished; *job_status is its outcome
+   (SETD_OK, SETD_E_NONFINITE, ...). */
+setd_status setd_poll(setd_server* server, setd_job job, int* done, setd_status* job_status);
+
+/* Block until every submitted job has finished. */
+setd_status setd_server_drain(setd_server* server);
+
+/* Observable of a finished job, computed when it finished (kinds SETD_OBS_SK,
+   SETD_OBS_WIDTH, SETD_OBS_STEP).  SETD_E_BUSY while it runs. */
+setd_status setd_job_observe(setd_server* server, setd_job job, int kind, double* out, size_t cap, size_t* len);
+
+/* Final spectral state of a finished job's realization r (layout above). */
+setd_status setd_job_get_field(setd_server* server, setd_job job, int realization, double* host_out, size_t cap);
+
+/* Host timestamps of a job in seconds on a monotonic clock:
+   out[0] submit, out[1] admit, out[2] finish; out[3] steps done. */
+setd_status setd_job_times(setd_server* server, setd_job job, double* out4);
+
+/* Stop the scheduler thread and release the server (jobs still queued are
+   dropped; the arena itself is the caller's). */
+setd_status setd_server_destroy(setd_server* server);
+
+/* Seconds on the clock used by setd_job_times. */
+double setd_clock(void);
+
+/* Text of the calling thread's last error. */
+const char* setd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SETD_H */

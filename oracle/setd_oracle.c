@@ -314,7 +314,7 @@ typedef struct {
     size_t nspec, nreal;
     cplx* phi;                 /* R x nspec                                 */
     cplx* fprev;               /* R x nspec                                 */
-    int have_prev;
+    unsigned char* have_prev;  /* per realization: F_{n-1} exists       */
     int64_t step;
     /* per-mode data (Sec. 4 step 3), computed once */
     double* k2;                /* |k|^2                                     */
@@ -388,7 +388,8 @@ orc_sim* orc_create_subset(const orc_desc* d, int r_first, int r_count)
     s->rwork = (double*)malloc(sizeof(double) * s->nreal);
     s->rwork2 = (double*)malloc(sizeof(double) * s->nreal);
     s->F = (cplx*)malloc(sizeof(cplx) * s->nspec);
-    if (!s->phi || !s->fprev || !s->k2 || !s->kidx || !s->mask || !s->E || !s->wa || !s->wb ||
+    s->have_prev = (unsigned char*)calloc(R, 1);
+    if (!s->have_prev || !s->phi || !s->fprev || !s->k2 || !s->kidx || !s->mask || !s->E || !s->wa || !s->wb ||
         !s->G || !s->pref || !s->work || !s->work2 || !s->rwork || !s->rwork2 || !s->F) {
         orc_destroy(s);
         return NULL;
@@ -468,7 +469,6 @@ orc_sim* orc_create_subset(const orc_desc* d, int r_first, int r_count)
             }
         }
     }
-    s->have_prev = 0;
     s->step = 0;
     return s;
 }
@@ -481,7 +481,7 @@ void orc_destroy(orc_sim* s)
     free(s->phi); free(s->fprev); free(s->k2); free(s->kidx); free(s->mask);
     free(s->E); free(s->wa); free(s->wb); free(s->G); free(s->pref);
     free(s->work); free(s->work2); free(s->rwork); free(s->rwork2); free(s->F);
-    free(s->snap); free(s->acc);
+    free(s->snap); free(s->acc); free(s->have_prev);
     free(s);
 }
 
@@ -582,7 +582,7 @@ static void update(orc_sim* s, int rr, const cplx* xi)
     cplx* ph = s->phi + (size_t)rr * s->nspec;
     cplx* fp = s->fprev + (size_t)rr * s->nspec;
     const cplx* F = s->F;
-    int first = !s->have_prev;
+    int first = !s->have_prev[rr];
     for (size_t e = 0; e < s->nspec; e++) {
         if (!s->mask[e]) { ph[e] = 0; fp[e] = 0; continue; }
         cplx Fp = (s->d.order == 2 && !first) ? fp[e] : F[e];
@@ -604,9 +604,9 @@ static int step_once(orc_sim* s, const cplx* xi_all)
             for (size_t e = 0; e < s->nspec; e++)
                 xi[e] = s->G[e] * noise_eta(s, e, s->step, (uint32_t)(s->r_first + rr));
         update(s, rr, xi);
+        s->have_prev[rr] = 1;
     }
     free(xi);
-    s->have_prev = 1;
     s->step += 1;
     return 0;
 }
@@ -631,14 +631,14 @@ int orc_get(const orc_sim* s, int which, int rr, double* out)
     return 0;
 }
 
-/* setting the state restarts the SETD2 history (F_{-1} = F_0 again) */
+/* setting a realization's state restarts its SETD2 history (F_{-1} = F_0) */
 int orc_set(orc_sim* s, int rr, const double* in)
 {
     if (rr < 0 || rr >= s->R) return -1;
     cplx* dst = s->phi + (size_t)rr * s->nspec;
     const cplx* src = (const cplx*)in;
     for (size_t e = 0; e < s->nspec; e++) dst[e] = s->mask[e] ? src[e] : 0;
-    s->have_prev = 0;
+    s->have_prev[rr] = 0;
     return 0;
 }
 

@@ -1,0 +1,46 @@
+// setd_launch.hpp -- host launchers of the SETD kernels (one instantiation per
+// state precision lives in setd_k32.hip / setd_k64.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "setd_types.hpp"
+
+namespace setd {
+
+// column tile width of the strided passes: 128-byte row segments, at most
+// 1024 threads and 64 KiB of LDS per block
+template <typename T>
+constexpr int tile_for(int n)
+{
+    return sizeof(T) == 4 ? (n <= 512 ? 16 : 8) : (n <= 512 ? 8 : 4);
+}
+
+// padding of the stored last axis, in elements (128 bytes)
+template <typename T>
+constexpr int pitch_align() { return sizeof(T) == 4 ? 16 : 8; }
+
+template <typename T>
+hipError_t launch_row(const Geo& g, const Item* items, int nitems, int mode, int sub, hipStream_t s);
+template <typename T>
+hipError_t launch_axis0(const Geo& g, const Item* items, int nitems, int mode, int sub, hipStream_t s);
+template <typename T>
+hipError_t launch_axis1(const Geo& g, const Item* items, int nitems, int dir, int sub, hipStream_t s);
+template <typename T>
+hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, hipStream_t s);
+template <typename T>
+hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind, int nbins, double vol,
+                          double* acc, hipStream_t s);
+
+struct CoefArgs;
+hipError_t launch_coef(const CoefArgs& a, hipStream_t s);
+hipError_t launch_twiddle(int n, double* out64, float* out32, hipStream_t s);
+hipError_t launch_ctrl_init(Ctrl* ctrl, int n, int64_t step, hipStream_t s);
+hipError_t launch_ctrl_set(Ctrl* ctrl, int n, int64_t step, int which, hipStream_t s);
+hipError_t launch_fill64(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_obs_final(int kind, int nb, const double* acc, double* out, double* skacc, double wscale,
+                            hipStream_t s);
+hipError_t launch_obs_mean(int nb, const double* skacc, double* out, hipStream_t s);
+
+}  // namespace setd

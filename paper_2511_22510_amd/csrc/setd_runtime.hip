@@ -1,0 +1,659 @@
+// setd_runtime.hip -- plans and the C ABI of include/setd.h.
+#include "setd_runtime.hpp"
+
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "setd_launch.hpp"
+
+namespace setd {
+
+static thread_local std::string g_err;
+
+setd_status fail(setd_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+setd_status ok() { return SETD_OK; }
+
+static bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+static int ceil_isqrt_host(long m)
+{
+    if (m <= 0) return 0;
+    long s = (long)std::floor(std::sqrt((double)m));
+    while (s * s > m) s--;
+    while ((s + 1) * (s + 1) <= m) s++;
+    return (int)(s * s == m ? s : s + 1);
+}
+
+static size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+setd_status validate(const setd_desc& d)
+{
+    if (d.ndim == 1) return fail(SETD_E_UNSUPPORTED, "1D lattices are not built");
+    if (d.ndim != 2 && d.ndim != 3) return fail(SETD_E_INVAL, "ndim must be 2 or 3");
+    for (int i = 0; i < d.ndim; i++)
+        if (!pow2_in(d.n[i], 8, 1024)) return fail(SETD_E_INVAL, "n[%d] = %d is not a power of two in [8, 1024]", i, d.n[i]);
+    if (!(d.dx > 0) || !std::isfinite(d.dx)) return fail(SETD_E_INVAL, "dx must be positive");
+    if (!(d.h > 0) || !std::isfinite(d.h)) return fail(SETD_E_INVAL, "h must be positive");
+    if (d.order != 1 && d.order != 2) return fail(SETD_E_INVAL, "order must be 1 or 2");
+    if (!(d.noise_D >= 0) || !std::isfinite(d.noise_D)) return fail(SETD_E_INVAL, "noise_D must be >= 0");
+    if (d.noise_kpow != 0 && d.noise_kpow != 2) return fail(SETD_E_INVAL, "noise_kpow must be 0 or 2");
+    if (d.precision != 32 && d.precision != 64) return fail(SETD_E_INVAL, "precision must be 32 or 64");
+    if (d.realizations < 1) return fail(SETD_E_INVAL, "realizations must be >= 1");
+    if (d.dealias != 0 && d.dealias != 1) return fail(SETD_E_INVAL, "dealias must be 0 or 1");
+    if (d.ic_kind != 0 && d.ic_kind != 1) return fail(SETD_E_INVAL, "ic_kind must be 0 or 1");
+    if (d.complex_field != 0 && d.complex_field != 1) return fail(SETD_E_INVAL, "complex_field must be 0 or 1");
+    const bool cimag = d.c0[1] != 0.0 || d.c2[1] != 0.0 || d.c4[1] != 0.0;
+    if (cimag && !d.complex_field) return fail(SETD_E_INVAL, "complex c(k) needs a complex field");
+    if (d.nl < 0 || d.nl > 4) return fail(SETD_E_INVAL, "unknown nonlinearity %d", d.nl);
+    if (d.complex_field && (d.nl == NL_PHI3 || d.nl == NL_PHI3_CONS || d.nl == NL_KPZ))
+        return fail(SETD_E_UNSUPPORTED, "complex fields take the CGL nonlinearity or none");
+    if (!d.complex_field && d.nl == NL_CGL) return fail(SETD_E_UNSUPPORTED, "the CGL nonlinearity needs a complex field");
+    if (d.nl == NL_KPZ && d.ndim != 2) return fail(SETD_E_UNSUPPORTED, "KPZ is built for 2D lattices");
+    const double cs[6] = {d.c0[0], d.c0[1], d.c2[0], d.c2[1], d.c4[0], d.c4[1]};
+    for (double v : cs)
+        if (!std::isfinite(v)) return fail(SETD_E_INVAL, "c(k) coefficients must be finite");
+    if (!std::isfinite(d.nl_par[0]) || !std::isfinite(d.ic_sigma)) return fail(SETD_E_INVAL, "parameters must be finite");
+    size_t sites = 1;
+    for (int i = 0; i < d.ndim; i++) sites *= (size_t)d.n[i];
+    if ((double)sites * d.realizations > 4.0e12) return fail(SETD_E_INVAL, "problem too large");
+    return SETD_OK;
+}
+
+setd_status Plan::init(const setd_desc& desc)
+{
+    setd_status st = validate(desc);
+    if (st != SETD_OK) return st;
+    d = desc;
+    R = d.realizations;
+    g = Geo{};
+    g.ndim = d.ndim;
+    g.cplx = d.complex_field;
+    g.prec = d.precision;
+    g.dealias = d.dealias;
+    const int last = d.ndim - 1;
+    for (int i = 0; i < 3; i++) {
+        if (i >= d.ndim) {
+            g.n[i] = 1;
+            g.kept[i] = 1;
+            g.kp[i] = 0;
+            continue;
+        }
+        const int n = d.n[i];
+        g.n[i] = n;
+        if (!g.cplx && i == last) {
+            const int K = d.dealias ? (n - 1) / 3 : n / 2;
+            g.kept[i] = K + 1;
+            g.kp[i] = K;
+        } else if (d.dealias) {
+            const int K = (n - 1) / 3;
+            g.kept[i] = 2 * K + 1;
+            g.kp[i] = K;
+        } else {
+            g.kept[i] = n;
+            g.kp[i] = n - 1;
+        }
+    }
+    g.nh_last = g.cplx ? g.n[last] : g.n[last] / 2 + 1;
+    const int align = (d.precision == 32) ? 16 : 8;
+    g.pitch = (int)round_up((size_t)g.kept[last], (size_t)align);
+    elt = (d.precision == 32) ? 8 : 16;
+
+    // lattice (App. A)
+    lat = 1.0;
+    vol = 1.0;
+    nreal = 1;
+    nspec = 1;
+    for (int i = 0; i < d.ndim; i++) {
+        const double L = d.n[i] * d.dx;
+        dk[i] = 2.0 * M_PI / L;
+        lat *= std::sqrt((double)d.n[i] * (double)d.n[i] / L);
+        vol *= L / ((double)d.n[i] * (double)d.n[i]);
+        nreal *= (size_t)d.n[i];
+        nspec *= (size_t)((i == last) ? g.nh_last : d.n[i]);
+    }
+    kept_modes = 1;
+    for (int i = 0; i < d.ndim; i++) kept_modes *= (size_t)g.kept[i];
+
+    // coefficient keys: |a|^2 when all axes share dk, else separable |a_i|
+    iso = 1;
+    for (int i = 1; i < d.ndim; i++)
+        if (d.n[i] != d.n[0]) iso = 0;
+    int kmax[3] = {0, 0, 0};
+    for (int i = 0; i < d.ndim; i++) kmax[i] = d.dealias ? (d.n[i] - 1) / 3 : d.n[i] / 2;
+    if (iso) {
+        long m = 0;
+        for (int i = 0; i < d.ndim; i++) m += (long)kmax[i] * kmax[i];
+        nkeys = (int)m + 1;
+        keydim[0] = keydim[1] = keydim[2] = 1;
+    } else {
+        for (int i = 0; i < 3; i++) keydim[i] = (i < d.ndim) ? kmax[i] + 1 : 1;
+        nkeys = keydim[0] * keydim[1] * keydim[2];
+    }
+    coef_cplx = (d.c0[1] != 0.0 || d.c2[1] != 0.0 || d.c4[1] != 0.0) ? 1 : 0;
+    long msq = 0;
+    for (int i = 0; i < d.ndim; i++) msq += (long)(d.n[i] / 2) * (d.n[i] / 2);
+    nbins = ceil_isqrt_host(msq) + 1;
+
+    // sizes
+    const size_t k1 = (d.ndim == 3) ? (size_t)g.kept[1] : 1;
+    S = (size_t)g.kept[0] * k1 * g.pitch;
+    P = (size_t)g.n[0] * k1 * g.pitch;
+    B = (d.ndim == 3) ? (size_t)g.n[0] * g.n[1] * g.pitch : 0;
+
+    // workspace layout, every buffer 256-byte aligned
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += round_up(bytes ? bytes : 1, 256);
+        return o;
+    };
+    const size_t cdbl = coef_cplx ? 8 : 4;
+    lay.items = take((size_t)R * sizeof(Item));
+    lay.ctrl = take((size_t)R * sizeof(Ctrl));
+    lay.coef64 = take((size_t)nkeys * cdbl * 8);
+    lay.coef32 = (d.precision == 32) ? take((size_t)nkeys * cdbl * 4) : 0;
+    for (int i = 0; i < d.ndim; i++) {
+        lay.tw64[i] = take((size_t)d.n[i] * 16);
+        lay.tw32[i] = take((size_t)d.n[i] * 8);
+    }
+    lay.acc = take((size_t)3 * nbins * 8);
+    lay.skacc = take((size_t)(2 * nbins + 1) * 8);
+    lay.out = take((size_t)3 * nbins * 8);
+    lay.phi = take((size_t)R * S * elt);
+    lay.prev = (d.order == 2) ? take((size_t)R * S * elt) : 0;
+    lay.pre0 = take((size_t)R * P * elt);
+    lay.pre1 = (d.nl == NL_KPZ) ? take((size_t)R * P * elt) : 0;
+    lay.big = B ? take((size_t)R * B * elt) : 0;
+    lay.snap = take((size_t)R * S * elt);
+    lay.total = off;
+    return SETD_OK;
+}
+
+int Plan::passes_per_step() const
+{
+    if (d.nl == NL_NONE) return 1;
+    return d.ndim == 2 ? 2 : 4;
+}
+
+// HBM bytes a step must move with the stored (2/3-pruned) arrays, counted per
+// pass as one read and one write of what LDS cannot hold.
+double Plan::alg_bytes_per_step() const
+{
+    const double kl = (double)g.kept[g.ndim - 1];
+    const double st = (double)kept_modes;                 // stored modes
+    const double hist = (d.order == 2) ? 2.0 : 0.0;       // read + write F_{n-1}
+    double per;
+    if (d.nl == NL_NONE) {
+        per = 2.0 * st;
+    } else if (d.ndim == 2) {
+        const double pre = (double)g.n[0] * kl;
+        const double npre = (d.nl == NL_KPZ) ? 2.0 : 1.0;
+        per = (npre + 1.0) * pre          // row pass: read pre (and pre1), write pre
+              + pre + npre * pre          // axis-0 pass: read pre, write pre (and pre1)
+              + (2.0 + hist) * st;        // state and history
+    } else {
+        const double small = (double)g.n[0] * g.kept[1] * kl;
+        const double bigv = (double)g.n[0] * g.n[1] * kl;
+        per = (small + bigv)              // axis-1 inverse
+              + 2.0 * bigv                // row pass
+              + (bigv + small)            // axis-1 forward
+              + 2.0 * small + (2.0 + hist) * st;
+    }
+    return per * (double)elt * R;
+}
+
+template <typename T>
+static setd_status launch_step_t(const Plan& p, const Item* items_dev, int nitems, int sub, hipStream_t s)
+{
+    const Geo& g = p.g;
+    if (p.d.nl == NL_NONE) {
+        SETD_HIP((launch_linear<T>(g, items_dev, nitems, sub, s)));
+        return SETD_OK;
+    }
+    if (g.ndim == 3) SETD_HIP((launch_axis1<T>(g, items_dev, nitems, +1, sub, s)));
+    SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_STEP, sub, s)));
+    if (g.ndim == 3) SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -1, sub, s)));
+    SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_STEP, sub, s)));
+    return SETD_OK;
+}
+
+setd_status Plan::launch_step(const Item* items_dev, int nitems, int sub, hipStream_t s) const
+{
+    return d.precision == 32 ? launch_step_t<float>(*this, items_dev, nitems, sub, s)
+                             : launch_step_t<double>(*this, items_dev, nitems, sub, s);
+}
+
+template <typename T>
+static setd_status launch_ic_t(const Plan& p, const Item* items_dev, int nitems, hipStream_t s)
+{
+    const Geo& g = p.g;
+    SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_IC, 0, s)));
+    if (g.ndim == 3) SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -1, 0, s)));
+    SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_IC, 0, s)));
+    return SETD_OK;
+}
+
+template <typename T>
+static setd_status launch_sync_t(const Plan& p, const Item* items_dev, int nitems, hipStream_t s)
+{
+    SETD_HIP((launch_axis0<T>(p.g, items_dev, nitems, MODE_SYNC, 0, s)));
+    return SETD_OK;
+}
+
+setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
+{
+    if (bound) return fail(SETD_E_STATE, "plan already bound");
+    if (!dev) return fail(SETD_E_INVAL, "null workspace");
+    if (((uintptr_t)dev) % 256 != 0) return fail(SETD_E_INVAL, "workspace must be 256-byte aligned");
+    if (bytes < lay.total) return fail(SETD_E_NOMEM, "workspace of %zu bytes, %zu needed", bytes, lay.total);
+    ws = (char*)dev;
+    stream = s;
+    const int last = d.ndim - 1;
+
+    items.assign(R, Item{});
+    for (int r = 0; r < R; r++) {
+        Item& it = items[r];
+        it.phi = ws + lay.phi + (size_t)r * S * elt;
+        it.prev = (d.order == 2) ? ws + lay.prev + (size_t)r * S * elt : nullptr;
+        it.pre0 = ws + lay.pre0 + (size_t)r * P * elt;
+        it.pre1 = (d.nl == NL_KPZ) ? ws + lay.pre1 + (size_t)r * P * elt : nullptr;
+        it.big = B ? ws + lay.big + (size_t)r * B * elt : nullptr;
+        it.snap = ws + lay.snap + (size_t)r * S * elt;
+        it.coef = ws + ((d.precision == 32) ? lay.coef32 : lay.coef64);
+        const size_t* tw = (d.precision == 32) ? lay.tw32 : lay.tw64;
+        it.tw0 = ws + tw[0];
+        it.tw1 = ws + tw[1];
+        it.tw2 = (d.ndim == 3) ? ws + tw[2] : nullptr;
+        it.ctrl = reinterpret_cast<Ctrl*>(ws + lay.ctrl) + r;
+        it.seed = d.seed;
+        it.r = (uint32_t)r;
+        it.nl = d.nl;
+        it.order = d.order;
+        it.iso = iso;
+        it.coef_cplx = coef_cplx;
+        it.steps = INT_MAX;
+        for (int i = 0; i < 3; i++) {
+            it.keydim[i] = keydim[i];
+            it.dk[i] = dk[i];
+        }
+        it.par0 = d.nl_par[0];
+        it.inv_vol = 1.0 / (double)nreal;
+        it.ic_sigma = d.ic_sigma;
+    }
+    (void)last;
+    SETD_HIP(hipMemcpyAsync(ws + lay.items, items.data(), (size_t)R * sizeof(Item), hipMemcpyHostToDevice, s));
+
+    // twiddles and the FP64 coefficient table (Sec. 4 step 3)
+    for (int i = 0; i < d.ndim; i++)
+        SETD_HIP(launch_twiddle(d.n[i], reinterpret_cast<double*>(ws + lay.tw64[i]),
+                                reinterpret_cast<float*>(ws + lay.tw32[i]), s));
+    CoefArgs ca{};
+    ca.nkeys = nkeys;
+    ca.iso = iso;
+    ca.ndim = d.ndim;
+    ca.order = d.order;
+    ca.kpow = d.noise_kpow;
+    ca.cplx_table = coef_cplx;
+    for (int i = 0; i < 3; i++) {
+        ca.keydim[i] = keydim[i];
+        ca.dk[i] = dk[i];
+    }
+    for (int j = 0; j < 2; j++) {
+        ca.c0[j] = d.c0[j];
+        ca.c2[j] = d.c2[j];
+        ca.c4[j] = d.c4[j];
+    }
+    ca.D = d.noise_D;
+    ca.h = d.h;
+    ca.lat = lat;
+    ca.out64 = reinterpret_cast<double*>(ws + lay.coef64);
+    ca.out32 = (d.precision == 32) ? (void*)(ws + lay.coef32) : nullptr;
+    SETD_HIP(launch_coef(ca, s));
+
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + lay.ctrl);
+    SETD_HIP(launch_ctrl_init(ctrl, R, 0, s));
+    SETD_HIP(launch_fill64(reinterpret_cast<double*>(ws + lay.skacc), 2 * nbins + 1, 0.0, s));
+    // state buffers start at zero (all of them are multiples of 8 bytes)
+    auto zero = [&](size_t off, size_t bytes) -> setd_status {
+        if (!bytes) return SETD_OK;
+        SETD_HIP(launch_fill64(reinterpret_cast<double*>(ws + off), (int64_t)(bytes / 8), 0.0, s));
+        return SETD_OK;
+    };
+    setd_status st;
+    if ((st = zero(lay.phi, (size_t)R * S * elt)) != SETD_OK) return st;
+    if (d.order == 2 && (st = zero(lay.prev, (size_t)R * S * elt)) != SETD_OK) return st;
+    if ((st = zero(lay.pre0, (size_t)R * P * elt)) != SETD_OK) return st;
+    if (d.nl == NL_KPZ && (st = zero(lay.pre1, (size_t)R * P * elt)) != SETD_OK) return st;
+    if (B && (st = zero(lay.big, (size_t)R * B * elt)) != SETD_OK) return st;
+    if ((st = zero(lay.snap, (size_t)R * S * elt)) != SETD_OK) return st;
+
+    const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
+    if (d.ic_kind == 1) {
+        st = (d.precision == 32) ? launch_ic_t<float>(*this, items_dev, R, s) : launch_ic_t<double>(*this, items_dev, R, s);
+        if (st != SETD_OK) return st;
+    }
+    SETD_HIP(hipStreamSynchronize(s));
+    bound = true;
+    step_host = 0;
+    return SETD_OK;
+}
+
+setd_status Plan::step(int64_t n)
+{
+    if (!bound) return fail(SETD_E_STATE, "plan not bound");
+    if (n < 0) return fail(SETD_E_INVAL, "negative step count");
+    if (step_host + n >= (int64_t)1 << 32) return fail(SETD_E_INVAL, "step index would exceed 2^32");
+    const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
+    for (int64_t i = 0; i < n; i++) {
+        setd_status st = launch_step(items_dev, R, 0, stream);
+        if (st != SETD_OK) return st;
+    }
+    step_host += n;
+    return SETD_OK;
+}
+
+setd_status Plan::nonfinite_any(int* flag)
+{
+    std::vector<Ctrl> c(R);
+    SETD_HIP(hipMemcpyAsync(c.data(), ws + lay.ctrl, (size_t)R * sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+    SETD_HIP(hipStreamSynchronize(stream));
+    int f = 0;
+    for (const Ctrl& x : c) f |= x.nonfinite;
+    *flag = f;
+    return SETD_OK;
+}
+
+setd_status Plan::observe(int kind, double* out, size_t cap, size_t* len)
+{
+    if (!bound) return fail(SETD_E_STATE, "plan not bound");
+    if (!out || !len) return fail(SETD_E_INVAL, "null output");
+    const int nb = nbins;
+    double* acc = reinterpret_cast<double*>(ws + lay.acc);
+    double* skacc = reinterpret_cast<double*>(ws + lay.skacc);
+    double* dout = reinterpret_cast<double*>(ws + lay.out);
+    const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
+    size_t n_out = 0;
+    auto reduce = [&](int red) -> setd_status {
+        SETD_HIP(launch_fill64(acc, 3 * nb, 0.0, stream));
+        if (d.precision == 32) SETD_HIP((launch_observe<float>(g, items_dev, R, red, nb, vol, acc, stream)));
+        else SETD_HIP((launch_observe<double>(g, items_dev, R, red, nb, vol, acc, stream)));
+        return SETD_OK;
+    };
+    setd_status st;
+    switch (kind) {
+    case SETD_OBS_SK:
+    case SETD_OBS_SK_ACCUM:
+        if (!iso) return fail(SETD_E_INVAL, "shell averages need equal n[i]");
+        if (kind == SETD_OBS_SK && cap < (size_t)2 * nb) return fail(SETD_E_INVAL, "output needs %d doubles", 2 * nb);
+        if (kind == SETD_OBS_SK_ACCUM && cap < 1) return fail(SETD_E_INVAL, "output needs 1 double");
+        if ((st = reduce(RED_SK)) != SETD_OK) return st;
+        SETD_HIP(launch_obs_final(kind == SETD_OBS_SK ? 0 : 5, nb, acc, dout, skacc, 0.0, stream));
+        n_out = (kind == SETD_OBS_SK) ? (size_t)2 * nb : 1;
+        break;
+    case SETD_OBS_SK_MEAN:
+        if (!iso) return fail(SETD_E_INVAL, "shell averages need equal n[i]");
+        if (cap < (size_t)2 * nb) return fail(SETD_E_INVAL, "output needs %d doubles", 2 * nb);
+        SETD_HIP(launch_obs_mean(nb, skacc, dout, stream));
+        n_out = (size_t)2 * nb;
+        break;
+    case SETD_OBS_WIDTH:
+        if (cap < 1) return fail(SETD_E_INVAL, "output needs 1 double");
+        if ((st = reduce(RED_WIDTH)) != SETD_OK) return st;
+        SETD_HIP(launch_obs_final(1, nb, acc, dout, skacc, 1.0 / ((double)nreal * (double)nreal * R), stream));
+        n_out = 1;
+        break;
+    case SETD_OBS_TWOTIME:
+        if (!iso) return fail(SETD_E_INVAL, "shell averages need equal n[i]");
+        if (!have_snap) return fail(SETD_E_INVAL, "no snapshot taken");
+        if (cap < (size_t)3 * nb) return fail(SETD_E_INVAL, "output needs %d doubles", 3 * nb);
+        if ((st = reduce(RED_TWOTIME)) != SETD_OK) return st;
+        SETD_HIP(launch_obs_final(3, nb, acc, dout, skacc, 0.0, stream));
+        n_out = (size_t)3 * nb;
+        break;
+    case SETD_OBS_SNAPSHOT: {
+        SETD_HIP(launch_copy(ws + lay.snap, ws + lay.phi, (size_t)R * S * elt, stream));
+        have_snap = true;
+        Ctrl c0;
+        SETD_HIP(hipMemcpyAsync(&c0, ws + lay.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+        SETD_HIP(hipStreamSynchronize(stream));
+        if (cap >= 1) {
+            out[0] = (double)c0.step;
+            *len = 1;
+        } else {
+            *len = 0;
+        }
+        int f = 0;
+        if ((st = nonfinite_any(&f)) != SETD_OK) return st;
+        return f ? fail(SETD_E_NONFINITE, "a realization produced a non-finite value") : SETD_OK;
+    }
+    case SETD_OBS_STEP: {
+        if (cap < 2) return fail(SETD_E_INVAL, "output needs 2 doubles");
+        Ctrl c0;
+        SETD_HIP(hipMemcpyAsync(&c0, ws + lay.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+        int f = 0;
+        if ((st = nonfinite_any(&f)) != SETD_OK) return st;
+        out[0] = (double)c0.step;
+        out[1] = (double)f;
+        *len = 2;
+        return f ? fail(SETD_E_NONFINITE, "a realization produced a non-finite value") : SETD_OK;
+    }
+    default:
+        return fail(SETD_E_INVAL, "unknown observable kind %d", kind);
+    }
+    SETD_HIP(hipMemcpyAsync(out, dout, n_out * sizeof(double), hipMemcpyDeviceToHost, stream));
+    SETD_HIP(hipStreamSynchronize(stream));
+    *len = n_out;
+    int f = 0;
+    if ((st = nonfinite_any(&f)) != SETD_OK) return st;
+    return f ? fail(SETD_E_NONFINITE, "a realization produced a non-finite value") : SETD_OK;
+}
+
+// Scatter a stored block (phi or F_{n-1}) of realization r into the unpruned
+// FFT-order layout of the ABI, as interleaved doubles.
+setd_status Plan::get_block(size_t off, int r, double* out, size_t cap)
+{
+    if (!bound) return fail(SETD_E_STATE, "plan not bound");
+    if (r < 0 || r >= R) return fail(SETD_E_INVAL, "realization %d out of range", r);
+    if (!out || cap < 2 * nspec) return fail(SETD_E_INVAL, "output needs %zu doubles", 2 * nspec);
+    std::vector<char> host(S * elt);
+    SETD_HIP(hipMemcpyAsync(host.data(), ws + off + (size_t)r * S * elt, S * elt, hipMemcpyDeviceToHost, stream));
+    SETD_HIP(hipStreamSynchronize(stream));
+    std::memset(out, 0, 2 * nspec * sizeof(double));
+    const int last = d.ndim - 1;
+    const int k1 = (d.ndim == 3) ? g.kept[1] : 1;
+    for (int i0 = 0; i0 < g.kept[0]; i0++) {
+        const int j0 = (i0 <= g.kp[0]) ? i0 : i0 + g.n[0] - g.kept[0];
+        for (int i1 = 0; i1 < k1; i1++) {
+            const int j1 = (d.ndim == 3) ? ((i1 <= g.kp[1]) ? i1 : i1 + g.n[1] - g.kept[1]) : 0;
+            for (int c = 0; c < g.kept[last]; c++) {
+                const int jl = g.cplx ? ((c <= g.kp[last]) ? c : c + g.n[last] - g.kept[last]) : c;
+                const size_t src = ((size_t)i0 * k1 + i1) * g.pitch + c;
+                const size_t dst = (d.ndim == 3) ? ((size_t)j0 * g.n[1] + j1) * g.nh_last + jl
+                                                 : (size_t)j0 * g.nh_last + jl;
+                double re, im;
+                if (d.precision == 32) {
+                    const float* f = reinterpret_cast<const float*>(host.data()) + 2 * src;
+                    re = f[0];
+                    im = f[1];
+                } else {
+                    const double* f = reinterpret_cast<const double*>(host.data()) + 2 * src;
+                    re = f[0];
+                    im = f[1];
+                }
+                out[2 * dst] = re;
+                out[2 * dst + 1] = im;
+            }
+        }
+    }
+    return SETD_OK;
+}
+
+setd_status Plan::set_field(int r, const double* in, size_t len)
+{
+    if (!bound) return fail(SETD_E_STATE, "plan not bound");
+    if (r < 0 || r >= R) return fail(SETD_E_INVAL, "realization %d out of range", r);
+    if (!in || len < 2 * nspec) return fail(SETD_E_INVAL, "input needs %zu doubles", 2 * nspec);
+    std::vector<char> host(S * elt, 0);
+    const int last = d.ndim - 1;
+    const int k1 = (d.ndim == 3) ? g.kept[1] : 1;
+    for (int i0 = 0; i0 < g.kept[0]; i0++) {
+        const int j0 = (i0 <= g.kp[0]) ? i0 : i0 + g.n[0] - g.kept[0];
+        for (int i1 = 0; i1 < k1; i1++) {
+            const int j1 = (d.ndim == 3) ? ((i1 <= g.kp[1]) ? i1 : i1 + g.n[1] - g.kept[1]) : 0;
+            for (int c = 0; c < g.kept[last]; c++) {
+                const int jl = g.cplx ? ((c <= g.kp[last]) ? c : c + g.n[last] - g.kept[last]) : c;
+                const size_t dst = ((size_t)i0 * k1 + i1) * g.pitch + c;
+                const size_t src = (d.ndim == 3) ? ((size_t)j0 * g.n[1] + j1) * g.nh_last + jl
+                                                 : (size_t)j0 * g.nh_last + jl;
+                if (d.precision == 32) {
+                    float* f = reinterpret_cast<float*>(host.data()) + 2 * dst;
+                    f[0] = (float)in[2 * src];
+                    f[1] = (float)in[2 * src + 1];
+                } else {
+                    double* f = reinterpret_cast<double*>(host.data()) + 2 * dst;
+                    f[0] = in[2 * src];
+                    f[1] = in[2 * src + 1];
+                }
+            }
+        }
+    }
+    SETD_HIP(hipMemcpyAsync(ws + lay.phi + (size_t)r * S * elt, host.data(), S * elt, hipMemcpyHostToDevice, stream));
+    const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items) + r;
+    setd_status st = (d.precision == 32) ? launch_sync_t<float>(*this, items_dev, 1, stream)
+                                         : launch_sync_t<double>(*this, items_dev, 1, stream);
+    if (st != SETD_OK) return st;
+    SETD_HIP(launch_ctrl_set(reinterpret_cast<Ctrl*>(ws + lay.ctrl) + r, 1, 0, 1, stream));
+    SETD_HIP(hipStreamSynchronize(stream));
+    return SETD_OK;
+}
+
+setd_status Plan::set_step(int64_t s)
+{
+    if (!bound) return fail(SETD_E_STATE, "plan not bound");
+    if (s < 0 || s >= ((int64_t)1 << 32)) return fail(SETD_E_INVAL, "step index out of range");
+    SETD_HIP(launch_ctrl_set(reinterpret_cast<Ctrl*>(ws + lay.ctrl), R, s, 0, stream));
+    SETD_HIP(hipStreamSynchronize(stream));
+    step_host = s;
+    return SETD_OK;
+}
+
+std::string class_key(const Plan& p)
+{
+    char buf[160];
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%d|%d|%d", p.g.ndim, p.g.cplx, p.g.prec, p.g.dealias, p.g.n[0],
+             p.g.n[1], p.g.n[2], p.d.nl == NL_NONE ? 1 : 0);
+    return buf;
+}
+
+}  // namespace setd
+
+// ====================================================================== C ABI
+using setd::Plan;
+
+struct setd_plan {
+    Plan p;
+};
+
+extern "C" {
+
+setd_status setd_plan_create(const setd_desc* desc, setd_plan** out)
+{
+    if (!desc || !out) return setd::fail(SETD_E_INVAL, "null argument");
+    *out = nullptr;
+    setd_plan* h = new (std::nothrow) setd_plan();
+    if (!h) return setd::fail(SETD_E_NOMEM, "host allocation failed");
+    setd_status st = h->p.init(*desc);
+    if (st != SETD_OK) {
+        delete h;
+        return st;
+    }
+    *out = h;
+    return SETD_OK;
+}
+
+setd_status setd_plan_workspace(const setd_plan* plan, size_t* bytes)
+{
+    if (!plan || !bytes) return setd::fail(SETD_E_INVAL, "null argument");
+    *bytes = plan->p.lay.total;
+    return SETD_OK;
+}
+
+setd_status setd_plan_info(const setd_plan* plan, setd_plan_info_t* info)
+{
+    if (!plan || !info) return setd::fail(SETD_E_INVAL, "null argument");
+    const Plan& p = plan->p;
+    info->workspace_bytes = p.lay.total;
+    info->spectral_len = p.nspec;
+    info->kept_modes = p.kept_modes;
+    info->nbins = p.nbins;
+    info->passes_per_step = p.passes_per_step();
+    info->alg_bytes_per_step = p.alg_bytes_per_step();
+    info->site_updates_per_step = (double)p.nreal * p.R;
+    return SETD_OK;
+}
+
+setd_status setd_plan_bind(setd_plan* plan, void* dev_ws, size_t bytes, void* hip_stream)
+{
+    if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
+    return plan->p.bind(dev_ws, bytes, (hipStream_t)hip_stream);
+}
+
+setd_status setd_step(setd_plan* plan, int64_t nsteps)
+{
+    if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
+    return plan->p.step(nsteps);
+}
+
+setd_status setd_observe(setd_plan* plan, int kind, double* host_out, size_t cap, size_t* len)
+{
+    if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
+    return plan->p.observe(kind, host_out, cap, len);
+}
+
+setd_status setd_get_field(setd_plan* plan, int realization, double* host_out, size_t cap)
+{
+    if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
+    return plan->p.get_block(plan->p.lay.phi, realization, host_out, cap);
+}
+
+setd_status setd_get_history(setd_plan* plan, int realization, double* host_out, size_t cap)
+{
+    if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
+    if (plan->p.d.order != 2) return setd::fail(SETD_E_INVAL, "SETD1 keeps no history");
+    return plan->p.get_block(plan->p.lay.prev, realization, host_out, cap);
+}
+
+setd_status setd_set_field(setd_plan* plan, int realization, const double* host_in, size_t len)
+{
+    if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
+    return plan->p.set_field(realization, host_in, len);
+}
+
+setd_status setd_set_step(setd_plan* plan, int64_t step)
+{
+    if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
+    return plan->p.set_step(step);
+}
+
+setd_status setd_plan_destroy(setd_plan* plan)
+{
+    delete plan;
+    return SETD_OK;
+}
+
+const char* setd_last_error(void) { return setd::g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// setd_runtime.hpp -- host-side plan object shared by the C ABI and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "../../include/setd.h"
+#include "setd_types.hpp"
+
+namespace setd {
+
+setd_status fail(setd_status s, const char* fmt, ...);
+setd_status ok();
+
+#define SETD_HIP(call)                                                                                       \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
+        if (e_ != hipSuccess) return ::setd::fail(SETD_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Byte offsets of every buffer of a plan's workspace.
+struct Layout {
+    size_t items = 0, ctrl = 0, coef64 = 0, coef32 = 0;
+    size_t tw64[3] = {0, 0, 0}, tw32[3] = {0, 0, 0};
+    size_t acc = 0, skacc = 0, out = 0;
+    size_t phi = 0, prev = 0, pre0 = 0, pre1 = 0, big = 0, snap = 0;
+    size_t total = 0;
+};
+
+struct Plan {
+    setd_desc d{};
+    Geo g{};
+    int R = 0;
+    int nkeys = 0, iso = 0, coef_cplx = 0, nbins = 0;
+    int keydim[3] = {1, 1, 1};
+    double dk[3] = {0, 0, 0};
+    double lat = 1.0, vol = 1.0;
+    size_t S = 0, P = 0, B = 0;   // complex elements per realization: state, pre, big
+    size_t elt = 0;               // bytes per complex element
+    size_t nspec = 0;             // unpruned spectral length per realization
+    size_t nreal = 0;             // lattice sites per realization
+    size_t kept_modes = 0;
+    Layout lay;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    bool have_snap = false;
+    int64_t step_host = 0;        // steps queued so far (mirror of the device counter)
+    std::vector<Item> items;      // host copy of the device item table
+
+    setd_status init(const setd_desc& desc);
+    setd_status bind(void* dev, size_t bytes, hipStream_t s);
+    // queue the passes of one step for nitems items starting at items_dev
+    setd_status launch_step(const Item* items_dev, int nitems, int sub, hipStream_t s) const;
+    setd_status step(int64_t n);
+    setd_status observe(int kind, double* out, size_t cap, size_t* len);
+    setd_status get_block(size_t off, int r, double* out, size_t cap);
+    setd_status set_field(int r, const double* in, size_t len);
+    setd_status set_step(int64_t step);
+    setd_status nonfinite_any(int* flag);
+    double alg_bytes_per_step() const;
+    int passes_per_step() const;
+};
+
+// descriptor validation shared by plans and the server
+setd_status validate(const setd_desc& d);
+// launch class key: jobs with equal keys can share launches
+std::string class_key(const Plan& p);
+
+}  // namespace setd

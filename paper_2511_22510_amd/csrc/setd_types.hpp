@@ -1,0 +1,78 @@
+// setd_types.hpp -- plain structs shared by the host runtime and the kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace setd {
+
+// Launch class: everything that fixes the kernels, their grids and the data
+// layout.  Realizations of different jobs with the same class share launches.
+struct Geo {
+    int ndim;         // 2 or 3
+    int cplx;         // 0 real field (last axis R2C), 1 complex field
+    int prec;         // 32 or 64
+    int dealias;      // 0 or 1
+    int n[3];         // lattice points per axis (n[ndim..2] = 1)
+    int kept[3];      // stored spectral entries per axis
+    int kp[3];        // largest stored FFT index on the low side of each axis
+    int pitch;        // padded length of the stored last axis (elements)
+    int nh_last;      // unpruned spectral length of the last axis (n/2+1 or n)
+};
+
+// Per-realization control block in device memory.
+struct Ctrl {
+    int64_t step;          // index n of the next transition n -> n+1
+    uint32_t done;         // blocks finished in the current update pass
+    int32_t have_prev;     // F_{n-1} stored (SETD2)
+    int32_t nonfinite;     // a NaN/Inf was produced
+    int32_t pad[3];
+};
+
+// One realization of one job, as the kernels see it.
+struct Item {
+    void* phi;        // stored spectral state  [kept0][kept1][pitch] (3D) / [kept0][pitch]
+    void* prev;       // F_{n-1}, same layout (SETD2), else null
+    void* pre0;       // axis-0 inverse of phi: [n0][kept1][pitch] / [n0][pitch]
+    void* pre1;       // KPZ: axis-0 inverse of i k0 phi (2D), else null
+    void* big;        // 3D: [n0][n1][pitch] line buffer of the last-axis pass
+    void* snap;       // snapshot of phi for two-time correlations
+    const void* coef; // coefficient table in the state precision
+    const void* tw0;  // twiddles exp(-2 pi i k / n_axis), state precision
+    const void* tw1;
+    const void* tw2;
+    Ctrl* ctrl;
+    uint64_t seed;
+    uint32_t r;       // realization index in the Philox counter
+    int32_t nl;       // nonlinearity kind
+    int32_t order;    // 1 or 2
+    int32_t iso;      // coefficient key |a|^2 (1) or separable (0)
+    int32_t coef_cplx;// coefficient table has complex entries
+    int32_t steps;    // sub-steps to take in the current scheduler tick
+    int32_t keydim[3];// separable key extents (K_i + 1)
+    int32_t pad0;
+    double dk[3];     // 2 pi / L_i
+    double par0;      // u | lambda | beta
+    double inv_vol;   // 1 / prod n_i (inverse DFT scale)
+    double ic_sigma;
+};
+
+// arguments of the FP64 coefficient-table kernel
+struct CoefArgs {
+    int nkeys, iso, ndim, order, kpow, cplx_table;
+    int keydim[3];
+    double dk[3];
+    double c0[2], c2[2], c4[2];
+    double D, h, lat;
+    double* out64;
+    void* out32;   // float table or null
+};
+
+enum { NL_PHI3 = 0, NL_PHI3_CONS = 1, NL_KPZ = 2, NL_CGL = 3, NL_NONE = 4 };
+
+// modes of the passes
+enum { MODE_STEP = 0, MODE_IC = 1, MODE_SYNC = 2 };
+
+// observable reductions
+enum { RED_SK = 0, RED_WIDTH = 1, RED_TWOTIME = 2 };
+
+}  // namespace setd

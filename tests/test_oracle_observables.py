@@ -73,7 +73,7 @@ def test_steady_state_structure_factor_matches_linear_theory():
         a = [(a0, a1) for a0 in range(-16, 16) for a1 in range(-16, 16)
              if _ceil_shell(a0 * a0 + a1 * a1) == b]
         th = np.mean([T / (r + (2 * np.pi / 32) ** 2 * (a0 * a0 + a1 * a1)) for a0, a1 in a])
-        zs.append((out[b] / th - 1) / np.sqrt(1.0 / (cnt * 64)))
+        zs.append((out[b] / th - 1) / np.sqrt(2.0 / (cnt * 64)))
     assert np.max(np.abs(zs)) < 4.5, zs
 
 
