@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the SETD pseudo-spectral step on one MI355X.
+
+Workload (the batched configuration the headline metric is quoted on): Model B
+(d phi/dt = lap(r phi + u phi^3 - lap phi) + sqrt(2T) div eta, r = -1, u = 1,
+T = 0.05) on a 512 x 512 lattice, dx = 1, h = 0.005, SETD2, complex64 state with
+FP64-evaluated coefficients, 64 noise realizations advanced together, 2/3
+dealiasing, initial phi ~ N(0, 0.05^2) per site.  Inputs are synthetic and
+seeded; all fields are resident in HBM before the timed region starts.
+
+One step = one SETD2 transition of every realization: the last-axis pass
+(inverse FFT, phi^3, forward FFT) and the axis-0 pass (forward FFT, ETD update
+with Philox noise and dealiasing, inverse FFT).
+
+Printed: one JSON line with site-updates/s, the roofline record of the
+dominant kernel (timed live with HIP events on the library's stream), the
+plain per-realization FP64 rate of the same model on the same GPU, a short
+continuous-batching serving run (p50/p99 job latency), and the FP64 oracle
+timed on the host cores over a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_axis0_model_b_512.txt")
+KERNEL_SOURCES = ["setd_device.hpp", "setd_kernels.hpp", "setd_launch_impl.hpp", "setd_types.hpp"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2511_22510_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when it is missing or the kernel sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash() or vals.get("kernel") != kernel:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_plan(setd, p, steps, warmup, profile):
+    import torch
+    plan = setd.Plan(p)
+    plan.step(warmup)
+    torch.cuda.synchronize()
+    if profile:
+        setd.setd_profile(plan.h, 1, plan.lib)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = setd.setd_profile_read(plan.h, plan.lib) if profile else None
+    out, st = setd.setd_observe(plan.h, setd.OBS_STEP, 4, plan.lib, allow_nonfinite=True)
+    ok = (st == setd.SETD_OK) and out[0] == warmup + steps
+    info = plan.info
+    plan.close()
+    return t1 - t0, prof, info, ok
+
+
+def serving_run(setd, W, n_jobs, seed):
+    """A Poisson stream of mixed SETD2 FP32 jobs through the continuous-batching
+    server; returns latency percentiles and throughput."""
+    import numpy as np
+    import torch
+    trace = W.serving_trace(n_jobs=n_jobs, rate=20.0, seed=seed, steps_range=(1000, 10000))
+    srv = setd.Server(arena_bytes=int(64 * 2**30))
+    t_start = setd.setd_clock(srv.lib)
+    ids = []
+    for job in trace:
+        while setd.setd_clock(srv.lib) - t_start < job["arrival"]:
+            time.sleep(0.0005)
+        ids.append((srv.submit(job["problem"], job["steps"]), job))
+    srv.drain()
+    t_end = setd.setd_clock(srv.lib)
+    lat, su = [], 0
+    for jid, job in ids:
+        times = srv.times(jid)
+        lat.append(times[2] - times[0])
+        su += W.site_updates(job["problem"], job["steps"])
+    srv.close()
+    torch.cuda.synchronize()
+    lat = np.array(lat)
+    return {
+        "jobs": len(ids), "arrival_rate_per_s": 20.0,
+        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+        "makespan_s": float(t_end - t_start), "site_updates_per_s": float(su / (t_end - t_start)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--serving-jobs", type=int, default=40, help="0 skips the serving run")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 512 MiB device-to-device (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(realizations shard across GPUs without communication; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2511_22510_amd import setd, workloads as W
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(2**27, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    p = W.problem(W.CONFIG_B)
+    elapsed, prof, info, ok = time_plan(setd, p, args.steps, args.warmup, profile=True)
+    if not ok:
+        print("bench: the batched run did not complete cleanly", file=sys.stderr)
+        sys.exit(1)
+    sites = float(info.site_updates_per_step)
+    value = sites * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    pass_names = ["k_row_real<float,512>", "k_axis0<float,512,16>"]
+    tot_ms = prof[:, 0]
+    cnt = prof[:, 1]
+    dom = int(np.argmax(tot_ms))
+    avg_s = tot_ms[dom] / cnt[dom] * 1e-3
+    alg = float(info.pass_bytes[dom])
+    achieved = alg / avg_s / 1e9
+    traffic = measured_traffic(pass_names[dom])
+    roofline = {
+        "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+        "kernel": pass_names[dom], "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": alg,
+        "passes": [{"kernel": pass_names[i], "avg_us": float(tot_ms[i] / cnt[i] * 1e3),
+                    "alg_bytes": float(info.pass_bytes[i]),
+                    "gbs": float(info.pass_bytes[i] / (tot_ms[i] / cnt[i] * 1e-3) / 1e9)}
+                   for i in range(len(tot_ms))],
+        "step_alg_bytes": float(info.alg_bytes_per_step),
+        "step_frac": float(info.alg_bytes_per_step / (elapsed / args.steps) / 1e9 / PEAK_HBM_GBS),
+    }
+
+    line = {
+        "metric": "site-updates/s per SETD step, batched FP32 vs plain FP64; p99 job latency",
+        "value": value, "unit": "site-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Model B 512x512, SETD2, complex64 state + FP64 coefficients, "
+                               "64 realizations, h=0.005, 2/3 dealiasing",
+                   "lattice": [512, 512], "realizations": 64, "scheme": "SETD2", "h": 0.005,
+                   "global_batch": 64, "parallelism": "single GPU"},
+        "roofline": roofline,
+    }
+
+    if not args.no_fp64:
+        p64 = W.problem(W.CONFIG_B, precision=64, realizations=1)
+        k64 = max(args.steps, 200)
+        e64, _, info64, ok64 = time_plan(setd, p64, k64, args.warmup, profile=False)
+        v64 = float(info64.site_updates_per_step) * k64 / e64
+        line["fp64_plain"] = {"workload": "Model B 512x512, SETD2, complex128, 1 realization",
+                              "value": v64, "ms_per_step": 1e3 * e64 / k64, "ok": bool(ok64)}
+        line["fp32_batched_over_fp64_plain"] = value / v64
+
+    if args.serving_jobs > 0 and hasattr(setd, "Server"):
+        line["serving"] = serving_run(setd, W, args.serving_jobs, seed=2024)
+
+    if not args.no_cpu:
+        from oracle import oracle as O
+        R_cpu, steps_cpu = 8, 100
+        o = O.Sim(p, r_first=0, r_count=R_cpu)
+        t0 = time.perf_counter()
+        o.step(steps_cpu)
+        dt = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+        line["cpu_baseline"] = {
+            "value": 512 * 512 * R_cpu * steps_cpu / dt, "unit": "site-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "Model B 512x512 SETD2 FP64 oracle, %d realizations x %d steps (%.1f s)" % (R_cpu, steps_cpu, dt),
+        }
+
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

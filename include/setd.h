@@ -119,6 +119,8 @@ typedef struct {
     int passes_per_step;      /* kernel launches per time step                     */
     double alg_bytes_per_step;/* HBM bytes one step must move (all realizations)   */
     double site_updates_per_step; /* prod n[i] * realizations                      */
+    double pass_bytes[4];     /* HBM bytes each kernel launch of a step must move,
+                                 in launch order (unused entries 0)                */
 } setd_plan_info_t;
 
 typedef struct setd_plan setd_plan;
@@ -187,6 +189,15 @@ setd_status setd_get_history(setd_plan* plan, int realization, double* host_out,
 /* Set the step index n of every realization (checkpoint restart); the next
    step draws noise for step n. */
 setd_status setd_set_step(setd_plan* plan, int64_t step);
+
+/* Kernel timing: while enabled, setd_step records a pair of HIP events on
+   the bound stream around every pass launch. */
+setd_status setd_profile(setd_plan* plan, int enable);
+
+/* Synchronise and return, per pass of a step in launch order, the summed
+   duration in milliseconds and the number of launches timed since the last
+   read: out = [ms_0, count_0, ms_1, count_1, ...]; resets the sums. */
+setd_status setd_profile_read(setd_plan* plan, double* out, size_t cap, size_t* len);
 
 /* Release a plan (not the caller's device memory or stream). */
 setd_status setd_plan_destroy(setd_plan* plan);

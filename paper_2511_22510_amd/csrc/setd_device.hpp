@@ -1,12 +1,13 @@
 // setd_device.hpp -- device building blocks of the gfx950 SETD path.
 //
 //  * cx<T>: complex numbers in float or double.
-//  * fft_line<T, N, SIGN>: one length-N line transform held by N/8 threads,
-//    8 values per thread.  Stockham autosort stages (radix 2/4 first, then
-//    radix 8) with the values exchanged through LDS between stages.  Thread t
-//    holds elements t + q N/8 (q = 0..7) on entry and output bins t + q N/8 on
-//    exit, so the first stage reads and the last stage writes in the layout in
-//    which lines are loaded from and stored to global memory.
+//  * fft_line<T, N, SIGN, PAD>: one length-N line transform held by N/8
+//    threads, 8 values per thread.  Stockham autosort stages (radix 2/4 first,
+//    then radix 8) with the values exchanged through LDS between stages.
+//    Thread t holds elements t + q N/8 (q = 0..7) on entry and output bins
+//    t + q N/8 on exit, so the first stage reads and the last stage writes in
+//    the layout in which lines are loaded from and stored to global memory.
+//    Each thread keeps one base twiddle per radix-8 stage in registers.
 //  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller normals
 //    for the Fourier-space noise of App. B.
 //  * phi1(x) = (e^x - 1)/x and phi2(x) = (e^x - 1 - x)/x^2 in FP64 for the ETD
@@ -106,11 +107,51 @@ __device__ __forceinline__ void dft(cx<T>* u)
 // ---------------------------------------------------------------- line FFT
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// One Stockham stage of radix R after NS points have been combined.  Thread t
-// owns butterflies j = t + b N/8, b < 8/R, whose inputs are elements
-// j + r N/R, i.e. v[b + (8/R) r].  Twiddles come from tw[k] = exp(-2 pi i k/N).
-template <typename T, int N, int R, int NS, int SIGN>
-__device__ __forceinline__ void fft_stage(cx<T>* v, int t, const cx<T>* __restrict__ tw)
+// Stage plan of a length-N line: a radix R0 in {2, 4, 8} first, then radix 8.
+template <int N>
+struct FftPlan {
+    static constexpr int LG = ilog2(N);
+    static constexpr int R0 = (LG % 3 == 0) ? 8 : (1 << (LG % 3));
+    static constexpr int NST = (LG % 3 == 0) ? LG / 3 : LG / 3 + 1;
+};
+
+// LDS slot of element e with one pad slot after every 2^PAD elements
+// (PAD = 0: no padding).  Spreads the strided Stockham writes over the banks.
+template <int PAD>
+__device__ __forceinline__ int lds_slot(int e)
+{
+    if constexpr (PAD > 0) return e + (e >> PAD);
+    else return e;
+}
+
+template <int N, int PAD>
+constexpr int lds_len() { return PAD > 0 ? N + (N >> PAD) : N; }
+
+// Per-thread twiddles: for the radix-8 stage after NS combined points, thread
+// t multiplies its inputs r = 1..7 by w^r with w = exp(-2 pi i (t mod NS) / (8 NS)).
+// Only the base w of each stage is kept; its powers are formed by products.
+template <typename T, int N>
+struct LineTw {
+    cx<T> w[FftPlan<N>::NST > 1 ? FftPlan<N>::NST - 1 : 1];
+};
+
+// tw[k] = exp(-2 pi i k / N) for k < N (FP64-evaluated table in state precision)
+template <typename T, int N>
+__device__ __forceinline__ void line_tw_load(LineTw<T, N>& L, int t, const cx<T>* __restrict__ tw)
+{
+    constexpr int NST = FftPlan<N>::NST;
+    int ns = FftPlan<N>::R0;
+#pragma unroll
+    for (int s = 0; s + 1 < NST; s++) {
+        L.w[s] = tw[(t & (ns - 1)) * (N / (ns * 8))];
+        ns *= 8;
+    }
+}
+
+// First stage (no twiddles).  Thread t owns butterflies j = t + b N/8,
+// b < 8/R0, whose inputs are elements j + r N/R0, i.e. v[b + (8/R0) r].
+template <typename T, int N, int R, int SIGN>
+__device__ __forceinline__ void fft_stage0(cx<T>* v)
 {
     constexpr int NB = 8 / R;
 #pragma unroll
@@ -118,64 +159,91 @@ __device__ __forceinline__ void fft_stage(cx<T>* v, int t, const cx<T>* __restri
         cx<T> u[R];
 #pragma unroll
         for (int r = 0; r < R; r++) u[r] = v[b + NB * r];
-        if constexpr (NS > 1) {
-            const int j = t + b * (N / 8);
-            const int jm = j & (NS - 1);
-            constexpr int TS = N / (NS * R);
-#pragma unroll
-            for (int r = 1; r < R; r++) {
-                const cx<T> w = tw[jm * r * TS];
-                u[r] = (SIGN < 0) ? cmul(u[r], w) : cmulc(u[r], w);
-            }
-        }
         dft<R, SIGN>(u);
 #pragma unroll
         for (int r = 0; r < R; r++) v[b + NB * r] = u[r];
     }
 }
 
-// Write the outputs of a stage to their Stockham positions
-// (j / NS) NS R + j mod NS + r NS, then read the next stage's inputs back in
-// the natural layout t + q N/8.  lds[e * stride] holds element e of the line.
-template <typename T, int N, int R, int NS>
-__device__ __forceinline__ void fft_exchange(cx<T>* v, int t, cx<T>* lds, int stride)
+// Radix-8 stage with base twiddle w: input r is multiplied by w^r (forward)
+// or conj(w)^r (inverse) before the butterfly.
+template <typename T, int SIGN>
+__device__ __forceinline__ void fft_stage8(cx<T>* v, cx<T> w)
+{
+    const cx<T> w2 = cmul(w, w), w3 = cmul(w2, w), w4 = cmul(w2, w2);
+    const cx<T> w5 = cmul(w4, w), w6 = cmul(w3, w3), w7 = cmul(w4, w3);
+    if constexpr (SIGN < 0) {
+        v[1] = cmul(v[1], w); v[2] = cmul(v[2], w2); v[3] = cmul(v[3], w3); v[4] = cmul(v[4], w4);
+        v[5] = cmul(v[5], w5); v[6] = cmul(v[6], w6); v[7] = cmul(v[7], w7);
+    } else {
+        v[1] = cmulc(v[1], w); v[2] = cmulc(v[2], w2); v[3] = cmulc(v[3], w3); v[4] = cmulc(v[4], w4);
+        v[5] = cmulc(v[5], w5); v[6] = cmulc(v[6], w6); v[7] = cmulc(v[7], w7);
+    }
+    dft8<SIGN>(v);
+}
+
+// Write the outputs of a stage (radix R, NS points combined before it) to
+// their Stockham positions (j / NS) NS R + j mod NS + r NS, then read the next
+// stage's inputs back in the natural layout t + q N/8.  Element e of line k
+// lives at lds[k * lstep + lds_slot<PAD>(e) * stride]; the NL lines of a thread
+// share the two block barriers of the exchange.
+template <typename T, int N, int R, int NS, int PAD, int NL>
+__device__ __forceinline__ void fft_exchange(cx<T> (&v)[NL][8], int t, cx<T>* lds, int stride, int lstep)
 {
     constexpr int NB = 8 / R;
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
-        const int j = t + b * (N / 8);
-        const int base = (j / NS) * NS * R + (j & (NS - 1));
+    for (int k = 0; k < NL; k++) {
 #pragma unroll
-        for (int r = 0; r < R; r++) lds[(base + r * NS) * stride] = v[b + NB * r];
+        for (int b = 0; b < NB; b++) {
+            const int j = t + b * (N / 8);
+            const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+            for (int r = 0; r < R; r++) lds[k * lstep + lds_slot<PAD>(base + r * NS) * stride] = v[k][b + NB * r];
+        }
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; q++) v[q] = lds[(t + q * (N / 8)) * stride];
+    for (int k = 0; k < NL; k++) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[k][q] = lds[k * lstep + lds_slot<PAD>(t + q * (N / 8)) * stride];
+    }
 }
 
-// Full line transform X_k = sum_m x_m exp(SIGN 2 pi i k m / N), unscaled.
-// Every thread of the block must call it (it contains block barriers).
-template <typename T, int N, int SIGN>
-__device__ __forceinline__ void fft_line(cx<T>* v, int t, cx<T>* lds, int stride, const cx<T>* __restrict__ tw)
+// NL independent line transforms X_k = sum_m x_m exp(SIGN 2 pi i k m / N),
+// unscaled, held by the same threads (same t, same twiddles).  Every thread of
+// the block must call it (it contains block barriers).
+template <typename T, int N, int SIGN, int PAD, int NL>
+__device__ __forceinline__ void fft_lines(cx<T> (&v)[NL][8], int t, cx<T>* lds, int stride, int lstep,
+                                          const LineTw<T, N>& tw)
 {
     static_assert(N >= 8 && (N & (N - 1)) == 0, "power-of-two line length >= 8");
-    constexpr int LG = ilog2(N);
-    constexpr int R0 = (LG % 3 == 0) ? 8 : (1 << (LG % 3));
-    constexpr int NST = (LG % 3 == 0) ? LG / 3 : LG / 3 + 1;
-    fft_stage<T, N, R0, 1, SIGN>(v, t, tw);
+    constexpr int R0 = FftPlan<N>::R0;
+    constexpr int NST = FftPlan<N>::NST;
+#pragma unroll
+    for (int k = 0; k < NL; k++) fft_stage0<T, N, R0, SIGN>(v[k]);
     if constexpr (NST > 1) {
-        fft_exchange<T, N, R0, 1>(v, t, lds, stride);
-        fft_stage<T, N, 8, R0, SIGN>(v, t, tw);
+        fft_exchange<T, N, R0, 1, PAD, NL>(v, t, lds, stride, lstep);
+#pragma unroll
+        for (int k = 0; k < NL; k++) fft_stage8<T, SIGN>(v[k], tw.w[0]);
     }
     if constexpr (NST > 2) {
-        fft_exchange<T, N, 8, R0>(v, t, lds, stride);
-        fft_stage<T, N, 8, R0 * 8, SIGN>(v, t, tw);
+        fft_exchange<T, N, 8, R0, PAD, NL>(v, t, lds, stride, lstep);
+#pragma unroll
+        for (int k = 0; k < NL; k++) fft_stage8<T, SIGN>(v[k], tw.w[1]);
     }
     if constexpr (NST > 3) {
-        fft_exchange<T, N, 8, R0 * 8>(v, t, lds, stride);
-        fft_stage<T, N, 8, R0 * 64, SIGN>(v, t, tw);
+        fft_exchange<T, N, 8, R0 * 8, PAD, NL>(v, t, lds, stride, lstep);
+#pragma unroll
+        for (int k = 0; k < NL; k++) fft_stage8<T, SIGN>(v[k], tw.w[2]);
     }
+}
+
+// One line held by the calling thread group.
+template <typename T, int N, int SIGN, int PAD>
+__device__ __forceinline__ void fft_line(cx<T> (&v)[8], int t, cx<T>* lds, int stride, const LineTw<T, N>& tw)
+{
+    fft_lines<T, N, SIGN, PAD, 1>(reinterpret_cast<cx<T>(&)[1][8]>(v), t, lds, stride, 0, tw);
 }
 
 // ---------------------------------------------------------------- Philox
@@ -188,8 +256,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -199,19 +269,16 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
     }
 }
 
-// Two 53-bit integers from one Philox block with counter (e, n, r, tag).
-__device__ __forceinline__ void philox_m53(uint64_t seed, uint32_t e, uint32_t n, uint32_t r, uint32_t tag,
-                                           uint64_t& m1, uint64_t& m2)
+// Box-Muller normals from one Philox block with counter (e, n, r, tag): the
+// word pairs give two 53-bit integers m = x_a 2^21 + (x_b >> 11) and the
+// uniforms u = (m + 1/2) 2^-53 in (0, 1).
+__device__ __forceinline__ void normal_pair(uint64_t seed, uint32_t e, uint32_t n, uint32_t r, uint32_t tag,
+                                            double& z1, double& z2)
 {
     uint32_t c0 = e, c1 = n, c2 = r, c3 = tag;
     philox4x32_10(c0, c1, c2, c3, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
-    m1 = ((uint64_t)c0 << 21) | (uint64_t)(c1 >> 11);
-    m2 = ((uint64_t)c2 << 21) | (uint64_t)(c3 >> 11);
-}
-
-// Box-Muller on u = (m + 1/2) 2^-53 in (0, 1).
-__device__ __forceinline__ void box_muller(uint64_t m1, uint64_t m2, double& z1, double& z2)
-{
+    const uint64_t m1 = ((uint64_t)c0 << 21) | (uint64_t)(c1 >> 11);
+    const uint64_t m2 = ((uint64_t)c2 << 21) | (uint64_t)(c3 >> 11);
     const double u1 = ((double)m1 + 0.5) * 0x1p-53;
     const double u2 = ((double)m2 + 0.5) * 0x1p-53;
     const double rad = sqrt(-2.0 * log(u1));
@@ -221,31 +288,33 @@ __device__ __forceinline__ void box_muller(uint64_t m1, uint64_t m2, double& z1,
     z2 = rad * s;
 }
 
-__device__ __forceinline__ void box_muller(uint64_t m1, uint64_t m2, float& z1, float& z2)
-{
-    // ln u1: for u1 > 1/2 take log1p of the exactly formed -(1 - u1)
-    float lg;
-    if (m1 >= (1ull << 52)) {
-        const double om = ((double)((1ull << 53) - m1) - 0.5) * 0x1p-53;
-        lg = log1pf(-(float)om);
-    } else {
-        lg = logf((float)(((double)m1 + 0.5) * 0x1p-53));
-    }
-    const float rad = sqrtf(-2.0f * lg);
-    const float u2 = (float)(((double)m2 + 0.5) * 0x1p-53);
-    float s, c;
-    sincospif(2.0f * u2, &s, &c);
-    z1 = rad * c;
-    z2 = rad * s;
-}
-
-template <typename T>
+// Single precision: the same uniforms rounded to float, formed without FP64
+// arithmetic, and the transcendental functions of the hardware (base-2
+// logarithm, square root, sine and cosine of 2 pi x).  For u1 >= 1/2 the
+// logarithm is taken of the exactly formed 1 - u1, by its series
+// -om (1 + om/2 + om^2/3 + ...) when om = 1 - u1 < 1/64.
 __device__ __forceinline__ void normal_pair(uint64_t seed, uint32_t e, uint32_t n, uint32_t r, uint32_t tag,
-                                            T& z1, T& z2)
+                                            float& z1, float& z2)
 {
-    uint64_t m1, m2;
-    philox_m53(seed, e, n, r, tag, m1, m2);
-    box_muller(m1, m2, z1, z2);
+    uint32_t c0 = e, c1 = n, c2 = r, c3 = tag;
+    philox4x32_10(c0, c1, c2, c3, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+    const float ln2 = 0.69314718055994530942f;
+    float lg;
+    if (c0 >= 0x80000000u) {
+        const float om = fmaf((float)(0xffffffffu - c0), 0x1p-32f, ((float)(0x1fffffu - (c1 >> 11)) + 0.5f) * 0x1p-53f);
+        if (om < 0.015625f) {
+            const float p = fmaf(om, fmaf(om, fmaf(om, fmaf(om, 1.0f / 6.0f, 0.2f), 0.25f), 1.0f / 3.0f), 0.5f);
+            lg = -om * fmaf(om, p, 1.0f);
+        } else {
+            lg = __builtin_amdgcn_logf(1.0f - om) * ln2;
+        }
+    } else {
+        lg = __builtin_amdgcn_logf(fmaf((float)c0, 0x1p-32f, ((float)(c1 >> 11) + 0.5f) * 0x1p-53f)) * ln2;
+    }
+    const float rad = __builtin_amdgcn_sqrtf(-2.0f * lg);
+    const float u2 = fmaf((float)c2, 0x1p-32f, ((float)(c3 >> 11) + 0.5f) * 0x1p-53f);
+    z1 = rad * __builtin_amdgcn_cosf(u2);
+    z2 = rad * __builtin_amdgcn_sinf(u2);
 }
 
 // ---------------------------------------------------------------- phi functions (FP64)

@@ -77,9 +77,11 @@ __device__ __forceinline__ Coef<T> load_coef(const Item& it, int key)
     return r;
 }
 
+// key of a mode in a shell-indexed table: |a|^2 (equal dk on every axis) or
+// the separable (|a0|, |a1|, |a2|) index
 __device__ __forceinline__ int coef_key(const Item& it, int a0, int a1, int a2)
 {
-    if (it.iso) return a0 * a0 + a1 * a1 + a2 * a2;
+    if (it.coef_mode == COEF_ISO) return a0 * a0 + a1 * a1 + a2 * a2;
     return (abs(a0) * it.keydim[1] + abs(a1)) * it.keydim[2] + abs(a2);
 }
 
@@ -99,33 +101,36 @@ __device__ __forceinline__ cx<T> nl_pref(const Item& it, T k2)
 
 // ---------------------------------------------------------------- noise (App. B)
 // Unit noise eta_a of the stored mode at FFT positions (j0, j1, jl) for step n.
+// Complex modes draw (z1 + i z2)/sqrt2 at their own linear index e; on the
+// a_d in {0, N_d/2} planes of a real field a self-conjugate mode takes z1 and a
+// conjugate pair draws once at the smaller of the two indices, the partner
+// taking the conjugate.  One Philox evaluation per mode.
 template <typename T>
 __device__ __forceinline__ cx<T> noise_eta(const Geo& g, const Item& it, int j0, int j1, int jl, uint32_t n)
 {
     const T rs2 = T(0.70710678118654752440084436210484903928);
     const int last = g.ndim - 1;
-    const uint32_t e = (g.ndim == 3) ? ((uint32_t)j0 * (uint32_t)g.n[1] + (uint32_t)j1) * (uint32_t)g.nh_last + (uint32_t)jl
-                                     : (uint32_t)j0 * (uint32_t)g.nh_last + (uint32_t)jl;
+    const uint32_t nh = (uint32_t)g.nh_last;
+    const uint32_t e = (g.ndim == 3) ? ((uint32_t)j0 * (uint32_t)g.n[1] + (uint32_t)j1) * nh + (uint32_t)jl
+                                     : (uint32_t)j0 * nh + (uint32_t)jl;
+    uint32_t ectr = e;
+    int kind = 0;   // 0: (z1 + i z2)/sqrt2, 1: z1, 2: (z1 - i z2)/sqrt2 drawn at the partner
+    if (!g.cplx && !(jl > 0 && 2 * jl < g.n[last])) {
+        const int p0 = j0 ? g.n[0] - j0 : 0;
+        const int p1 = (g.ndim == 3 && j1) ? g.n[1] - j1 : 0;
+        const uint32_t ep = (g.ndim == 3) ? ((uint32_t)p0 * (uint32_t)g.n[1] + (uint32_t)p1) * nh + (uint32_t)jl
+                                          : (uint32_t)p0 * nh + (uint32_t)jl;
+        if (ep == e) {
+            kind = 1;
+        } else if (ep < e) {
+            kind = 2;
+            ectr = ep;
+        }
+    }
     T z1, z2;
-    if (g.cplx || (jl > 0 && 2 * jl < g.n[last])) {
-        normal_pair<T>(it.seed, e, n, it.r, 0u, z1, z2);
-        return {rs2 * z1, rs2 * z2};
-    }
-    // a_d in {0, N_d/2}: the conjugate partner -a lies on the same plane
-    const int p0 = j0 ? g.n[0] - j0 : 0;
-    const int p1 = (g.ndim == 3 && j1) ? g.n[1] - j1 : 0;
-    const uint32_t ep = (g.ndim == 3) ? ((uint32_t)p0 * (uint32_t)g.n[1] + (uint32_t)p1) * (uint32_t)g.nh_last + (uint32_t)jl
-                                      : (uint32_t)p0 * (uint32_t)g.nh_last + (uint32_t)jl;
-    if (ep == e) {
-        normal_pair<T>(it.seed, e, n, it.r, 0u, z1, z2);
-        return {z1, T(0)};
-    }
-    if (e < ep) {
-        normal_pair<T>(it.seed, e, n, it.r, 0u, z1, z2);
-        return {rs2 * z1, rs2 * z2};
-    }
-    normal_pair<T>(it.seed, ep, n, it.r, 0u, z1, z2);
-    return {rs2 * z1, -rs2 * z2};
+    normal_pair(it.seed, ectr, n, it.r, 0u, z1, z2);
+    if (kind == 1) return {z1, T(0)};
+    return {rs2 * z1, (kind == 2) ? -rs2 * z2 : rs2 * z2};
 }
 
 // ---------------------------------------------------------------- launch arguments
@@ -141,8 +146,9 @@ struct RowArgs {
 struct AxisArgs {
     Geo g;
     const Item* items;
-    int ntiles;  // column tiles across the padded last axis
-    int mode;    // axis-0 pass: MODE_STEP / MODE_IC / MODE_SYNC; axis-1 pass: +1 inverse, -1 forward
+    int ntiles;    // column tiles across the padded last axis
+    int per_item;  // blocks per realization
+    int mode;      // axis-0 pass: MODE_STEP / MODE_IC / MODE_SYNC; axis-1 pass: +1 inverse, -1 forward
     int sub;
 };
 
@@ -156,15 +162,25 @@ struct LinArgs {
 template <typename T>
 __device__ __forceinline__ const cx<T>* twid(const void* p) { return reinterpret_cast<const cx<T>*>(p); }
 
+// Workgroups are dealt round-robin to the 8 XCDs.  Give every XCD a contiguous
+// range of logical blocks, so that neighbouring column tiles (which can share
+// 128-byte lines) meet in the same L2.
+__device__ __forceinline__ unsigned xcd_logical(unsigned L, unsigned G)
+{
+    if (G % 8u != 0u) return L;
+    return (L % 8u) * (G / 8u) + L / 8u;
+}
+
 // ---------------------------------------------------------------- row pass, real field
 // Two real rows a, b travel as one complex line z = a + i b: the inverse uses
 // Z_k = A_k + i B_k (k <= N/2) and conj(A_{N-k}) + i conj(B_{N-k}) above; the
 // forward splits Z back into A_k = (Z_k + conj Z_{N-k})/2 and
 // B_k = (Z_k - conj Z_{N-k})/(2i).  Block: lpw row pairs x N/8 threads.
-template <typename T, int N>
+// KIND: 0 = phi^3 (Model A/B) step, 1 = KPZ step, 2 = initial condition
+template <typename T, int N, int PAD, int KIND>
 __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
 {
-    const Item& it = a.items[blockIdx.y];
+    const Item it = a.items[blockIdx.y];
     if (a.sub >= it.steps) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -173,18 +189,19 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
     const int l = tid / TPL, t = tid - l * TPL;
     const int pair = blockIdx.x * a.lpw + l;
     const bool valid = 2 * pair < a.nrows;
-    cx<T>* L = lds + l * N;
+    cx<T>* L = lds + l * lds_len<N, PAD>();
     const Geo& g = a.g;
     const int last = g.ndim - 1;
-    const cx<T>* tw = twid<T>(last == 1 ? it.tw1 : it.tw2);
+    LineTw<T, N> tw;
+    line_tw_load(tw, t, twid<T>(last == 1 ? it.tw1 : it.tw2));
     const int pitch = g.pitch;
     const int K = g.kp[last];
-    cx<T>* buf = reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big);
+    cx<T>* __restrict__ buf = reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big);
     const size_t r0 = (size_t)(2 * pair) * pitch, r1 = r0 + pitch;
     const T inv = (T)it.inv_vol;
     cx<T> v[8];
 
-    if (a.mode == MODE_IC) {
+    if constexpr (KIND == 2) {
         // i.i.d. N(0, sigma^2) per site, Philox counter (site, 0, r, 1)
         const T sig = (T)it.ic_sigma;
 #pragma unroll
@@ -194,46 +211,55 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
             if (valid) {
                 T za, zb, zc, zd;
                 const uint32_t s0 = (uint32_t)(2 * pair) * (uint32_t)N + (uint32_t)n;
-                normal_pair<T>(it.seed, s0, 0u, it.r, 1u, za, zb);
-                normal_pair<T>(it.seed, s0 + (uint32_t)N, 0u, it.r, 1u, zc, zd);
+                normal_pair(it.seed, s0, 0u, it.r, 1u, za, zb);
+                normal_pair(it.seed, s0 + (uint32_t)N, 0u, it.r, 1u, zc, zd);
                 v[q] = {sig * za, sig * zc};
             }
         }
-    } else if (it.nl == NL_KPZ) {
+    } else if constexpr (KIND == 1) {
         // |grad h|^2 with d0 h = IFFT[i k0 h] (from pre1) and d1 h = IFFT[i k1 h]
-        const cx<T>* buf2 = reinterpret_cast<const cx<T>*>(it.pre1);
+        const cx<T>* __restrict__ buf2 = reinterpret_cast<const cx<T>*>(it.pre1);
         const T dkl = (T)it.dk[last];
         T gsq[2][8];
+        cx<T> A[2][8], X[2][8];
 #pragma unroll
         for (int s = 0; s < 2; s++) {
             const size_t rr = s ? r1 : r0;
 #pragma unroll
             for (int q = 0; q < 8; q++) {
                 const int k = t + q * TPL;
+                const int m = (k <= K) ? k : N - k;
+                A[s][q] = czero<T>();
+                X[s][q] = czero<T>();
+                if (valid && (k <= K || k >= N - K)) {
+                    A[s][q] = buf2[rr + m];
+                    X[s][q] = buf[rr + m];
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int k = t + q * TPL;
                 cx<T> z = czero<T>();
-                if (valid) {
-                    if (k <= K) {
-                        cx<T> A = buf2[rr + k];
-                        const cx<T> X = buf[rr + k];
-                        const T kk = (2 * k == N) ? T(0) : dkl * (T)k;
-                        cx<T> B = {-kk * X.y, kk * X.x};
-                        if (k == 0 || 2 * k == N) {
-                            A.y = T(0);
-                            B.y = T(0);
-                        }
-                        z = {A.x - B.y, A.y + B.x};
-                    } else if (k >= N - K) {
-                        const int m = N - k;
-                        const cx<T> A = buf2[rr + m];
-                        const cx<T> X = buf[rr + m];
-                        const T kk = dkl * (T)m;
-                        const cx<T> B = {-kk * X.y, kk * X.x};
-                        z = {A.x + B.y, B.x - A.y};
+                if (k <= K) {
+                    cx<T> Aq = A[s][q];
+                    const T kk = (2 * k == N) ? T(0) : dkl * (T)k;
+                    cx<T> B = {-kk * X[s][q].y, kk * X[s][q].x};
+                    if (k == 0 || 2 * k == N) {
+                        Aq.y = T(0);
+                        B.y = T(0);
                     }
+                    z = {Aq.x - B.y, Aq.y + B.x};
+                } else if (k >= N - K) {
+                    const T kk = dkl * (T)(N - k);
+                    const cx<T> B = {-kk * X[s][q].y, kk * X[s][q].x};
+                    z = {A[s][q].x + B.y, B.x - A[s][q].y};
                 }
                 v[q] = z;
             }
-            fft_line<T, N, +1>(v, t, L, 1, tw);
+            fft_line<T, N, +1, PAD>(v, t, L, 1, tw);
 #pragma unroll
             for (int q = 0; q < 8; q++) {
                 const T x = v[q].x * inv, y = v[q].y * inv;
@@ -262,7 +288,7 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
             }
             v[q] = z;
         }
-        fft_line<T, N, +1>(v, t, L, 1, tw);
+        fft_line<T, N, +1, PAD>(v, t, L, 1, tw);
         // phi^3 in real space (Model A and B)
 #pragma unroll
         for (int q = 0; q < 8; q++) {
@@ -271,16 +297,16 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
         }
     }
 
-    fft_line<T, N, -1>(v, t, L, 1, tw);
+    fft_line<T, N, -1, PAD>(v, t, L, 1, tw);
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; q++) L[t + q * TPL] = v[q];
+    for (int q = 0; q < 8; q++) L[lds_slot<PAD>(t + q * TPL)] = v[q];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 8; q++) {
         const int k = t + q * TPL;
         if (valid && k <= K) {
-            const cx<T> Zk = L[k], Zm = L[(N - k) & (N - 1)];
+            const cx<T> Zk = L[lds_slot<PAD>(k)], Zm = L[lds_slot<PAD>((N - k) & (N - 1))];
             buf[r0 + k] = {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y - Zm.y)};
             buf[r1 + k] = {T(0.5) * (Zk.y + Zm.y), T(0.5) * (Zm.x - Zk.x)};
         }
@@ -288,10 +314,10 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
 }
 
 // ---------------------------------------------------------------- row pass, complex field
-template <typename T, int N>
+template <typename T, int N, int PAD, bool IC>
 __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
 {
-    const Item& it = a.items[blockIdx.y];
+    const Item it = a.items[blockIdx.y];
     if (a.sub >= it.steps) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -300,15 +326,16 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
     const int l = tid / TPL, t = tid - l * TPL;
     const int line = blockIdx.x * a.lpw + l;
     const bool valid = line < a.nrows;
-    cx<T>* L = lds + l * N;
+    cx<T>* L = lds + l * lds_len<N, PAD>();
     const Geo& g = a.g;
     const int last = g.ndim - 1;
-    const cx<T>* tw = twid<T>(last == 1 ? it.tw1 : it.tw2);
+    LineTw<T, N> tw;
+    line_tw_load(tw, t, twid<T>(last == 1 ? it.tw1 : it.tw2));
     const int kept = g.kept[last], kp = g.kp[last];
-    cx<T>* buf = reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big) + (size_t)line * g.pitch;
+    cx<T>* __restrict__ buf = reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big) + (size_t)line * g.pitch;
     const T inv = (T)it.inv_vol;
     cx<T> v[8];
-    if (a.mode == MODE_IC) {
+    if constexpr (IC) {
         const T sig = (T)it.ic_sigma;
 #pragma unroll
         for (int q = 0; q < 8; q++) {
@@ -316,7 +343,7 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
             if (valid) {
                 T z1, z2;
                 const uint32_t s = (uint32_t)line * (uint32_t)N + (uint32_t)(t + q * TPL);
-                normal_pair<T>(it.seed, s, 0u, it.r, 1u, z1, z2);
+                normal_pair(it.seed, s, 0u, it.r, 1u, z1, z2);
                 v[q] = {sig * z1, sig * z2};
             }
         }
@@ -326,7 +353,7 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
             const int i = stored_idx(t + q * TPL, N, kept, kp);
             v[q] = (valid && i >= 0) ? buf[i] : czero<T>();
         }
-        fft_line<T, N, +1>(v, t, L, 1, tw);
+        fft_line<T, N, +1, PAD>(v, t, L, 1, tw);
         // |A|^2 A in real space (CGL)
 #pragma unroll
         for (int q = 0; q < 8; q++) {
@@ -335,7 +362,7 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
             v[q] = {m * x, m * y};
         }
     }
-    fft_line<T, N, -1>(v, t, L, 1, tw);
+    fft_line<T, N, -1, PAD>(v, t, L, 1, tw);
 #pragma unroll
     for (int q = 0; q < 8; q++) {
         const int i = stored_idx(t + q * TPL, N, kept, kp);
@@ -345,54 +372,59 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
 
 // ---------------------------------------------------------------- axis-0 pass
 // A block owns TILE adjacent columns of the stored last axis (3D: at one
-// stored index of axis 1).  Thread (c, t) = (tid % TILE, tid / TILE) holds
-// elements t + q N0/8 of column c, so each row of the tile is one contiguous
-// 128-byte segment in every global access.
+// stored index of axis 1).  Each thread carries LPT columns: thread
+// (c0, t) = (tid % CW, tid / CW), CW = TILE / LPT, holds elements t + q N0/8 of
+// columns c0 + k CW, so the rows of a tile are contiguous segments in every
+// global access.
 //
 // MODE_STEP: pre -> forward FFT -> F_a = pref * FFT[N] -> ETD update with the
 //            noise of step n -> phi, F_{n-1} -> inverse FFT -> pre.
 // MODE_IC:   pre (forward-transformed initial field) -> forward FFT -> phi.
 // MODE_SYNC: phi -> inverse FFT -> pre.
-template <typename T, int N0, int TILE>
-__global__ void __launch_bounds__(1024) k_axis0(AxisArgs a)
+template <typename T, int N0, int TILE, int PAD, bool KPZ, int LPT>
+__global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
 {
-    const Item& it = a.items[blockIdx.y];
+    const unsigned lg = xcd_logical(blockIdx.x, gridDim.x);
+    const int item = (int)(lg / (unsigned)a.per_item);
+    const int blk = (int)(lg % (unsigned)a.per_item);
+    const Item it = a.items[item];
     if (a.sub >= it.steps) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Geo& g = a.g;
     constexpr int TPL = N0 / 8;
+    constexpr int CW = TILE / LPT;
+    constexpr int NTHR = CW * TPL;
     const int tid = threadIdx.x;
-    const int c = tid % TILE, t = tid / TILE;
-    const int tile = blockIdx.x % a.ntiles, i1 = blockIdx.x / a.ntiles;
-    const int col = tile * TILE + c;
+    const int c0 = tid % CW, t = tid / CW;
+    const int tile = blk % a.ntiles, i1 = blk / a.ntiles;
     const int last = g.ndim - 1;
-    const bool cv = col < g.kept[last];
+    const int keptl = g.kept[last];
     const size_t lstride = (g.ndim == 3) ? (size_t)g.kept[1] * g.pitch : (size_t)g.pitch;
-    const size_t poff = (size_t)i1 * g.pitch + col;
-    cx<T>* pre0 = reinterpret_cast<cx<T>*>(it.pre0);
-    cx<T>* phi = reinterpret_cast<cx<T>*>(it.phi);
-    cx<T>* prev = reinterpret_cast<cx<T>*>(it.prev);
-    const cx<T>* tw = twid<T>(it.tw0);
-    cx<T>* L = lds + c;
+    const size_t plane = (size_t)i1 * g.pitch + (size_t)tile * TILE;   // offset of the tile within a row
+    int col[LPT];
+    bool cv[LPT];
+#pragma unroll
+    for (int k = 0; k < LPT; k++) {
+        col[k] = c0 + k * CW;   // column within the tile
+        cv[k] = tile * TILE + col[k] < keptl;
+    }
+    cx<T>* __restrict__ pre0 = reinterpret_cast<cx<T>*>(it.pre0);
+    cx<T>* __restrict__ phi = reinterpret_cast<cx<T>*>(it.phi);
+    cx<T>* __restrict__ prev = reinterpret_cast<cx<T>*>(it.prev);
+    LineTw<T, N0> tw;
+    line_tw_load(tw, t, twid<T>(it.tw0));
+    cx<T>* L = lds + c0;   // line k at L + k * CW, element stride TILE
     const int kept0 = g.kept[0], kp0 = g.kp[0];
 
-    // FFT positions and signed indices of the other axes
     int j1 = 0, a1 = 0;
     if (g.ndim == 3) {
         j1 = fft_pos(i1, g.n[1], g.kept[1], g.kp[1]);
         a1 = sgn_idx(j1, g.n[1]);
     }
-    int jl = col, al = col;
-    if (g.cplx) {
-        jl = fft_pos(col, g.n[last], g.kept[last], g.kp[last]);
-        al = sgn_idx(jl, g.n[last]);
-    }
     const T dk0 = (T)it.dk[0], dk1 = (T)it.dk[1], dk2 = (T)it.dk[2];
-    const T k2rest = (g.ndim == 3) ? (dk1 * (T)a1) * (dk1 * (T)a1) + (dk2 * (T)al) * (dk2 * (T)al)
-                                   : (dk1 * (T)al) * (dk1 * (T)al);
 
-    cx<T> v[8];
+    cx<T> v[LPT][8];
     int64_t nstep = 0;
     int hp = 0;
     if (a.mode == MODE_STEP) {
@@ -401,67 +433,147 @@ __global__ void __launch_bounds__(1024) k_axis0(AxisArgs a)
     }
     if (a.mode == MODE_SYNC) {
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int i0 = stored_idx(t + q * TPL, N0, kept0, kp0);
-            v[q] = (cv && i0 >= 0) ? phi[(size_t)i0 * lstride + poff] : czero<T>();
+        for (int k = 0; k < LPT; k++) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int i0 = stored_idx(t + q * TPL, N0, kept0, kp0);
+                v[k][q] = (cv[k] && i0 >= 0) ? phi[(size_t)i0 * lstride + plane + col[k]] : czero<T>();
+            }
         }
     } else {
 #pragma unroll
-        for (int q = 0; q < 8; q++) v[q] = cv ? pre0[(size_t)(t + q * TPL) * lstride + poff] : czero<T>();
-        fft_line<T, N0, -1>(v, t, L, TILE, tw);
-        bool bad = false;
+        for (int k = 0; k < LPT; k++) {
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int j0 = t + q * TPL;
-            const int i0 = stored_idx(j0, N0, kept0, kp0);
-            if (cv && i0 >= 0) {
-                const size_t si = (size_t)i0 * lstride + poff;
+            for (int q = 0; q < 8; q++)
+                v[k][q] = cv[k] ? pre0[(size_t)(t + q * TPL) * lstride + plane + col[k]] : czero<T>();
+        }
+        fft_lines<T, N0, -1, PAD, LPT>(v, t, L, TILE, CW, tw);
+#pragma unroll
+        for (int k = 0; k < LPT; k++) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) L[k * CW + lds_slot<PAD>(t + q * TPL) * TILE] = v[k][q];
+        }
+        __syncthreads();
+        // Update the stored modes of the tile in a linear sweep, one mode per
+        // thread at a time, with the state, history and coefficients of the
+        // next mode fetched while the current one is computed.
+        const bool use_prev = (a.mode == MODE_STEP) && it.order == 2 && hp;
+        const int nst = kept0 * TILE;
+        struct Fetch {
+            cx<T> ph, pv;
+            Coef<T> cf;
+        };
+        auto last_pos = [&](int colm, int& jlm, int& alm) {
+            jlm = colm;
+            alm = colm;
+            if (g.cplx) {
+                jlm = fft_pos(colm, g.n[last], keptl, g.kp[last]);
+                alm = sgn_idx(jlm, g.n[last]);
+            }
+        };
+        auto fetch = [&](int m) {
+            Fetch f;
+            f.ph = czero<T>();
+            f.pv = czero<T>();
+            f.cf = Coef<T>{czero<T>(), czero<T>(), czero<T>(), T(0)};
+            if (m < nst && a.mode == MODE_STEP) {
+                const int i0 = m / TILE, cc = m % TILE;
+                const int colm = tile * TILE + cc;
+                if (colm < keptl) {
+                    const size_t si = (size_t)i0 * lstride + plane + cc;
+                    f.ph = phi[si];
+                    if (use_prev) f.pv = prev[si];
+                    int key;
+                    if (it.coef_mode == COEF_PER_MODE) {
+                        key = i0 * g.pitch + colm;
+                    } else {
+                        int jlm, alm;
+                        last_pos(colm, jlm, alm);
+                        const int a0 = sgn_idx(fft_pos(i0, N0, kept0, kp0), N0);
+                        key = (g.ndim == 3) ? coef_key(it, a0, a1, alm) : coef_key(it, a0, alm, 0);
+                    }
+                    f.cf = load_coef<T>(it, key);
+                }
+            }
+            return f;
+        };
+        bool bad = false;
+        Fetch cur = fetch(tid);
+        for (int m = tid; m < nst; m += NTHR) {
+            const Fetch nxt = fetch(m + NTHR);
+            const int i0 = m / TILE, cc = m % TILE;
+            const int colm = tile * TILE + cc;
+            const int j0 = fft_pos(i0, N0, kept0, kp0);
+            cx<T>* slot = lds + lds_slot<PAD>(j0) * TILE + cc;
+            if (colm < keptl) {
+                const size_t si = (size_t)i0 * lstride + plane + cc;
                 if (a.mode == MODE_IC) {
-                    phi[si] = v[q];
+                    phi[si] = *slot;
                 } else {
+                    int jlm, alm;
+                    last_pos(colm, jlm, alm);
                     const int a0 = sgn_idx(j0, N0);
-                    const T k2 = (dk0 * (T)a0) * (dk0 * (T)a0) + k2rest;
-                    const cx<T> F = cmul(nl_pref<T>(it, k2), v[q]);
-                    const int key = (g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0);
-                    const Coef<T> cf = load_coef<T>(it, key);
-                    const cx<T> eta = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)nstep);
-                    cx<T> nw = cmul(cf.E, phi[si]) + cmul(cf.wa, F) + cf.G * eta;
+                    const T kl = (g.ndim == 3) ? dk2 * (T)alm : dk1 * (T)alm;
+                    const T km = (g.ndim == 3) ? dk1 * (T)a1 : T(0);
+                    const T k2 = (dk0 * (T)a0) * (dk0 * (T)a0) + km * km + kl * kl;
+                    const cx<T> F = cmul(nl_pref<T>(it, k2), *slot);
+                    const cx<T> eta = noise_eta<T>(g, it, j0, j1, jlm, (uint32_t)nstep);
+                    cx<T> nw = cmul(cur.cf.E, cur.ph) + cmul(cur.cf.wa, F) + cur.cf.G * eta;
                     if (it.order == 2) {
-                        const cx<T> Fp = hp ? prev[si] : F;
-                        nw = nw + cmul(cf.wb, Fp);
+                        nw = nw + cmul(cur.cf.wb, use_prev ? cur.pv : F);
                         prev[si] = F;
                     }
                     bad |= !(isfinite(nw.x) && isfinite(nw.y));
                     phi[si] = nw;
-                    v[q] = nw;
+                    *slot = nw;
                 }
             } else {
-                v[q] = czero<T>();
+                *slot = czero<T>();
+            }
+            cur = nxt;
+        }
+        // the rows the 2/3 rule removes
+        for (int m = tid; m < (N0 - kept0) * TILE; m += NTHR) {
+            const int row = kp0 + 1 + m / TILE;
+            lds[lds_slot<PAD>(row) * TILE + (m % TILE)] = czero<T>();
+        }
+        // one flag update per block
+        if (__syncthreads_or(bad) && tid == 0) atomicOr(&it.ctrl->nonfinite, 1);
+#pragma unroll
+        for (int k = 0; k < LPT; k++) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) v[k][q] = L[k * CW + lds_slot<PAD>(t + q * TPL) * TILE];
+        }
+    }
+    cx<T> v2[KPZ ? LPT : 1][8];
+    if constexpr (KPZ) {
+#pragma unroll
+        for (int k = 0; k < LPT; k++) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int j0 = t + q * TPL;
+                const T kk = (2 * j0 == N0) ? T(0) : dk0 * (T)sgn_idx(j0, N0);
+                v2[k][q] = {-kk * v[k][q].y, kk * v[k][q].x};
             }
         }
-        if (bad) atomicOr(&it.ctrl->nonfinite, 1);
     }
-    cx<T> v2[8];
-    const bool kpz = (it.nl == NL_KPZ);
-    if (kpz) {
+    fft_lines<T, N0, +1, PAD, LPT>(v, t, L, TILE, CW, tw);
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int j0 = t + q * TPL;
-            const T kk = (2 * j0 == N0) ? T(0) : dk0 * (T)sgn_idx(j0, N0);
-            v2[q] = {-kk * v[q].y, kk * v[q].x};
+    for (int k = 0; k < LPT; k++) {
+        if (cv[k]) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) pre0[(size_t)(t + q * TPL) * lstride + plane + col[k]] = v[k][q];
         }
     }
-    fft_line<T, N0, +1>(v, t, L, TILE, tw);
-    if (cv) {
+    if constexpr (KPZ) {
+        cx<T>* __restrict__ pre1 = reinterpret_cast<cx<T>*>(it.pre1);
+        fft_lines<T, N0, +1, PAD, LPT>(v2, t, L, TILE, CW, tw);
 #pragma unroll
-        for (int q = 0; q < 8; q++) pre0[(size_t)(t + q * TPL) * lstride + poff] = v[q];
-    }
-    if (kpz) {
-        cx<T>* pre1 = reinterpret_cast<cx<T>*>(it.pre1);
-        fft_line<T, N0, +1>(v2, t, L, TILE, tw);
-        if (cv) {
+        for (int k = 0; k < LPT; k++) {
+            if (cv[k]) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) pre1[(size_t)(t + q * TPL) * lstride + poff] = v2[q];
+                for (int q = 0; q < 8; q++) pre1[(size_t)(t + q * TPL) * lstride + plane + col[k]] = v2[k][q];
+            }
         }
     }
     if (a.mode == MODE_STEP) {
@@ -470,7 +582,7 @@ __global__ void __launch_bounds__(1024) k_axis0(AxisArgs a)
         if (tid == 0) {
             __threadfence();
             const unsigned prior = atomicAdd(&it.ctrl->done, 1u);
-            if (prior == gridDim.x - 1) {
+            if (prior == (unsigned)a.per_item - 1u) {
                 atomicExch(&it.ctrl->done, 0u);
                 atomicExch(reinterpret_cast<unsigned long long*>(&it.ctrl->step), (unsigned long long)(nstep + 1));
                 atomicExch(&it.ctrl->have_prev, 1);
@@ -483,45 +595,67 @@ __global__ void __launch_bounds__(1024) k_axis0(AxisArgs a)
 // ---------------------------------------------------------------- axis-1 pass (3D)
 // mode +1: stored axis-1 entries of pre -> inverse FFT -> big
 // mode -1: big -> forward FFT -> stored axis-1 entries of pre
-template <typename T, int N1, int TILE>
-__global__ void __launch_bounds__(1024) k_axis1(AxisArgs a)
+template <typename T, int N1, int TILE, int PAD, int LPT>
+__global__ void __launch_bounds__(TILE / LPT * N1 / 8) k_axis1(AxisArgs a)
 {
-    const Item& it = a.items[blockIdx.y];
+    const unsigned lg = xcd_logical(blockIdx.x, gridDim.x);
+    const int item = (int)(lg / (unsigned)a.per_item);
+    const int blk = (int)(lg % (unsigned)a.per_item);
+    const Item it = a.items[item];
     if (a.sub >= it.steps) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Geo& g = a.g;
     constexpr int TPL = N1 / 8;
+    constexpr int CW = TILE / LPT;
     const int tid = threadIdx.x;
-    const int c = tid % TILE, t = tid / TILE;
-    const int tile = blockIdx.x % a.ntiles, n0 = blockIdx.x / a.ntiles;
-    const int col = tile * TILE + c;
-    const bool cv = col < g.kept[2];
+    const int c0 = tid % CW, t = tid / CW;
+    const int tile = blk % a.ntiles, n0 = blk / a.ntiles;
     const int pitch = g.pitch, kept1 = g.kept[1], kp1 = g.kp[1];
-    cx<T>* small = reinterpret_cast<cx<T>*>(it.pre0) + (size_t)n0 * kept1 * pitch + col;
-    cx<T>* big = reinterpret_cast<cx<T>*>(it.big) + (size_t)n0 * N1 * pitch + col;
-    const cx<T>* tw = twid<T>(it.tw1);
-    cx<T>* L = lds + c;
-    cx<T> v[8];
+    int col[LPT];
+    bool cv[LPT];
+#pragma unroll
+    for (int k = 0; k < LPT; k++) {
+        col[k] = tile * TILE + c0 + k * CW;
+        cv[k] = col[k] < g.kept[2];
+    }
+    cx<T>* __restrict__ small = reinterpret_cast<cx<T>*>(it.pre0) + (size_t)n0 * kept1 * pitch;
+    cx<T>* __restrict__ big = reinterpret_cast<cx<T>*>(it.big) + (size_t)n0 * N1 * pitch;
+    LineTw<T, N1> tw;
+    line_tw_load(tw, t, twid<T>(it.tw1));
+    cx<T>* L = lds + c0;
+    cx<T> v[LPT][8];
     if (a.mode > 0) {
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int i = stored_idx(t + q * TPL, N1, kept1, kp1);
-            v[q] = (cv && i >= 0) ? small[(size_t)i * pitch] : czero<T>();
-        }
-        fft_line<T, N1, +1>(v, t, L, TILE, tw);
-        if (cv) {
+        for (int k = 0; k < LPT; k++) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) big[(size_t)(t + q * TPL) * pitch] = v[q];
+            for (int q = 0; q < 8; q++) {
+                const int i = stored_idx(t + q * TPL, N1, kept1, kp1);
+                v[k][q] = (cv[k] && i >= 0) ? small[(size_t)i * pitch + col[k]] : czero<T>();
+            }
+        }
+        fft_lines<T, N1, +1, PAD, LPT>(v, t, L, TILE, CW, tw);
+#pragma unroll
+        for (int k = 0; k < LPT; k++) {
+            if (cv[k]) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) big[(size_t)(t + q * TPL) * pitch + col[k]] = v[k][q];
+            }
         }
     } else {
 #pragma unroll
-        for (int q = 0; q < 8; q++) v[q] = cv ? big[(size_t)(t + q * TPL) * pitch] : czero<T>();
-        fft_line<T, N1, -1>(v, t, L, TILE, tw);
+        for (int k = 0; k < LPT; k++) {
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int i = stored_idx(t + q * TPL, N1, kept1, kp1);
-            if (cv && i >= 0) small[(size_t)i * pitch] = v[q];
+            for (int q = 0; q < 8; q++) v[k][q] = cv[k] ? big[(size_t)(t + q * TPL) * pitch + col[k]] : czero<T>();
+        }
+        fft_lines<T, N1, -1, PAD, LPT>(v, t, L, TILE, CW, tw);
+#pragma unroll
+        for (int k = 0; k < LPT; k++) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int i = stored_idx(t + q * TPL, N1, kept1, kp1);
+                if (cv[k] && i >= 0) small[(size_t)i * pitch + col[k]] = v[k][q];
+            }
         }
     }
 }
@@ -530,12 +664,13 @@ __global__ void __launch_bounds__(1024) k_axis1(AxisArgs a)
 template <typename T>
 __global__ void __launch_bounds__(256) k_linear(LinArgs a)
 {
-    const Item& it = a.items[blockIdx.y];
+    const Item it = a.items[blockIdx.y];
     if (a.sub >= it.steps) return;
     const Geo& g = a.g;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nstep = it.ctrl->step;
     const int last = g.ndim - 1;
+    bool bad = false;
     if (idx < a.total) {
         const int col = idx % g.pitch;
         const int rest = idx / g.pitch;
@@ -554,16 +689,17 @@ __global__ void __launch_bounds__(256) k_linear(LinArgs a)
                 jl = fft_pos(col, g.n[last], g.kept[last], g.kp[last]);
                 al = sgn_idx(jl, g.n[last]);
             }
-            const int key = (g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0);
+            const int key = (it.coef_mode == COEF_PER_MODE) ? i0 * g.pitch + col
+                            : (g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0);
             const Coef<T> cf = load_coef<T>(it, key);
             const cx<T> eta = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)nstep);
             cx<T>* phi = reinterpret_cast<cx<T>*>(it.phi);
             const cx<T> nw = cmul(cf.E, phi[idx]) + cf.G * eta;
             phi[idx] = nw;
-            if (!(isfinite(nw.x) && isfinite(nw.y))) atomicOr(&it.ctrl->nonfinite, 1);
+            bad = !(isfinite(nw.x) && isfinite(nw.y));
         }
     }
-    __syncthreads();
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&it.ctrl->nonfinite, 1);
     if (threadIdx.x == 0) {
         __threadfence();
         const unsigned prior = atomicAdd(&it.ctrl->done, 1u);

@@ -14,7 +14,27 @@ __global__ void __launch_bounds__(256) k_coef(CoefArgs a)
     const int key = blockIdx.x * blockDim.x + threadIdx.x;
     if (key >= a.nkeys) return;
     double k2;
-    if (a.iso) {
+    if (a.mode == COEF_PER_MODE) {
+        // one entry per stored mode of a 2D lattice, in the state layout
+        const Geo& g = a.g;
+        const int i0 = key / g.pitch, col = key % g.pitch;
+        if (col >= g.kept[1]) {
+            const int w = a.cplx_table ? 8 : 4;
+            for (int i = 0; i < w; i++) {
+                a.out64[w * (size_t)key + i] = 0.0;
+                if (a.out32) reinterpret_cast<float*>(a.out32)[w * (size_t)key + i] = 0.0f;
+            }
+            return;
+        }
+        const int j0 = (i0 <= g.kp[0]) ? i0 : i0 + g.n[0] - g.kept[0];
+        const int a0 = (j0 < g.n[0] / 2) ? j0 : j0 - g.n[0];
+        int a1 = col;
+        if (g.cplx) {
+            const int j1 = (col <= g.kp[1]) ? col : col + g.n[1] - g.kept[1];
+            a1 = (j1 < g.n[1] / 2) ? j1 : j1 - g.n[1];
+        }
+        k2 = (a.dk[0] * a0) * (a.dk[0] * a0) + (a.dk[1] * a1) * (a.dk[1] * a1);
+    } else if (a.mode == COEF_ISO) {
         k2 = a.dk[0] * a.dk[0] * (double)key;
     } else {
         const int a2 = key % a.keydim[2];

@@ -8,24 +8,20 @@
 
 namespace setd {
 
-// column tile width of the strided passes: 128-byte row segments, at most
-// 1024 threads and 64 KiB of LDS per block
-template <typename T>
-constexpr int tile_for(int n)
-{
-    return sizeof(T) == 4 ? (n <= 512 ? 16 : 8) : (n <= 512 ? 8 : 4);
-}
-
 // padding of the stored last axis, in elements (128 bytes)
 template <typename T>
 constexpr int pitch_align() { return sizeof(T) == 4 ? 16 : 8; }
 
+// `var` selects a kernel variant (see setd_launch_impl.hpp); 0..3 for the
+// row pass, 0..3 for the axis passes
 template <typename T>
-hipError_t launch_row(const Geo& g, const Item* items, int nitems, int mode, int sub, hipStream_t s);
+hipError_t launch_row(const Geo& g, const Item* items, int nitems, int mode, int sub, int var, int kpz,
+                      hipStream_t s);
 template <typename T>
-hipError_t launch_axis0(const Geo& g, const Item* items, int nitems, int mode, int sub, hipStream_t s);
+hipError_t launch_axis0(const Geo& g, const Item* items, int nitems, int mode, int sub, int var, int kpz,
+                        hipStream_t s);
 template <typename T>
-hipError_t launch_axis1(const Geo& g, const Item* items, int nitems, int dir, int sub, hipStream_t s);
+hipError_t launch_axis1(const Geo& g, const Item* items, int nitems, int dir, int sub, int var, hipStream_t s);
 template <typename T>
 hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, hipStream_t s);
 template <typename T>

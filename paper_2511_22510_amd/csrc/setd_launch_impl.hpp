@@ -1,4 +1,11 @@
 // setd_launch_impl.hpp -- grid shapes and template dispatch of the SETD passes.
+//
+// Every pass exists in a few variants that the plan's autotuner chooses from:
+//   row pass : LDS padding (0 or one slot per 8) x line groups per block
+//              (one wavefront or 256 threads)
+//   axis pass: (column tile width, columns per thread) in
+//              {(tm, 2), (tm, 1), (tm, 4), (tm/2, 1)}, tm = tile_max, with LDS
+//              padding whenever the padded tile still fits 64 KiB
 #pragma once
 
 #include "setd_kernels.hpp"
@@ -6,8 +13,8 @@
 
 namespace setd {
 
-#define SETD_DISPATCH_N(N, CALL)                 \
-    switch (N) {                                 \
+#define SETD_DISPATCH_N(N, CALL)                         \
+    switch (N) {                                         \
     case 8: { constexpr int NN = 8; CALL; } break;       \
     case 16: { constexpr int NN = 16; CALL; } break;     \
     case 32: { constexpr int NN = 32; CALL; } break;     \
@@ -16,16 +23,15 @@ namespace setd {
     case 256: { constexpr int NN = 256; CALL; } break;   \
     case 512: { constexpr int NN = 512; CALL; } break;   \
     case 1024: { constexpr int NN = 1024; CALL; } break; \
-    default: return hipErrorInvalidValue;        \
+    default: return hipErrorInvalidValue;                \
     }
 
-template <typename T>
-hipError_t launch_row(const Geo& g, const Item* items, int nitems, int mode, int sub, hipStream_t s)
+template <typename T, int N, int PAD>
+static hipError_t launch_row_np(const Geo& g, const Item* items, int nitems, int mode, int sub, int big_block,
+                                bool kpz, hipStream_t s)
 {
-    const int last = g.ndim - 1;
-    const int N = g.n[last];
-    const int tpl = N / 8;
-    const int lpw = tpl >= 256 ? 1 : 256 / tpl;
+    constexpr int tpl = N / 8;
+    const int lpw = big_block ? (tpl >= 256 ? 1 : 256 / tpl) : (tpl >= 64 ? 1 : 64 / tpl);
     RowArgs a;
     a.g = g;
     a.items = items;
@@ -36,61 +42,94 @@ hipError_t launch_row(const Geo& g, const Item* items, int nitems, int mode, int
     const int lines = g.cplx ? a.nrows : a.nrows / 2;
     dim3 grid((lines + lpw - 1) / lpw, nitems);
     dim3 block(lpw * tpl);
-    const size_t lds = (size_t)lpw * N * 2 * sizeof(T);
+    const size_t lds = (size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T);
     if (g.cplx) {
-        SETD_DISPATCH_N(N, hipLaunchKernelGGL((k_row_cplx<T, NN>), grid, block, lds, s, a));
+        if (mode == MODE_IC) hipLaunchKernelGGL((k_row_cplx<T, N, PAD, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_row_cplx<T, N, PAD, false>), grid, block, lds, s, a);
+    } else if (mode == MODE_IC) {
+        hipLaunchKernelGGL((k_row_real<T, N, PAD, 2>), grid, block, lds, s, a);
+    } else if (kpz) {
+        hipLaunchKernelGGL((k_row_real<T, N, PAD, 1>), grid, block, lds, s, a);
     } else {
-        SETD_DISPATCH_N(N, hipLaunchKernelGGL((k_row_real<T, NN>), grid, block, lds, s, a));
+        hipLaunchKernelGGL((k_row_real<T, N, PAD, 0>), grid, block, lds, s, a);
     }
     return hipGetLastError();
 }
 
-template <typename T, int N>
-static hipError_t launch_axis0_n(const Geo& g, const Item* items, int nitems, int mode, int sub, hipStream_t s)
-{
-    constexpr int TILE = tile_for<T>(N);
-    AxisArgs a;
-    a.g = g;
-    a.items = items;
-    a.ntiles = g.pitch / TILE;
-    a.mode = mode;
-    a.sub = sub;
-    const int planes = (g.ndim == 3) ? g.kept[1] : 1;
-    dim3 grid(a.ntiles * planes, nitems);
-    dim3 block(TILE * (N / 8));
-    const size_t lds = (size_t)TILE * N * 2 * sizeof(T);
-    hipLaunchKernelGGL((k_axis0<T, N, TILE>), grid, block, lds, s, a);
-    return hipGetLastError();
-}
-
+// var: bit 0 = LDS padding, bit 1 = 256-thread blocks
 template <typename T>
-hipError_t launch_axis0(const Geo& g, const Item* items, int nitems, int mode, int sub, hipStream_t s)
+hipError_t launch_row(const Geo& g, const Item* items, int nitems, int mode, int sub, int var, int kpz,
+                      hipStream_t s)
 {
-    SETD_DISPATCH_N(g.n[0], return (launch_axis0_n<T, NN>(g, items, nitems, mode, sub, s)));
+    const int N = g.n[g.ndim - 1];
+    const int big = (var >> 1) & 1;
+    const bool kp = kpz && mode == MODE_STEP;
+    if (var & 1) {
+        SETD_DISPATCH_N(N, return (launch_row_np<T, NN, 3>(g, items, nitems, mode, sub, big, kp, s)));
+    } else {
+        SETD_DISPATCH_N(N, return (launch_row_np<T, NN, 0>(g, items, nitems, mode, sub, big, kp, s)));
+    }
     return hipSuccess;
 }
 
-template <typename T, int N>
-static hipError_t launch_axis1_n(const Geo& g, const Item* items, int nitems, int dir, int sub, hipStream_t s)
+template <typename T>
+constexpr int tile_max(int n)
 {
-    constexpr int TILE = tile_for<T>(N);
+    return sizeof(T) == 4 ? (n <= 512 ? 16 : 8) : (n <= 512 ? 8 : 4);
+}
+
+template <typename T, int N, int TILE>
+constexpr int tile_pad()
+{
+    return (size_t)TILE * lds_len<N, 3>() * 2 * sizeof(T) <= 65536 ? 3 : 0;
+}
+
+template <typename T, int N, int TILE, int LPT, bool AX0>
+static hipError_t launch_axis_nt(const Geo& g, const Item* items, int nitems, int mode, int sub, bool kpz,
+                                 hipStream_t s)
+{
+    constexpr int PAD = tile_pad<T, N, TILE>();
     AxisArgs a;
     a.g = g;
     a.items = items;
     a.ntiles = g.pitch / TILE;
-    a.mode = dir;
+    a.per_item = a.ntiles * (AX0 ? ((g.ndim == 3) ? g.kept[1] : 1) : g.n[0]);
+    a.mode = mode;
     a.sub = sub;
-    dim3 grid(a.ntiles * g.n[0], nitems);
-    dim3 block(TILE * (N / 8));
-    const size_t lds = (size_t)TILE * N * 2 * sizeof(T);
-    hipLaunchKernelGGL((k_axis1<T, N, TILE>), grid, block, lds, s, a);
+    dim3 grid(a.per_item * nitems);
+    dim3 block(TILE / LPT * (N / 8));
+    const size_t lds = (size_t)TILE * lds_len<N, PAD>() * 2 * sizeof(T);
+    if (AX0 && kpz) hipLaunchKernelGGL((k_axis0<T, N, TILE, PAD, true, LPT>), grid, block, lds, s, a);
+    else if (AX0) hipLaunchKernelGGL((k_axis0<T, N, TILE, PAD, false, LPT>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_axis1<T, N, TILE, PAD, LPT>), grid, block, lds, s, a);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_axis1(const Geo& g, const Item* items, int nitems, int dir, int sub, hipStream_t s)
+template <typename T, int N, bool AX0>
+static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int mode, int sub, int var,
+                                bool kpz, hipStream_t s)
 {
-    SETD_DISPATCH_N(g.n[1], return (launch_axis1_n<T, NN>(g, items, nitems, dir, sub, s)));
+    constexpr int TM = tile_max<T>(N);
+    switch (var) {
+    case 0: return launch_axis_nt<T, N, TM, 2, AX0>(g, items, nitems, mode, sub, kpz, s);
+    case 1: return launch_axis_nt<T, N, TM, 1, AX0>(g, items, nitems, mode, sub, kpz, s);
+    case 2: return launch_axis_nt<T, N, TM, 4, AX0>(g, items, nitems, mode, sub, kpz, s);
+    default: return launch_axis_nt<T, N, TM / 2, 1, AX0>(g, items, nitems, mode, sub, kpz, s);
+    }
+}
+
+template <typename T>
+hipError_t launch_axis0(const Geo& g, const Item* items, int nitems, int mode, int sub, int var, int kpz,
+                        hipStream_t s)
+{
+    SETD_DISPATCH_N(g.n[0], return (launch_axis_n<T, NN, true>(g, items, nitems, mode, sub, var, kpz != 0, s)));
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_axis1(const Geo& g, const Item* items, int nitems, int dir, int sub, int var, hipStream_t s)
+{
+    SETD_DISPATCH_N(g.n[1], return (launch_axis_n<T, NN, false>(g, items, nitems, dir, sub, var, false, s)));
     return hipSuccess;
 }
 
@@ -129,9 +168,9 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
 }
 
 #define SETD_INSTANTIATE(T)                                                                                     \
-    template hipError_t launch_row<T>(const Geo&, const Item*, int, int, int, hipStream_t);                     \
-    template hipError_t launch_axis0<T>(const Geo&, const Item*, int, int, int, hipStream_t);                   \
-    template hipError_t launch_axis1<T>(const Geo&, const Item*, int, int, int, hipStream_t);                   \
+    template hipError_t launch_row<T>(const Geo&, const Item*, int, int, int, int, int, hipStream_t);           \
+    template hipError_t launch_axis0<T>(const Geo&, const Item*, int, int, int, int, int, hipStream_t);         \
+    template hipError_t launch_axis1<T>(const Geo&, const Item*, int, int, int, int, hipStream_t);              \
     template hipError_t launch_linear<T>(const Geo&, const Item*, int, int, hipStream_t);                       \
     template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, hipStream_t);
 

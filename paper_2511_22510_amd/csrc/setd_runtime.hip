@@ -5,6 +5,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <new>
 
 #include "setd_launch.hpp"
@@ -133,12 +137,17 @@ setd_status Plan::init(const setd_desc& desc)
         if (d.n[i] != d.n[0]) iso = 0;
     int kmax[3] = {0, 0, 0};
     for (int i = 0; i < d.ndim; i++) kmax[i] = d.dealias ? (d.n[i] - 1) / 3 : d.n[i] / 2;
-    if (iso) {
+    if (d.ndim == 2) {
+        coef_mode = COEF_PER_MODE;   // the state layout: coalesced, shared by all realizations
+        keydim[0] = keydim[1] = keydim[2] = 1;
+    } else if (iso) {
+        coef_mode = COEF_ISO;
         long m = 0;
         for (int i = 0; i < d.ndim; i++) m += (long)kmax[i] * kmax[i];
         nkeys = (int)m + 1;
         keydim[0] = keydim[1] = keydim[2] = 1;
     } else {
+        coef_mode = COEF_SEPARABLE;
         for (int i = 0; i < 3; i++) keydim[i] = (i < d.ndim) ? kmax[i] + 1 : 1;
         nkeys = keydim[0] * keydim[1] * keydim[2];
     }
@@ -148,6 +157,7 @@ setd_status Plan::init(const setd_desc& desc)
     nbins = ceil_isqrt_host(msq) + 1;
 
     // sizes
+    if (coef_mode == COEF_PER_MODE) nkeys = g.kept[0] * g.pitch;
     const size_t k1 = (d.ndim == 3) ? (size_t)g.kept[1] : 1;
     S = (size_t)g.kept[0] * k1 * g.pitch;
     P = (size_t)g.n[0] * k1 * g.pitch;
@@ -188,68 +198,93 @@ int Plan::passes_per_step() const
     return d.ndim == 2 ? 2 : 4;
 }
 
-// HBM bytes a step must move with the stored (2/3-pruned) arrays, counted per
-// pass as one read and one write of what LDS cannot hold.
-double Plan::alg_bytes_per_step() const
+// HBM bytes each pass must move with the stored (2/3-pruned) arrays: one read
+// and one write of every array a pass cannot keep in LDS, at the unpadded
+// stored sizes.
+void Plan::pass_bytes(double* out) const
 {
+    for (int i = 0; i < 4; i++) out[i] = 0.0;
+    const double e = (double)elt * R;
     const double kl = (double)g.kept[g.ndim - 1];
     const double st = (double)kept_modes;                 // stored modes
     const double hist = (d.order == 2) ? 2.0 : 0.0;       // read + write F_{n-1}
-    double per;
     if (d.nl == NL_NONE) {
-        per = 2.0 * st;
-    } else if (d.ndim == 2) {
+        out[0] = 2.0 * st * e;
+        return;
+    }
+    if (d.ndim == 2) {
         const double pre = (double)g.n[0] * kl;
         const double npre = (d.nl == NL_KPZ) ? 2.0 : 1.0;
-        per = (npre + 1.0) * pre          // row pass: read pre (and pre1), write pre
-              + pre + npre * pre          // axis-0 pass: read pre, write pre (and pre1)
-              + (2.0 + hist) * st;        // state and history
-    } else {
-        const double small = (double)g.n[0] * g.kept[1] * kl;
-        const double bigv = (double)g.n[0] * g.n[1] * kl;
-        per = (small + bigv)              // axis-1 inverse
-              + 2.0 * bigv                // row pass
-              + (bigv + small)            // axis-1 forward
-              + 2.0 * small + (2.0 + hist) * st;
+        out[0] = (npre + 1.0) * pre * e;                        // row pass: read pre (and pre1), write pre
+        out[1] = ((1.0 + npre) * pre + (2.0 + hist) * st) * e;  // axis 0: pre in/out, state, history
+        return;
     }
-    return per * (double)elt * R;
+    const double small = (double)g.n[0] * g.kept[1] * kl;
+    const double bigv = (double)g.n[0] * g.n[1] * kl;
+    out[0] = (small + bigv) * e;                                // axis-1 inverse
+    out[1] = 2.0 * bigv * e;                                    // row pass
+    out[2] = (bigv + small) * e;                                // axis-1 forward
+    out[3] = (2.0 * small + (2.0 + hist) * st) * e;             // axis 0
+}
+
+double Plan::alg_bytes_per_step() const
+{
+    double b[4];
+    pass_bytes(b);
+    return b[0] + b[1] + b[2] + b[3];
 }
 
 template <typename T>
-static setd_status launch_step_t(const Plan& p, const Item* items_dev, int nitems, int sub, hipStream_t s)
+static setd_status launch_pass_t(const Plan& p, int i, const Item* items_dev, int nitems, int sub, hipStream_t s)
 {
     const Geo& g = p.g;
     if (p.d.nl == NL_NONE) {
         SETD_HIP((launch_linear<T>(g, items_dev, nitems, sub, s)));
         return SETD_OK;
     }
-    if (g.ndim == 3) SETD_HIP((launch_axis1<T>(g, items_dev, nitems, +1, sub, s)));
-    SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_STEP, sub, s)));
-    if (g.ndim == 3) SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -1, sub, s)));
-    SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_STEP, sub, s)));
+    if (g.ndim == 2) {
+        if (i == 0) SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.row, p.d.nl == NL_KPZ, s)));
+        else SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.ax0, p.d.nl == NL_KPZ, s)));
+        return SETD_OK;
+    }
+    switch (i) {
+    case 0: SETD_HIP((launch_axis1<T>(g, items_dev, nitems, +1, sub, p.tune.ax1, s))); break;
+    case 1: SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.row, p.d.nl == NL_KPZ, s))); break;
+    case 2: SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -1, sub, p.tune.ax1, s))); break;
+    default: SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.ax0, p.d.nl == NL_KPZ, s))); break;
+    }
     return SETD_OK;
+}
+
+setd_status Plan::launch_pass(int i, const Item* items_dev, int nitems, int sub, hipStream_t s) const
+{
+    return d.precision == 32 ? launch_pass_t<float>(*this, i, items_dev, nitems, sub, s)
+                             : launch_pass_t<double>(*this, i, items_dev, nitems, sub, s);
 }
 
 setd_status Plan::launch_step(const Item* items_dev, int nitems, int sub, hipStream_t s) const
 {
-    return d.precision == 32 ? launch_step_t<float>(*this, items_dev, nitems, sub, s)
-                             : launch_step_t<double>(*this, items_dev, nitems, sub, s);
+    for (int i = 0; i < passes_per_step(); i++) {
+        setd_status st = launch_pass(i, items_dev, nitems, sub, s);
+        if (st != SETD_OK) return st;
+    }
+    return SETD_OK;
 }
 
 template <typename T>
 static setd_status launch_ic_t(const Plan& p, const Item* items_dev, int nitems, hipStream_t s)
 {
     const Geo& g = p.g;
-    SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_IC, 0, s)));
-    if (g.ndim == 3) SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -1, 0, s)));
-    SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_IC, 0, s)));
+    SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_IC, 0, p.tune.row, 0, s)));
+    if (g.ndim == 3) SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -1, 0, p.tune.ax1, s)));
+    SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_IC, 0, p.tune.ax0, p.d.nl == NL_KPZ, s)));
     return SETD_OK;
 }
 
 template <typename T>
 static setd_status launch_sync_t(const Plan& p, const Item* items_dev, int nitems, hipStream_t s)
 {
-    SETD_HIP((launch_axis0<T>(p.g, items_dev, nitems, MODE_SYNC, 0, s)));
+    SETD_HIP((launch_axis0<T>(p.g, items_dev, nitems, MODE_SYNC, 0, p.tune.ax0, p.d.nl == NL_KPZ, s)));
     return SETD_OK;
 }
 
@@ -282,7 +317,7 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
         it.r = (uint32_t)r;
         it.nl = d.nl;
         it.order = d.order;
-        it.iso = iso;
+        it.coef_mode = coef_mode;
         it.coef_cplx = coef_cplx;
         it.steps = INT_MAX;
         for (int i = 0; i < 3; i++) {
@@ -302,7 +337,8 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
                                 reinterpret_cast<float*>(ws + lay.tw32[i]), s));
     CoefArgs ca{};
     ca.nkeys = nkeys;
-    ca.iso = iso;
+    ca.mode = coef_mode;
+    ca.g = g;
     ca.ndim = d.ndim;
     ca.order = d.order;
     ca.kpow = d.noise_kpow;
@@ -325,6 +361,14 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
 
     Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + lay.ctrl);
     SETD_HIP(launch_ctrl_init(ctrl, R, 0, s));
+    {
+        // variant choice runs real passes on zeroed buffers; everything below
+        // resets them again
+        SETD_HIP(launch_fill64(reinterpret_cast<double*>(ws + lay.phi), (int64_t)((lay.total - lay.phi) / 8), 0.0, s));
+        setd_status tst = autotune();
+        if (tst != SETD_OK) return tst;
+        SETD_HIP(launch_ctrl_init(ctrl, R, 0, s));
+    }
     SETD_HIP(launch_fill64(reinterpret_cast<double*>(ws + lay.skacc), 2 * nbins + 1, 0.0, s));
     // state buffers start at zero (all of them are multiples of 8 bytes)
     auto zero = [&](size_t off, size_t bytes) -> setd_status {
@@ -351,6 +395,119 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
     return SETD_OK;
 }
 
+// ---------------------------------------------------------------- autotuner
+// Variants are timed per pass with HIP events on the plan's own buffers and
+// the fastest kept.  Choices are cached per launch class and realization count
+// for the process, and in the text file named by SETD_TUNE_CACHE if set.
+// SETD_AUTOTUNE=0 keeps the default variants.
+static std::mutex g_tune_mu;
+static std::map<std::string, Tune> g_tune_cache;
+static bool g_tune_loaded = false;
+
+static std::string tune_key(const Plan& p)
+{
+    char buf[64];
+    snprintf(buf, sizeof buf, "|%d|%d", p.R, p.d.nl);
+    return class_key(p) + buf;
+}
+
+static void tune_cache_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("SETD_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    std::string key;
+    Tune t;
+    while (f >> key >> t.row >> t.ax0 >> t.ax1) g_tune_cache[key] = t;
+}
+
+static void tune_cache_store(const std::string& key, const Tune& t)
+{
+    g_tune_cache[key] = t;
+    const char* path = std::getenv("SETD_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << t.row << " " << t.ax0 << " " << t.ax1 << "\n";
+}
+
+setd_status Plan::autotune()
+{
+    // SETD_VARIANT="row,axis0,axis1" pins the variants (tests, reproducible timing)
+    if (const char* pin = std::getenv("SETD_VARIANT")) {
+        int r = 0, a0 = 0, a1 = 0;
+        if (sscanf(pin, "%d,%d,%d", &r, &a0, &a1) == 3 && r >= 0 && r < 4 && a0 >= 0 && a0 < 4 && a1 >= 0 && a1 < 4) {
+            tune.row = r;
+            tune.ax0 = a0;
+            tune.ax1 = a1;
+            return SETD_OK;
+        }
+        return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row in 0..3 and axes in 0..3");
+    }
+    const char* env = std::getenv("SETD_AUTOTUNE");
+    if (env && env[0] == '0') return SETD_OK;
+    if (d.nl == NL_NONE) return SETD_OK;
+    const std::string key = tune_key(*this);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_load();
+        auto itc = g_tune_cache.find(key);
+        if (itc != g_tune_cache.end()) {
+            tune = itc->second;
+            return SETD_OK;
+        }
+    }
+    const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
+    hipEvent_t e0, e1;
+    SETD_HIP(hipEventCreate(&e0));
+    SETD_HIP(hipEventCreate(&e1));
+    // pass index in launch order for each tunable knob
+    const int row_pass = (d.ndim == 2) ? 0 : 1;
+    const int ax0_pass = (d.ndim == 2) ? 1 : 3;
+    struct Knob { int* var; int nvar; int pass; int pass2; };
+    Knob knobs[3] = {{&tune.row, 4, row_pass, -1}, {&tune.ax0, 4, ax0_pass, -1}, {&tune.ax1, 4, 0, 2}};
+    const int nknobs = (d.ndim == 3) ? 3 : 2;
+    setd_status st = SETD_OK;
+    for (int k = 0; k < nknobs && st == SETD_OK; k++) {
+        Knob& kb = knobs[k];
+        float best = 1e30f;
+        int best_v = 0;
+        for (int v = 0; v < kb.nvar && st == SETD_OK; v++) {
+            *kb.var = v;
+            auto run = [&]() -> setd_status {
+                setd_status s1 = launch_pass(kb.pass, items_dev, R, 0, stream);
+                if (s1 == SETD_OK && kb.pass2 >= 0) s1 = launch_pass(kb.pass2, items_dev, R, 0, stream);
+                return s1;
+            };
+            if ((st = run()) != SETD_OK) break;   // warm-up
+            if (hipEventRecord(e0, stream) != hipSuccess) { st = fail(SETD_E_DEVICE, "event record failed"); break; }
+            for (int rep = 0; rep < 3 && st == SETD_OK; rep++) st = run();
+            if (st != SETD_OK) break;
+            if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = fail(SETD_E_DEVICE, "event wait failed");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (const char* vb = std::getenv("SETD_TUNE_VERBOSE"))
+                if (vb[0] == '1') fprintf(stderr, "setd tune %s knob %d variant %d: %.1f us\n", key.c_str(), k, v, ms * 1e3f / 3);
+            if (ms < best) {
+                best = ms;
+                best_v = v;
+            }
+        }
+        *kb.var = best_v;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SETD_OK) return st;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_store(key, tune);
+    return SETD_OK;
+}
+
+
 setd_status Plan::step(int64_t n)
 {
     if (!bound) return fail(SETD_E_STATE, "plan not bound");
@@ -358,12 +515,51 @@ setd_status Plan::step(int64_t n)
     if (step_host + n >= (int64_t)1 << 32) return fail(SETD_E_INVAL, "step index would exceed 2^32");
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
     for (int64_t i = 0; i < n; i++) {
-        setd_status st = launch_step(items_dev, R, 0, stream);
-        if (st != SETD_OK) return st;
+        if (!profiling) {
+            setd_status st = launch_step(items_dev, R, 0, stream);
+            if (st != SETD_OK) return st;
+            continue;
+        }
+        for (int k = 0; k < passes_per_step(); k++) {
+            EvPair ev{k, nullptr, nullptr};
+            SETD_HIP(hipEventCreate(&ev.a));
+            SETD_HIP(hipEventCreate(&ev.b));
+            events.push_back(ev);
+            SETD_HIP(hipEventRecord(ev.a, stream));
+            setd_status st = launch_pass(k, items_dev, R, 0, stream);
+            if (st != SETD_OK) return st;
+            SETD_HIP(hipEventRecord(ev.b, stream));
+        }
     }
     step_host += n;
     return SETD_OK;
 }
+
+setd_status Plan::profile_read(double* out, size_t cap, size_t* len)
+{
+    if (!out || !len) return fail(SETD_E_INVAL, "null output");
+    const int np = passes_per_step();
+    if (cap < (size_t)2 * np) return fail(SETD_E_INVAL, "output needs %d doubles", 2 * np);
+    if (bound) SETD_HIP(hipStreamSynchronize(stream));
+    for (EvPair& ev : events) {
+        float ms = 0.0f;
+        SETD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+        prof_ms[ev.pass] += ms;
+        prof_cnt[ev.pass] += 1.0;
+        (void)hipEventDestroy(ev.a);
+        (void)hipEventDestroy(ev.b);
+    }
+    events.clear();
+    for (int k = 0; k < np; k++) {
+        out[2 * k] = prof_ms[k];
+        out[2 * k + 1] = prof_cnt[k];
+        prof_ms[k] = 0.0;
+        prof_cnt[k] = 0.0;
+    }
+    *len = (size_t)2 * np;
+    return SETD_OK;
+}
+
 
 setd_status Plan::nonfinite_any(int* flag)
 {
@@ -553,8 +749,9 @@ setd_status Plan::set_step(int64_t s)
 std::string class_key(const Plan& p)
 {
     char buf[160];
+    const int kind = p.d.nl == NL_NONE ? 1 : (p.d.nl == NL_KPZ ? 2 : 0);
     snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%d|%d|%d", p.g.ndim, p.g.cplx, p.g.prec, p.g.dealias, p.g.n[0],
-             p.g.n[1], p.g.n[2], p.d.nl == NL_NONE ? 1 : 0);
+             p.g.n[1], p.g.n[2], kind);
     return buf;
 }
 
@@ -602,8 +799,23 @@ setd_status setd_plan_info(const setd_plan* plan, setd_plan_info_t* info)
     info->passes_per_step = p.passes_per_step();
     info->alg_bytes_per_step = p.alg_bytes_per_step();
     info->site_updates_per_step = (double)p.nreal * p.R;
+    p.pass_bytes(info->pass_bytes);
     return SETD_OK;
 }
+
+setd_status setd_profile(setd_plan* plan, int enable)
+{
+    if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
+    plan->p.profiling = enable != 0;
+    return SETD_OK;
+}
+
+setd_status setd_profile_read(setd_plan* plan, double* out, size_t cap, size_t* len)
+{
+    if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
+    return plan->p.profile_read(out, cap, len);
+}
+
 
 setd_status setd_plan_bind(setd_plan* plan, void* dev_ws, size_t bytes, void* hip_stream)
 {
@@ -650,6 +862,12 @@ setd_status setd_set_step(setd_plan* plan, int64_t step)
 
 setd_status setd_plan_destroy(setd_plan* plan)
 {
+    if (plan) {
+        for (auto& ev : plan->p.events) {
+            (void)hipEventDestroy(ev.a);
+            (void)hipEventDestroy(ev.b);
+        }
+    }
     delete plan;
     return SETD_OK;
 }

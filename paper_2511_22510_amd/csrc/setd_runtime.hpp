@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/setd.h"
+#include "setd.h"
 #include "setd_types.hpp"
 
 namespace setd {
@@ -30,11 +30,19 @@ struct Layout {
     size_t total = 0;
 };
 
+// Kernel variants of a plan's passes (see setd_launch_impl.hpp).
+struct Tune {
+    int row = 0;   // 0..3
+    int ax0 = 0;   // 0..3
+    int ax1 = 0;   // 0..3
+};
+
 struct Plan {
     setd_desc d{};
+    Tune tune{};
     Geo g{};
     int R = 0;
-    int nkeys = 0, iso = 0, coef_cplx = 0, nbins = 0;
+    int nkeys = 0, iso = 0, coef_mode = 0, coef_cplx = 0, nbins = 0;
     int keydim[3] = {1, 1, 1};
     double dk[3] = {0, 0, 0};
     double lat = 1.0, vol = 1.0;
@@ -50,12 +58,24 @@ struct Plan {
     bool have_snap = false;
     int64_t step_host = 0;        // steps queued so far (mirror of the device counter)
     std::vector<Item> items;      // host copy of the device item table
+    // kernel timing (setd_profile)
+    bool profiling = false;
+    struct EvPair { int pass; hipEvent_t a, b; };
+    std::vector<EvPair> events;
+    double prof_ms[4] = {0, 0, 0, 0};
+    double prof_cnt[4] = {0, 0, 0, 0};
 
     setd_status init(const setd_desc& desc);
     setd_status bind(void* dev, size_t bytes, hipStream_t s);
     // queue the passes of one step for nitems items starting at items_dev
     setd_status launch_step(const Item* items_dev, int nitems, int sub, hipStream_t s) const;
+    // queue pass i (launch order) of one step
+    setd_status launch_pass(int i, const Item* items_dev, int nitems, int sub, hipStream_t s) const;
+    setd_status profile_read(double* out, size_t cap, size_t* len);
+    void pass_bytes(double* out4) const;
     setd_status step(int64_t n);
+    // time every variant of every pass on the bound buffers and keep the fastest
+    setd_status autotune();
     setd_status observe(int kind, double* out, size_t cap, size_t* len);
     setd_status get_block(size_t off, int r, double* out, size_t cap);
     setd_status set_field(int r, const double* in, size_t len);

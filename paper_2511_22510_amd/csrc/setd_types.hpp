@@ -45,7 +45,7 @@ struct Item {
     uint32_t r;       // realization index in the Philox counter
     int32_t nl;       // nonlinearity kind
     int32_t order;    // 1 or 2
-    int32_t iso;      // coefficient key |a|^2 (1) or separable (0)
+    int32_t coef_mode;// COEF_SEPARABLE, COEF_ISO or COEF_PER_MODE
     int32_t coef_cplx;// coefficient table has complex entries
     int32_t steps;    // sub-steps to take in the current scheduler tick
     int32_t keydim[3];// separable key extents (K_i + 1)
@@ -58,7 +58,8 @@ struct Item {
 
 // arguments of the FP64 coefficient-table kernel
 struct CoefArgs {
-    int nkeys, iso, ndim, order, kpow, cplx_table;
+    int nkeys, mode, ndim, order, kpow, cplx_table;
+    Geo g;            // lattice (per-mode tables)
     int keydim[3];
     double dk[3];
     double c0[2], c2[2], c4[2];
@@ -68,6 +69,10 @@ struct CoefArgs {
 };
 
 enum { NL_PHI3 = 0, NL_PHI3_CONS = 1, NL_KPZ = 2, NL_CGL = 3, NL_NONE = 4 };
+
+// coefficient table layouts: by (|a0|, |a1|, |a2|), by |a|^2, or one entry
+// per stored mode of a 2D lattice in the state layout
+enum { COEF_SEPARABLE = 0, COEF_ISO = 1, COEF_PER_MODE = 2 };
 
 // modes of the passes
 enum { MODE_STEP = 0, MODE_IC = 1, MODE_SYNC = 2 };

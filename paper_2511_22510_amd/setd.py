@@ -51,6 +51,7 @@ class setd_plan_info_t(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t), ("spectral_len", ctypes.c_size_t),
         ("kept_modes", ctypes.c_size_t), ("nbins", ctypes.c_int), ("passes_per_step", ctypes.c_int),
         ("alg_bytes_per_step", ctypes.c_double), ("site_updates_per_step", ctypes.c_double),
+        ("pass_bytes", ctypes.c_double * 4),
     ]
 
 
@@ -76,6 +77,8 @@ SIGNATURES = {
     "setd_set_field": (ctypes.c_int, [_P, ctypes.c_int, _D, _SZ]),
     "setd_get_history": (ctypes.c_int, [_P, ctypes.c_int, _D, _SZ]),
     "setd_set_step": (ctypes.c_int, [_P, _I64]),
+    "setd_profile": (ctypes.c_int, [_P, ctypes.c_int]),
+    "setd_profile_read": (ctypes.c_int, [_P, _D, _SZ, ctypes.POINTER(_SZ)]),
     "setd_plan_destroy": (ctypes.c_int, [_P]),
     "setd_server_create": (ctypes.c_int, [_P, _SZ, _P, ctypes.POINTER(_P)]),
     "setd_submit": (ctypes.c_int, [_P, ctypes.POINTER(setd_desc), _I64, ctypes.POINTER(_I64)]),
@@ -225,6 +228,19 @@ def setd_get_history(plan, r, nspec, lib=None):
 def setd_set_step(plan, step, lib=None):
     lib = lib or load()
     _check(lib, lib.setd_set_step(plan, int(step)))
+
+
+def setd_profile(plan, enable, lib=None):
+    lib = lib or load()
+    _check(lib, lib.setd_profile(plan, int(enable)))
+
+
+def setd_profile_read(plan, lib=None):
+    lib = lib or load()
+    out = np.zeros(8, dtype=np.float64)
+    ln = _SZ()
+    _check(lib, lib.setd_profile_read(plan, out.ctypes.data_as(_D), out.size, ctypes.byref(ln)))
+    return out[: ln.value].reshape(-1, 2)
 
 
 def setd_plan_destroy(plan, lib=None):

@@ -220,3 +220,22 @@ def test_linear_theory_variance_full_size():
         zs.append((out[b] / th - 1) / np.sqrt(2.0 / (cnt * 8)))
     say("z-scores", zs)
     assert np.max(np.abs(zs)) < 4.5
+
+
+VARIANT_CASES = [
+    W.model_b([64, 64], precision=32, realizations=2),
+    W.kpz([64, 32], precision=64, realizations=1, ic_kind=1, ic_sigma=0.2),
+    W.cgl([32, 32], precision=32, realizations=1),
+    W.cgl([16, 32, 32], precision=64, realizations=1),
+]
+
+
+@pytest.mark.parametrize("variant", ["0,0,0", "1,1,1", "2,2,2", "3,3,3", "1,2,3", "3,0,1"])
+def test_every_kernel_variant_matches_oracle(variant, monkeypatch):
+    """Each autotuner choice (row: LDS padding x block size; axis passes: tile
+    width x columns per thread) gives the same trajectory."""
+    monkeypatch.setenv("SETD_VARIANT", variant)
+    for p in VARIANT_CASES:
+        err = run_pair(p, steps=12, every=6)
+        say("variant", variant, p["nl"], p["n"], "err", err)
+        assert err <= TOL[p["precision"]]
