@@ -667,6 +667,14 @@ setd_status Plan::get_block(size_t off, int r, double* out, size_t cap)
     std::vector<char> host(S * elt);
     SETD_HIP(hipMemcpyAsync(host.data(), ws + off + (size_t)r * S * elt, S * elt, hipMemcpyDeviceToHost, stream));
     SETD_HIP(hipStreamSynchronize(stream));
+    scatter(host.data(), out);
+    return SETD_OK;
+}
+
+// Stored block of one realization (state precision, padded last axis) ->
+// unpruned FFT-order spectrum as interleaved doubles.
+void Plan::scatter(const char* raw, double* out) const
+{
     std::memset(out, 0, 2 * nspec * sizeof(double));
     const int last = d.ndim - 1;
     const int k1 = (d.ndim == 3) ? g.kept[1] : 1;
@@ -681,11 +689,11 @@ setd_status Plan::get_block(size_t off, int r, double* out, size_t cap)
                                                  : (size_t)j0 * g.nh_last + jl;
                 double re, im;
                 if (d.precision == 32) {
-                    const float* f = reinterpret_cast<const float*>(host.data()) + 2 * src;
+                    const float* f = reinterpret_cast<const float*>(raw) + 2 * src;
                     re = f[0];
                     im = f[1];
                 } else {
-                    const double* f = reinterpret_cast<const double*>(host.data()) + 2 * src;
+                    const double* f = reinterpret_cast<const double*>(raw) + 2 * src;
                     re = f[0];
                     im = f[1];
                 }
@@ -694,7 +702,6 @@ setd_status Plan::get_block(size_t off, int r, double* out, size_t cap)
             }
         }
     }
-    return SETD_OK;
 }
 
 setd_status Plan::set_field(int r, const double* in, size_t len)

@@ -78,6 +78,7 @@ struct Plan {
     setd_status autotune();
     setd_status observe(int kind, double* out, size_t cap, size_t* len);
     setd_status get_block(size_t off, int r, double* out, size_t cap);
+    void scatter(const char* raw, double* out) const;
     setd_status set_field(int r, const double* in, size_t len);
     setd_status set_step(int64_t step);
     setd_status nonfinite_any(int* flag);

@@ -324,6 +324,54 @@ def _torch_workspace(nbytes):
     return buf, buf.data_ptr(), stream
 
 
+class Server:
+    """A continuous-batching job server over a device arena from torch."""
+
+    def __init__(self, arena_bytes, lib=None, workspace=None):
+        self.lib = lib or load()
+        if workspace is None:
+            self._buf, ptr, stream = _torch_workspace(arena_bytes)
+        else:
+            self._buf, ptr, stream = workspace(arena_bytes)
+        self.stream = stream
+        self.h = setd_server_create(ptr, int(arena_bytes), stream, self.lib)
+        self._shape = {}
+
+    def submit(self, params, nsteps):
+        jid = setd_submit(self.h, make_desc(params), nsteps, self.lib)
+        shp = spectral_shape(params)
+        self._shape[jid] = (shp, int(np.prod(shp)))
+        return jid
+
+    def poll(self, jid):
+        return setd_poll(self.h, jid, self.lib)
+
+    def drain(self):
+        setd_server_drain(self.h, self.lib)
+
+    def times(self, jid):
+        return setd_job_times(self.h, jid, self.lib)
+
+    def observe(self, jid, kind, allow_nonfinite=False):
+        out, _ = setd_job_observe(self.h, jid, kind, 4096, self.lib, allow_nonfinite)
+        return out
+
+    def get(self, jid, r=0):
+        shp, n = self._shape[jid]
+        return setd_job_get_field(self.h, jid, r, n, self.lib).reshape(shp)
+
+    def close(self):
+        if getattr(self, "h", None):
+            setd_server_destroy(self.h, self.lib)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Plan:
     """A bound plan: problem dict -> workspace on the current torch device."""
 
