@@ -146,7 +146,9 @@ def main():
     value = sites * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
 
-    pass_names = ["k_row_real<float,512>", "k_axis0<float,512,16>"]
+    rv = int(info.variants[0])
+    pass_names = ["k_row_real<float,512,pad=%d,block=%d>" % (3 if rv & 1 else 0, 256 if rv & 2 else 64),
+                  "k_axis0<float,512,tile=%d,cols_per_thread=%d>" % (info.axis_tile[0], info.axis_tile[1])]
     tot_ms = prof[:, 0]
     cnt = prof[:, 1]
     dom = int(np.argmax(tot_ms))

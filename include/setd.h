@@ -121,6 +121,9 @@ typedef struct {
     double site_updates_per_step; /* prod n[i] * realizations                      */
     double pass_bytes[4];     /* HBM bytes each kernel launch of a step must move,
                                  in launch order (unused entries 0)                */
+    int variants[3];          /* kernel variants in use (row, axis 0, axis 1) after
+                                 the autotuner; meaningful once bound               */
+    int axis_tile[2];         /* axis-0 pass: column tile width, columns per thread */
 } setd_plan_info_t;
 
 typedef struct setd_plan setd_plan;

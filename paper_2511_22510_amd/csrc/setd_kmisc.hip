@@ -160,6 +160,16 @@ __global__ void k_obs_mean(int nb, const double* skacc, double* out)
 }
 
 
+void axis_shape(int precision, int n, int var, int* tile, int* lpt)
+{
+    const int tm = (precision == 32) ? (n <= 512 ? 16 : 8) : (n <= 512 ? 8 : 4);
+    static const int tl[4] = {1, 1, 1, 2};
+    static const int lp[4] = {2, 1, 4, 1};
+    const int v = (var >= 0 && var < 4) ? var : 0;
+    *tile = tm / tl[v];
+    *lpt = lp[v];
+}
+
 hipError_t launch_coef(const CoefArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_coef, dim3((a.nkeys + 255) / 256), dim3(256), 0, s, a);

@@ -28,6 +28,9 @@ template <typename T>
 hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind, int nbins, double vol,
                           double* acc, hipStream_t s);
 
+// (tile width, columns per thread) of axis-pass variant `var` for line length n
+void axis_shape(int precision, int n, int var, int* tile, int* lpt);
+
 struct CoefArgs;
 hipError_t launch_coef(const CoefArgs& a, hipStream_t s);
 hipError_t launch_twiddle(int n, double* out64, float* out32, hipStream_t s);

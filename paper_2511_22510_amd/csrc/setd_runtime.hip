@@ -807,6 +807,10 @@ setd_status setd_plan_info(const setd_plan* plan, setd_plan_info_t* info)
     info->alg_bytes_per_step = p.alg_bytes_per_step();
     info->site_updates_per_step = (double)p.nreal * p.R;
     p.pass_bytes(info->pass_bytes);
+    info->variants[0] = p.tune.row;
+    info->variants[1] = p.tune.ax0;
+    info->variants[2] = p.tune.ax1;
+    setd::axis_shape(p.d.precision, p.g.n[0], p.tune.ax0, &info->axis_tile[0], &info->axis_tile[1]);
     return SETD_OK;
 }
 

@@ -51,7 +51,8 @@ class setd_plan_info_t(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t), ("spectral_len", ctypes.c_size_t),
         ("kept_modes", ctypes.c_size_t), ("nbins", ctypes.c_int), ("passes_per_step", ctypes.c_int),
         ("alg_bytes_per_step", ctypes.c_double), ("site_updates_per_step", ctypes.c_double),
-        ("pass_bytes", ctypes.c_double * 4),
+        ("pass_bytes", ctypes.c_double * 4), ("variants", ctypes.c_int * 3),
+        ("axis_tile", ctypes.c_int * 2),
     ]
 
 
@@ -388,6 +389,7 @@ class Plan:
             self._buf, ptr, stream = workspace(self.nbytes)
         self.stream = stream
         setd_plan_bind(self.h, ptr, max(self.nbytes, 256), stream, self.lib)
+        self.info = setd_plan_info(self.h, self.lib)
         self.spec_shape = spectral_shape(self.p)
         self.nspec = int(self.info.spectral_len)
         self.nbins = int(self.info.nbins)
