@@ -148,6 +148,7 @@ def main():
 
     rv = int(info.variants[0])
     pass_names = ["k_row_real<float,512,pad=%d,block=%d>" % (3 if rv & 1 else 0, 256 if rv & 2 else 64),
+                  ("k_axis0r<float,512,tile=%d>" % info.axis_tile[0]) if int(info.variants[1]) >= 4 else
                   "k_axis0<float,512,tile=%d,cols_per_thread=%d>" % (info.axis_tile[0], info.axis_tile[1])]
     tot_ms = prof[:, 0]
     cnt = prof[:, 1]
@@ -194,12 +195,12 @@ def main():
 
     if not args.no_cpu:
         from oracle import oracle as O
-        R_cpu, steps_cpu = 8, 100
+        R_cpu, steps_cpu = 8, 300
         o = O.Sim(p, r_first=0, r_count=R_cpu)
         t0 = time.perf_counter()
         o.step(steps_cpu)
         dt = time.perf_counter() - t0
-        cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+        cores = O.threads()
         line["cpu_baseline"] = {
             "value": 512 * 512 * R_cpu * steps_cpu / dt, "unit": "site-updates/s", "cores": cores,
             "kind": "oracle",

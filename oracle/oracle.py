@@ -65,6 +65,7 @@ def lib():
         L.orc_step_index.argtypes = [vp]
         L.orc_step_index.restype = ctypes.c_int64
         L.orc_nbins.argtypes = [vp]
+        L.orc_threads.argtypes = []
         L.orc_step.argtypes = [vp, ctypes.c_int64]
         L.orc_step_xi.argtypes = [vp, dp]
         L.orc_noise_xi.argtypes = [vp, ctypes.c_int64, dp]
@@ -76,6 +77,11 @@ def lib():
                                   ctypes.POINTER(ctypes.c_size_t)]
         _lib = L
     return _lib
+
+
+def threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
 
 
 def _dptr(a):

@@ -38,6 +38,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -488,6 +489,9 @@ void orc_destroy(orc_sim* s)
 size_t orc_nspec(const orc_sim* s) { return s->nspec; }
 int64_t orc_step_index(const orc_sim* s) { return s->step; }
 int orc_nbins(const orc_sim* s) { return s->nbins; }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int orc_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Step 1 of Sec. 4: F_a = M_a pref_a FFT[N(IFFT[phi])]                      */

@@ -41,6 +41,118 @@ __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) { return {a.x * b.x + a
 template <typename T>
 __device__ __forceinline__ cx<T> czero() { return {T(0), T(0)}; }
 
+// ---------------------------------------------------------------- global memory
+// Loads and stores through the global address space at a 32-bit byte offset
+// from a wave-uniform base, so that the compiler emits global (not flat)
+// instructions with the base in scalar registers; callers guarantee that the
+// offset fits 32 bits.
+template <typename T>
+struct vec2;
+template <>
+struct vec2<float> {
+    typedef float __attribute__((ext_vector_type(2))) type;
+};
+template <>
+struct vec2<double> {
+    typedef double __attribute__((ext_vector_type(2))) type;
+};
+#define SETD_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ cx<T> gload(const void* base, uint32_t off)
+{
+    typedef typename vec2<T>::type V;
+    const V u = *(const SETD_GLOBAL V*)((const SETD_GLOBAL char*)base + off);
+    return {u.x, u.y};
+}
+
+template <typename T>
+__device__ __forceinline__ void gstore(void* base, uint32_t off, cx<T> v)
+{
+    typedef typename vec2<T>::type V;
+    V u;
+    u.x = v.x;
+    u.y = v.y;
+    *(SETD_GLOBAL V*)((SETD_GLOBAL char*)base + off) = u;
+}
+
+template <typename T>
+struct alignas(4 * sizeof(T)) T4 {
+    T a, b, c, d;
+};
+
+template <typename T>
+__device__ __forceinline__ T4<T> gload4(const void* base, uint32_t off)
+{
+    typedef T __attribute__((ext_vector_type(4))) V;
+    const V u = *(const SETD_GLOBAL V*)((const SETD_GLOBAL char*)base + off);
+    return {u.x, u.y, u.z, u.w};
+}
+
+// ---------------------------------------------------------------- buffer access
+// Raw buffer loads and stores: a 128-bit resource in scalar registers holds the
+// base and byte size of an array (third word 0x00020000, the gfx9-family
+// format for untyped dword access), and each access adds a 32-bit per-lane
+// offset and a wave-uniform offset.  A lane whose per-lane offset is at or past
+// the size reads zero and writes nothing, which is how masked lanes are
+// expressed (BUF_OOB; every array addressed this way is under 2 GiB).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t BUF_OOB = 0x80000000u;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ cx<T> bload(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(T) == 4) {
+        const u32x2 u = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+        return {__uint_as_float(u.x), __uint_as_float(u.y)};
+    } else {
+        const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+        return {__hiloint2double((int)u.y, (int)u.x), __hiloint2double((int)u.w, (int)u.z)};
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, cx<T> v)
+{
+    if constexpr (sizeof(T) == 4) {
+        u32x2 u;
+        u.x = __float_as_uint(v.x);
+        u.y = __float_as_uint(v.y);
+        __builtin_amdgcn_raw_buffer_store_b64(u, r, (int)voff, (int)soff, 0);
+    } else {
+        const unsigned long long a = (unsigned long long)__double_as_longlong(v.x);
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v.y);
+        u32x4 u;
+        u.x = (unsigned)a;
+        u.y = (unsigned)(a >> 32);
+        u.z = (unsigned)b;
+        u.w = (unsigned)(b >> 32);
+        __builtin_amdgcn_raw_buffer_store_b128(u, r, (int)voff, (int)soff, 0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T4<T> bload4(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(T) == 4) {
+        const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+        return {__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), __uint_as_float(u.w)};
+    } else {
+        const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+        const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff + 16, 0);
+        return {__hiloint2double((int)u.y, (int)u.x), __hiloint2double((int)u.w, (int)u.z),
+                __hiloint2double((int)w.y, (int)w.x), __hiloint2double((int)w.w, (int)w.z)};
+    }
+}
+
 // ---------------------------------------------------------------- butterflies
 // a * (SIGN i)
 template <int SIGN, typename T>
@@ -143,7 +255,7 @@ __device__ __forceinline__ void line_tw_load(LineTw<T, N>& L, int t, const cx<T>
     int ns = FftPlan<N>::R0;
 #pragma unroll
     for (int s = 0; s + 1 < NST; s++) {
-        L.w[s] = tw[(t & (ns - 1)) * (N / (ns * 8))];
+        L.w[s] = gload<T>(tw, (uint32_t)((t & (ns - 1)) * (N / (ns * 8))) * (uint32_t)sizeof(cx<T>));
         ns *= 8;
     }
 }
@@ -182,31 +294,45 @@ __device__ __forceinline__ void fft_stage8(cx<T>* v, cx<T> w)
     dft8<SIGN>(v);
 }
 
+// Slot distance of element e0 + d from element e0 for a power-of-two d when no
+// multiple of 2^PAD lies in (e0, e0 + d] other than those d itself implies
+// (see fft_exchange): d plus one pad slot per 2^PAD.
+template <int PAD>
+constexpr int slot_step(int d) { return PAD > 0 ? d + (d >> PAD) : d; }
+
 // Write the outputs of a stage (radix R, NS points combined before it) to
 // their Stockham positions (j / NS) NS R + j mod NS + r NS, then read the next
 // stage's inputs back in the natural layout t + q N/8.  Element e of line k
 // lives at lds[k * lstep + lds_slot<PAD>(e) * stride]; the NL lines of a thread
 // share the two block barriers of the exchange.
+// Every address is one per-thread base plus a compile-time offset: with
+// A = (j / NS) NS R and power-of-two NS, R, 2^PAD, the positions A + j mod NS
+// + r NS cross a multiple of 2^PAD exactly where r NS does when NS R >= 2^PAD
+// (offset slot_step(r NS)) and never otherwise (offset r NS); the reads
+// t + q N/8 with t < N/8 likewise sit at slot(t) + slot_step(q N/8).
 template <typename T, int N, int R, int NS, int PAD, int NL>
 __device__ __forceinline__ void fft_exchange(cx<T> (&v)[NL][8], int t, cx<T>* lds, int stride, int lstep)
 {
     constexpr int NB = 8 / R;
+    constexpr bool LIN = PAD == 0 || NS * R >= (1 << PAD);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NL; k++) {
+    for (int b = 0; b < NB; b++) {
+        const int j = t + b * (N / 8);
+        const int base = (j / NS) * NS * R + (j & (NS - 1));
+        cx<T>* p = lds + lds_slot<PAD>(base) * stride;
 #pragma unroll
-        for (int b = 0; b < NB; b++) {
-            const int j = t + b * (N / 8);
-            const int base = (j / NS) * NS * R + (j & (NS - 1));
+        for (int k = 0; k < NL; k++) {
 #pragma unroll
-            for (int r = 0; r < R; r++) lds[k * lstep + lds_slot<PAD>(base + r * NS) * stride] = v[k][b + NB * r];
+            for (int r = 0; r < R; r++) p[k * lstep + (LIN ? slot_step<PAD>(r * NS) : r * NS) * stride] = v[k][b + NB * r];
         }
     }
     __syncthreads();
+    const cx<T>* p = lds + lds_slot<PAD>(t) * stride;
 #pragma unroll
     for (int k = 0; k < NL; k++) {
 #pragma unroll
-        for (int q = 0; q < 8; q++) v[k][q] = lds[k * lstep + lds_slot<PAD>(t + q * (N / 8)) * stride];
+        for (int q = 0; q < 8; q++) v[k][q] = p[k * lstep + slot_step<PAD>(q * (N / 8)) * stride];
     }
 }
 

@@ -52,11 +52,6 @@ struct Coef {
 };
 
 template <typename T>
-struct alignas(4 * sizeof(T)) T4 {
-    T a, b, c, d;
-};
-
-template <typename T>
 __device__ __forceinline__ Coef<T> load_coef(const Item& it, int key)
 {
     Coef<T> r;
@@ -69,6 +64,29 @@ __device__ __forceinline__ Coef<T> load_coef(const Item& it, int key)
         r.G = w.c;
     } else {
         const T4<T> u = reinterpret_cast<const T4<T>*>(it.coef)[key];
+        r.E = {u.a, T(0)};
+        r.wa = {u.b, T(0)};
+        r.wb = {u.c, T(0)};
+        r.G = u.d;
+    }
+    return r;
+}
+
+// the same with the table's entry type known at compile time, through global
+// loads at a 32-bit offset
+template <typename T, bool CC>
+__device__ __forceinline__ Coef<T> load_coef_t(const void* coef, int key)
+{
+    Coef<T> r;
+    if constexpr (CC) {
+        const uint32_t o = (uint32_t)key * (uint32_t)(8 * sizeof(T));
+        const T4<T> u = gload4<T>(coef, o), w = gload4<T>(coef, o + 4 * sizeof(T));
+        r.E = {u.a, u.b};
+        r.wa = {u.c, u.d};
+        r.wb = {w.a, w.b};
+        r.G = w.c;
+    } else {
+        const T4<T> u = gload4<T>(coef, (uint32_t)key * (uint32_t)(4 * sizeof(T)));
         r.E = {u.a, T(0)};
         r.wa = {u.b, T(0)};
         r.wb = {u.c, T(0)};
@@ -131,6 +149,24 @@ __device__ __forceinline__ cx<T> noise_eta(const Geo& g, const Item& it, int j0,
     normal_pair(it.seed, ectr, n, it.r, 0u, z1, z2);
     if (kind == 1) return {z1, T(0)};
     return {rs2 * z1, (kind == 2) ? -rs2 * z2 : rs2 * z2};
+}
+
+// ---------------------------------------------------------------- step counter
+// Called by thread 0 of every block of a realization's pass, after a block
+// barrier (so every thread of the block has read the step counter): the last
+// block to arrive advances the realization's step and marks its history valid.
+// The counter is read only at the start of the next launch, and consecutive
+// launches on a stream are ordered for all memory, so no fence is needed; a
+// device-scope fence here would write back the whole L2 of the XCD from every
+// block.
+__device__ __forceinline__ void advance_step(Ctrl* c, unsigned blocks, int64_t nstep)
+{
+    const unsigned prior = atomicAdd(&c->done, 1u);
+    if (prior == blocks - 1u) {
+        atomicExch(&c->done, 0u);
+        atomicExch(reinterpret_cast<unsigned long long*>(&c->step), (unsigned long long)(nstep + 1));
+        atomicExch(&c->have_prev, 1);
+    }
 }
 
 // ---------------------------------------------------------------- launch arguments
@@ -579,17 +615,247 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
     if (a.mode == MODE_STEP) {
         // the last block of this realization advances its step counter
         __syncthreads();
-        if (tid == 0) {
-            __threadfence();
-            const unsigned prior = atomicAdd(&it.ctrl->done, 1u);
-            if (prior == (unsigned)a.per_item - 1u) {
-                atomicExch(&it.ctrl->done, 0u);
-                atomicExch(reinterpret_cast<unsigned long long*>(&it.ctrl->step), (unsigned long long)(nstep + 1));
-                atomicExch(&it.ctrl->have_prev, 1);
-                __threadfence();
+        if (tid == 0) advance_step(it.ctrl, (unsigned)a.per_item, nstep);
+    }
+}
+
+// ---------------------------------------------------------------- axis-0 pass, update in registers
+// The time step of k_axis0 (MODE_STEP, 2/3 rule on), one column per thread
+// group, with the ETD update done in the layout the column transform leaves in
+// registers: thread t holds bins j = t + q N0/8 (q = 0..7).  The state and
+// history of those bins do not depend on the transform, so they are requested
+// before it starts, and the unit noise is drawn while they are in flight (a
+// rolled loop with one Philox call site, its results rotated through a
+// register array); the coefficient table (L2-resident, shared by all
+// realizations) is read after the transform.  There is no LDS sweep.  (With
+// 512-thread blocks at four waves per SIMD the register budget allows only the
+// noise to be prepared early; state and history are then read after the
+// forward transform.)
+//
+// Under the 2/3 rule the bins of q = 0, 1, 6, 7 are always stored, those of
+// q = 3, 4 (3N0/8 <= j < 5N0/8) never, those of q = 2, 5 in part; a stored
+// bin's row is j (q <= 2) or j - N0 + kept0 (q >= 5).  Every array access is
+// a buffer access at the per-lane offset of row t plus a uniform per-q offset;
+// lanes without a stored mode (and padding columns past the stored last-axis
+// modes) use BUF_OOB, so they read zeros and write nothing.  Padding columns
+// are still transformed: every column is an independent line.
+// KIND: 0 real field, 1 real field with the KPZ gradient, 2 complex field
+// (complex coefficient entries).
+// Occupancy target in waves per SIMD: at least two resident blocks per CU
+// (a CU has 4 SIMDs), so that one block's transforms overlap another's memory
+// traffic; three for small blocks of single precision.
+template <typename T, int NTHR>
+constexpr int axis0r_waves()
+{
+    constexpr int w = NTHR / 64;   // waves per block
+    return sizeof(T) == 8 ? (w >= 4 ? w / 2 : 2) : (w >= 8 ? w / 2 : 3);
+}
+
+template <typename T, int N0, int TILE, int PAD, int KIND>
+__global__ void __launch_bounds__(TILE * N0 / 8)
+__attribute__((amdgpu_waves_per_eu(axis0r_waves<T, TILE * N0 / 8>())))
+k_axis0r(AxisArgs a)
+{
+    constexpr bool KPZ = KIND == 1, CC = KIND == 2;
+    const unsigned lg = xcd_logical(blockIdx.x, gridDim.x);
+    const int item = (int)(lg / (unsigned)a.per_item);
+    const int blk = (int)(lg % (unsigned)a.per_item);
+    const Item it = a.items[item];
+    if (a.sub >= it.steps) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    const Geo& g = a.g;
+    constexpr int TPL = N0 / 8;
+    constexpr uint32_t ES = sizeof(cx<T>);
+    constexpr uint32_t CS = (CC ? 8 : 4) * sizeof(T);   // bytes of a coefficient entry
+    const int tid = threadIdx.x;
+    const int c0 = tid % TILE, t = tid / TILE;
+    const int tile = blk % a.ntiles, i1 = blk / a.ntiles;
+    const int last = g.ndim - 1;
+    const int keptl = g.kept[last];
+    const int kept0 = g.kept[0], kp0 = g.kp[0];
+    // bytes of one row (axis-0 index) of the arrays of a realization
+    const uint32_t lstride = ((g.ndim == 3) ? (uint32_t)g.kept[1] * g.pitch : (uint32_t)g.pitch) * ES;
+    const int colm = tile * TILE + c0;
+    const bool cv = colm < keptl;
+    const uint32_t vrow = (uint32_t)t * lstride + ((uint32_t)i1 * g.pitch + colm) * ES;   // row t, this column
+    const uint32_t vcol = cv ? vrow : BUF_OOB;
+    const rsrc_t rpre = make_rsrc(it.pre0, (uint32_t)N0 * lstride);
+    const rsrc_t rphi = make_rsrc(it.phi, (uint32_t)kept0 * lstride);
+    const rsrc_t rprev = make_rsrc(it.prev, (uint32_t)kept0 * lstride);
+    const rsrc_t rcoef = make_rsrc(it.coef, it.coef_bytes);
+    // stored-row shift of bin q and whether this lane's bin of q is stored
+    auto dq = [&](int q) { return q <= 2 ? 0 : kept0 - N0; };
+    auto stored = [&](int q) {
+        if (q == 3 || q == 4) return false;
+        if (q == 2) return t + 2 * TPL <= kp0;
+        if (q == 5) return t + 5 * TPL >= N0 - kp0;
+        return true;
+    };
+    auto live = [](int q) { return q != 3 && q != 4; };
+    auto voff = [&](int q) { return (q == 2 || q == 5) ? (stored(q) ? vcol : BUF_OOB) : vcol; };
+    auto soff = [&](int q) { return (uint32_t)(q * TPL + dq(q)) * lstride; };
+
+    int j1 = 0, a1 = 0;
+    if (g.ndim == 3) {
+        j1 = fft_pos(i1, g.n[1], g.kept[1], g.kp[1]);
+        a1 = sgn_idx(j1, g.n[1]);
+    }
+    int jl = colm, al = colm;   // FFT position and signed index on the last axis
+    if (CC) {
+        jl = fft_pos(colm, g.n[last], keptl, g.kp[last]);
+        al = sgn_idx(jl, g.n[last]);
+    }
+
+    const int64_t nstep = *(const SETD_GLOBAL int64_t*)&it.ctrl->step;
+    const int hp = *(const SETD_GLOBAL int*)&it.ctrl->have_prev;
+
+    cx<T> v[1][8];
+    cx<T> ph[8], pv[8], eta[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) v[0][q] = bload<T>(rpre, vrow, (uint32_t)(q * TPL) * lstride);
+    // at the highest occupancy target state and history are read after the
+    // forward transform, with the coefficients, to stay within the register
+    // budget
+    constexpr bool EARLY = axis0r_waves<T, TILE * N0 / 8>() < 4;
+    auto load_state = [&]() {
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            ph[q] = czero<T>();
+            pv[q] = czero<T>();
+            if (live(q)) {
+                ph[q] = bload<T>(rphi, voff(q), soff(q));
+                if (it.order == 2) pv[q] = bload<T>(rprev, voff(q), soff(q));
             }
         }
+    };
+    if constexpr (EARLY) load_state();
+    // unit noise of the six bins that can hold a stored mode (q = 0, 1, 2,
+    // 5, 6, 7), while the loads are in flight
+    cx<T> ez[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) ez[k] = czero<T>();
+#pragma unroll 1
+    for (int k = 0; k < 6; k++) {
+        const int j0 = t + (k < 3 ? k : k + 2) * TPL;
+        cx<T> e = czero<T>();
+        if (cv && stored_idx(j0, N0, kept0, kp0) >= 0) e = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)nstep);
+#pragma unroll
+        for (int s = 0; s < 5; s++) ez[s] = ez[s + 1];
+        ez[5] = e;
     }
+#pragma unroll
+    for (int q = 0; q < 8; q++) eta[q] = live(q) ? ez[q < 3 ? q : q - 2] : czero<T>();
+    LineTw<T, N0> tw;
+    line_tw_load(tw, t, twid<T>(it.tw0));
+    cx<T>* L = lds + c0;   // element e of the column at L + e * TILE
+
+    fft_lines<T, N0, -1, PAD, 1>(v, t, L, TILE, 0, tw);
+    const bool per_mode = it.coef_mode == COEF_PER_MODE;
+    const uint32_t vcoef = ((uint32_t)t * g.pitch + colm) * CS;
+    auto load_coef_q = [&](int q) {
+        // lanes without a stored mode read nothing
+        const bool st = cv && stored(q);
+        uint32_t vo, so;
+        if (per_mode) {
+            // entry (row, column) of the table in the state layout
+            vo = st ? vcoef : BUF_OOB;
+            so = (uint32_t)(q * TPL + dq(q)) * g.pitch * CS;
+        } else {
+            const int a0 = sgn_idx(t + q * TPL, N0);
+            const int key = (g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0);
+            vo = st ? (uint32_t)key * CS : BUF_OOB;
+            so = 0;
+        }
+        Coef<T> c;
+        if constexpr (CC) {
+            const T4<T> u = bload4<T>(rcoef, vo, so), w = bload4<T>(rcoef, vo, so + 4 * sizeof(T));
+            c.E = {u.a, u.b};
+            c.wa = {u.c, u.d};
+            c.wb = {w.a, w.b};
+            c.G = w.c;
+        } else {
+            const T4<T> u = bload4<T>(rcoef, vo, so);
+            c.E = {u.a, T(0)};
+            c.wa = {u.b, T(0)};
+            c.wb = {u.c, T(0)};
+            c.G = u.d;
+        }
+        return c;
+    };
+    const bool use_prev = it.order == 2 && hp;
+    const T dk0 = (T)it.dk[0], dk1 = (T)it.dk[1], dk2 = (T)it.dk[2];
+    const T kl = (g.ndim == 3) ? dk2 * (T)al : dk1 * (T)al;
+    const T km = (g.ndim == 3) ? dk1 * (T)a1 : T(0);
+    bool bad = false;
+    v[0][3] = czero<T>();
+    v[0][4] = czero<T>();
+    // the six bins in two groups of three (q = 0..2, then 5..7): each group
+    // reads its coefficients (and, when not read early, state and history)
+    // and is updated and stored before the next group's reads
+#pragma unroll
+    for (int grp = 0; grp < 2; grp++) {
+        const int qb = grp == 0 ? 0 : 5;
+        cx<T> gph[3], gpv[3];
+        Coef<T> cf[3];
+#pragma unroll
+        for (int u = 0; u < 3; u++) {
+            const int q = qb + u;
+            if constexpr (EARLY) {
+                gph[u] = ph[q];
+                gpv[u] = pv[q];
+            } else {
+                gph[u] = bload<T>(rphi, voff(q), soff(q));
+                gpv[u] = it.order == 2 ? bload<T>(rprev, voff(q), soff(q)) : czero<T>();
+            }
+            cf[u] = load_coef_q(q);
+        }
+#pragma unroll
+        for (int u = 0; u < 3; u++) {
+            const int q = qb + u;
+            // lanes without a stored mode compute on zeros and store nothing
+            const bool st = cv && stored(q);
+            const T k0 = dk0 * (T)sgn_idx(t + q * TPL, N0);
+            const T k2 = k0 * k0 + km * km + kl * kl;
+            const cx<T> F = cmul(nl_pref<T>(it, k2), v[0][q]);
+            cx<T> nw;
+            if constexpr (CC) {
+                nw = cmul(cf[u].E, gph[u]) + cmul(cf[u].wa, F) + cf[u].G * eta[q];
+                if (it.order == 2) nw = nw + cmul(cf[u].wb, use_prev ? gpv[u] : F);
+            } else {
+                nw = cf[u].E.x * gph[u] + cf[u].wa.x * F + cf[u].G * eta[q];
+                if (it.order == 2) nw = nw + cf[u].wb.x * (use_prev ? gpv[u] : F);
+            }
+            if (it.order == 2) bstore<T>(rprev, voff(q), soff(q), F);
+            bstore<T>(rphi, voff(q), soff(q), nw);
+            bad |= st && !(isfinite(nw.x) && isfinite(nw.y));
+            v[0][q] = st ? nw : czero<T>();
+        }
+    }
+    // one flag update per block
+    if (__syncthreads_or(bad) && tid == 0) atomicOr(&it.ctrl->nonfinite, 1);
+
+    cx<T> v2[1][8];
+    if constexpr (KPZ) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int j0 = t + q * TPL;
+            const T kk = (2 * j0 == N0) ? T(0) : dk0 * (T)sgn_idx(j0, N0);
+            v2[0][q] = {-kk * v[0][q].y, kk * v[0][q].x};
+        }
+    }
+    fft_lines<T, N0, +1, PAD, 1>(v, t, L, TILE, 0, tw);
+#pragma unroll
+    for (int q = 0; q < 8; q++) bstore<T>(rpre, vcol, (uint32_t)(q * TPL) * lstride, v[0][q]);
+    if constexpr (KPZ) {
+        const rsrc_t rpre1 = make_rsrc(it.pre1, (uint32_t)N0 * lstride);
+        fft_lines<T, N0, +1, PAD, 1>(v2, t, L, TILE, 0, tw);
+#pragma unroll
+        for (int q = 0; q < 8; q++) bstore<T>(rpre1, vcol, (uint32_t)(q * TPL) * lstride, v2[0][q]);
+    }
+    // the last block of this realization advances its step counter
+    __syncthreads();
+    if (tid == 0) advance_step(it.ctrl, (unsigned)a.per_item, nstep);
 }
 
 // ---------------------------------------------------------------- axis-1 pass (3D)
@@ -700,16 +966,7 @@ __global__ void __launch_bounds__(256) k_linear(LinArgs a)
         }
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&it.ctrl->nonfinite, 1);
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prior = atomicAdd(&it.ctrl->done, 1u);
-        if (prior == gridDim.x - 1) {
-            atomicExch(&it.ctrl->done, 0u);
-            atomicExch(reinterpret_cast<unsigned long long*>(&it.ctrl->step), (unsigned long long)(nstep + 1));
-            atomicExch(&it.ctrl->have_prev, 1);
-            __threadfence();
-        }
-    }
+    if (threadIdx.x == 0) advance_step(it.ctrl, gridDim.x, nstep);
 }
 
 // ---------------------------------------------------------------- FP64 observables

@@ -12,8 +12,8 @@ namespace setd {
 template <typename T>
 constexpr int pitch_align() { return sizeof(T) == 4 ? 16 : 8; }
 
-// `var` selects a kernel variant (see setd_launch_impl.hpp); 0..3 for the
-// row pass, 0..3 for the axis passes
+// `var` selects a kernel variant (see setd_launch_impl.hpp); 0..3 for the row
+// and axis-1 passes, 0..5 for the axis-0 pass
 template <typename T>
 hipError_t launch_row(const Geo& g, const Item* items, int nitems, int mode, int sub, int var, int kpz,
                       hipStream_t s);

@@ -5,7 +5,9 @@
 //              (one wavefront or 256 threads)
 //   axis pass: (column tile width, columns per thread) in
 //              {(tm, 2), (tm, 1), (tm, 4), (tm/2, 1)}, tm = tile_max, with LDS
-//              padding whenever the padded tile still fits 64 KiB
+//              padding whenever the padded tile still fits 64 KiB; the axis-0
+//              time step also has the register-update kernel k_axis0r with
+//              tile tm/2 (variant 4) or tm/4 (variant 5)
 #pragma once
 
 #include "setd_kernels.hpp"
@@ -105,11 +107,47 @@ static hipError_t launch_axis_nt(const Geo& g, const Item* items, int nitems, in
     return hipGetLastError();
 }
 
+// axis-0 pass with the update in registers (k_axis0r), one column per thread group
+template <typename T, int N, int TILE>
+static hipError_t launch_axis0r(const Geo& g, const Item* items, int nitems, int mode, int sub, bool kpz,
+                                hipStream_t s)
+{
+    constexpr int PAD = tile_pad<T, N, TILE>();
+    AxisArgs a;
+    a.g = g;
+    a.items = items;
+    a.ntiles = g.pitch / TILE;
+    a.per_item = a.ntiles * ((g.ndim == 3) ? g.kept[1] : 1);
+    a.mode = mode;
+    a.sub = sub;
+    dim3 grid(a.per_item * nitems);
+    dim3 block(TILE * (N / 8));
+    const size_t lds = (size_t)TILE * lds_len<N, PAD>() * 2 * sizeof(T);
+    if (g.cplx) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 2>), grid, block, lds, s, a);
+    else if (kpz) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 1>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 0>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
 template <typename T, int N, bool AX0>
 static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int mode, int sub, int var,
                                 bool kpz, hipStream_t s)
 {
     constexpr int TM = tile_max<T>(N);
+    if constexpr (AX0) {
+        // the register-update kernel does the time step under the 2/3 rule,
+        // with buffer accesses into arrays of under 2 GiB per realization;
+        // other modes and plans take the tile-sweep kernel
+        const size_t pre_bytes = (size_t)g.n[0] * (g.ndim == 3 ? g.kept[1] : 1) * g.pitch * 2 * sizeof(T);
+        const bool reg = mode == MODE_STEP && g.dealias && pre_bytes < ((size_t)1 << 31);
+        if (var == 4) {
+            if (reg) return launch_axis0r<T, N, (TM >= 2 ? TM / 2 : 1)>(g, items, nitems, mode, sub, kpz, s);
+            var = 3;
+        } else if (var == 5) {
+            if (reg) return launch_axis0r<T, N, (TM >= 4 ? TM / 4 : 1)>(g, items, nitems, mode, sub, kpz, s);
+            var = 3;
+        }
+    }
     switch (var) {
     case 0: return launch_axis_nt<T, N, TM, 2, AX0>(g, items, nitems, mode, sub, kpz, s);
     case 1: return launch_axis_nt<T, N, TM, 1, AX0>(g, items, nitems, mode, sub, kpz, s);

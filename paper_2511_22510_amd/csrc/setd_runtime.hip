@@ -151,7 +151,9 @@ setd_status Plan::init(const setd_desc& desc)
         for (int i = 0; i < 3; i++) keydim[i] = (i < d.ndim) ? kmax[i] + 1 : 1;
         nkeys = keydim[0] * keydim[1] * keydim[2];
     }
-    coef_cplx = (d.c0[1] != 0.0 || d.c2[1] != 0.0 || d.c4[1] != 0.0) ? 1 : 0;
+    // complex fields always take complex entries (the kernels of a launch class
+    // then share one table layout); real fields have real c(k)
+    coef_cplx = d.complex_field ? 1 : 0;
     long msq = 0;
     for (int i = 0; i < d.ndim; i++) msq += (long)(d.n[i] / 2) * (d.n[i] / 2);
     nbins = ceil_isqrt_host(msq) + 1;
@@ -319,6 +321,10 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
         it.order = d.order;
         it.coef_mode = coef_mode;
         it.coef_cplx = coef_cplx;
+        {
+            const size_t cb = (size_t)nkeys * (coef_cplx ? 8 : 4) * (d.precision == 32 ? 4 : 8);
+            it.coef_bytes = (uint32_t)(cb < 0x7fffffffu ? cb : 0x7fffffffu);
+        }
         it.steps = INT_MAX;
         for (int i = 0; i < 3; i++) {
             it.keydim[i] = keydim[i];
@@ -437,13 +443,13 @@ setd_status Plan::autotune()
     // SETD_VARIANT="row,axis0,axis1" pins the variants (tests, reproducible timing)
     if (const char* pin = std::getenv("SETD_VARIANT")) {
         int r = 0, a0 = 0, a1 = 0;
-        if (sscanf(pin, "%d,%d,%d", &r, &a0, &a1) == 3 && r >= 0 && r < 4 && a0 >= 0 && a0 < 4 && a1 >= 0 && a1 < 4) {
+        if (sscanf(pin, "%d,%d,%d", &r, &a0, &a1) == 3 && r >= 0 && r < 4 && a0 >= 0 && a0 < 6 && a1 >= 0 && a1 < 4) {
             tune.row = r;
             tune.ax0 = a0;
             tune.ax1 = a1;
             return SETD_OK;
         }
-        return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row in 0..3 and axes in 0..3");
+        return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row and axis1 in 0..3, axis0 in 0..5");
     }
     const char* env = std::getenv("SETD_AUTOTUNE");
     if (env && env[0] == '0') return SETD_OK;
@@ -466,7 +472,8 @@ setd_status Plan::autotune()
     const int row_pass = (d.ndim == 2) ? 0 : 1;
     const int ax0_pass = (d.ndim == 2) ? 1 : 3;
     struct Knob { int* var; int nvar; int pass; int pass2; };
-    Knob knobs[3] = {{&tune.row, 4, row_pass, -1}, {&tune.ax0, 4, ax0_pass, -1}, {&tune.ax1, 4, 0, 2}};
+    // axis-0 variants 4 and 5 (register update) exist for dealiased plans
+    Knob knobs[3] = {{&tune.row, 4, row_pass, -1}, {&tune.ax0, g.dealias ? 6 : 4, ax0_pass, -1}, {&tune.ax1, 4, 0, 2}};
     const int nknobs = (d.ndim == 3) ? 3 : 2;
     setd_status st = SETD_OK;
     for (int k = 0; k < nknobs && st == SETD_OK; k++) {

@@ -49,7 +49,7 @@ struct Item {
     int32_t coef_cplx;// coefficient table has complex entries
     int32_t steps;    // sub-steps to take in the current scheduler tick
     int32_t keydim[3];// separable key extents (K_i + 1)
-    int32_t pad0;
+    uint32_t coef_bytes;// bytes of the coefficient table (capped at 2^31 - 1)
     double dk[3];     // 2 pi / L_i
     double par0;      // u | lambda | beta
     double inv_vol;   // 1 / prod n_i (inverse DFT scale)

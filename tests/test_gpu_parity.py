@@ -227,13 +227,16 @@ VARIANT_CASES = [
     W.kpz([64, 32], precision=64, realizations=1, ic_kind=1, ic_sigma=0.2),
     W.cgl([32, 32], precision=32, realizations=1),
     W.cgl([16, 32, 32], precision=64, realizations=1),
+    W.model_a([8, 16], precision=32, order=2, realizations=3),
+    W.kpz([128, 64], precision=32, realizations=2, ic_kind=1, ic_sigma=0.2),
 ]
 
 
-@pytest.mark.parametrize("variant", ["0,0,0", "1,1,1", "2,2,2", "3,3,3", "1,2,3", "3,0,1"])
+@pytest.mark.parametrize("variant", ["0,0,0", "1,1,1", "2,2,2", "3,3,3", "1,2,3", "3,0,1", "0,4,0", "2,5,3"])
 def test_every_kernel_variant_matches_oracle(variant, monkeypatch):
     """Each autotuner choice (row: LDS padding x block size; axis passes: tile
-    width x columns per thread) gives the same trajectory."""
+    width x columns per thread; axis-0 variants 4 and 5: the register-update
+    kernel at two tile widths) gives the same trajectory."""
     monkeypatch.setenv("SETD_VARIANT", variant)
     for p in VARIANT_CASES:
         err = run_pair(p, steps=12, every=6)
