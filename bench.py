@@ -12,8 +12,10 @@ One step = one SETD2 transition of every realization: the last-axis pass
 (inverse FFT, phi^3, forward FFT) and the axis-0 pass (forward FFT, ETD update
 with Philox noise and dealiasing, inverse FFT).
 
-Printed: one JSON line with site-updates/s, the roofline record of the
-dominant kernel (timed live with HIP events on the library's stream), the
+Printed: one JSON line with site-updates/s (a timed segment with no
+instrumentation), the roofline record of the dominant kernel (a second timed
+segment of the same length, HIP events around every pass on the library's
+stream), the
 plain per-realization FP64 rate of the same model on the same GPU, a short
 continuous-batching serving run (p50/p99 job latency), and the FP64 oracle
 timed on the host cores over a bounded sample.
@@ -60,23 +62,35 @@ def measured_traffic(kernel):
 
 
 def time_plan(setd, p, steps, warmup, profile):
+    """Time `steps` steps of plan `p` after `warmup` untimed ones, with no
+    instrumentation; with `profile`, then time a second segment of `steps`
+    steps with HIP events around every pass on the library's stream (per-pass
+    durations; the events add a little time per pass, so that segment does not
+    give the step rate).  Returns (seconds of the first segment, per-pass
+    [total ms, launches] of the second or None, plan info, clean finish,
+    seconds of the second segment or None)."""
     import torch
     plan = setd.Plan(p)
     plan.step(warmup)
-    torch.cuda.synchronize()
-    if profile:
-        setd.setd_profile(plan.h, 1, plan.lib)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = setd.setd_profile_read(plan.h, plan.lib) if profile else None
+    prof, t_prof = None, None
+    if profile:
+        setd.setd_profile(plan.h, 1, plan.lib)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        plan.step(steps)
+        torch.cuda.synchronize()
+        t_prof = time.perf_counter() - t2
+        prof = setd.setd_profile_read(plan.h, plan.lib)
     out, st = setd.setd_observe(plan.h, setd.OBS_STEP, 4, plan.lib, allow_nonfinite=True)
-    ok = (st == setd.SETD_OK) and out[0] == warmup + steps
+    ok = (st == setd.SETD_OK) and out[0] == warmup + steps * (2 if profile else 1)
     info = plan.info
     plan.close()
-    return t1 - t0, prof, info, ok
+    return t1 - t0, prof, info, ok, t_prof
 
 
 def serving_run(setd, W, n_jobs, seed):
@@ -138,7 +152,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     p = W.problem(W.CONFIG_B)
-    elapsed, prof, info, ok = time_plan(setd, p, args.steps, args.warmup, profile=True)
+    elapsed, prof, info, ok, t_prof = time_plan(setd, p, args.steps, args.warmup, profile=True)
     if not ok:
         print("bench: the batched run did not complete cleanly", file=sys.stderr)
         sys.exit(1)
@@ -165,6 +179,7 @@ def main():
                     "alg_bytes": float(info.pass_bytes[i]),
                     "gbs": float(info.pass_bytes[i] / (tot_ms[i] / cnt[i] * 1e-3) / 1e9)}
                    for i in range(len(tot_ms))],
+        "timed_with_events_ms_per_step": 1e3 * t_prof / args.steps,
         "step_alg_bytes": float(info.alg_bytes_per_step),
         "step_frac": float(info.alg_bytes_per_step / (elapsed / args.steps) / 1e9 / PEAK_HBM_GBS),
     }
@@ -184,7 +199,7 @@ def main():
     if not args.no_fp64:
         p64 = W.problem(W.CONFIG_B, precision=64, realizations=1)
         k64 = max(args.steps, 200)
-        e64, _, info64, ok64 = time_plan(setd, p64, k64, args.warmup, profile=False)
+        e64, _, info64, ok64, _ = time_plan(setd, p64, k64, args.warmup, profile=False)
         v64 = float(info64.site_updates_per_step) * k64 / e64
         line["fp64_plain"] = {"workload": "Model B 512x512, SETD2, complex128, 1 realization",
                               "value": v64, "ms_per_step": 1e3 * e64 / k64, "ok": bool(ok64)}

@@ -212,8 +212,15 @@ __device__ __forceinline__ unsigned xcd_logical(unsigned L, unsigned G)
 // Z_k = A_k + i B_k (k <= N/2) and conj(A_{N-k}) + i conj(B_{N-k}) above; the
 // forward splits Z back into A_k = (Z_k + conj Z_{N-k})/2 and
 // B_k = (Z_k - conj Z_{N-k})/(2i).  Block: lpw row pairs x N/8 threads.
-// KIND: 0 = phi^3 (Model A/B) step, 1 = KPZ step, 2 = initial condition
-template <typename T, int N, int PAD, int KIND>
+// Rows are read and written with buffer accesses relative to the block's first
+// row (the resource covers the block's rows that exist); a lane whose bin has
+// no stored mode uses BUF_OOB, reads zero and writes nothing, so the loads are
+// unconditional and all in flight together.
+// KIND: 0 = phi^3 (Model A/B) step, 1 = KPZ step, 2 = initial condition.
+// DA: the 2/3 rule is on; then bins q = 0, 1 (k < N/4) always hold a stored
+// mode, q = 6, 7 (k >= 3N/4) always its mirror, q = 3, 4 never any, and only
+// q = 0..2 are written back, all decided at compile time.
+template <typename T, int N, int PAD, int KIND, bool DA>
 __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
 {
     const Item it = a.items[blockIdx.y];
@@ -221,6 +228,7 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int TPL = N / 8;
+    constexpr uint32_t ES = sizeof(cx<T>);
     const int tid = threadIdx.x;
     const int l = tid / TPL, t = tid - l * TPL;
     const int pair = blockIdx.x * a.lpw + l;
@@ -232,8 +240,28 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
     line_tw_load(tw, t, twid<T>(last == 1 ? it.tw1 : it.tw2));
     const int pitch = g.pitch;
     const int K = g.kp[last];
-    cx<T>* __restrict__ buf = reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big);
-    const size_t r0 = (size_t)(2 * pair) * pitch, r1 = r0 + pitch;
+    // rows of this block: 2 lpw from row 2 blockIdx.x lpw, clipped to the array
+    const int row0 = 2 * blockIdx.x * a.lpw;
+    const int nrow = min(2 * a.lpw, a.nrows - row0);
+    const size_t boff = (size_t)row0 * pitch;
+    cx<T>* const bufp = reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big) + boff;
+    const rsrc_t rb = make_rsrc(bufp, (uint32_t)nrow * (uint32_t)pitch * ES);
+    // byte offsets of the pair's two rows within the block (per lane: a
+    // wavefront can hold several pairs); BUF_OOB plus a row offset stays out
+    // of range
+    const uint32_t o0 = (uint32_t)(2 * l) * (uint32_t)pitch * ES, o1 = o0 + (uint32_t)pitch * ES;
+    // stored column read for bin k (k itself, or N - k for the mirrored upper
+    // half), BUF_OOB where the bin has no stored mode
+    auto col_off = [&](int q) -> uint32_t {
+        const int k = t + q * TPL;
+        if (!valid) return BUF_OOB;
+        if (DA && q <= 1) return (uint32_t)k * ES;
+        if (DA && q >= 6) return (uint32_t)(N - k) * ES;
+        if (k <= K) return (uint32_t)k * ES;
+        if (k >= N - K) return (uint32_t)(N - k) * ES;
+        return BUF_OOB;
+    };
+    auto empty = [](int q) { return DA && (q == 3 || q == 4); };   // no stored mode in any lane
     const T inv = (T)it.inv_vol;
     cx<T> v[8];
 
@@ -254,23 +282,20 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
         }
     } else if constexpr (KIND == 1) {
         // |grad h|^2 with d0 h = IFFT[i k0 h] (from pre1) and d1 h = IFFT[i k1 h]
-        const cx<T>* __restrict__ buf2 = reinterpret_cast<const cx<T>*>(it.pre1);
+        const rsrc_t rb2 = make_rsrc(reinterpret_cast<cx<T>*>(it.pre1) + boff, (uint32_t)nrow * (uint32_t)pitch * ES);
         const T dkl = (T)it.dk[last];
         T gsq[2][8];
         cx<T> A[2][8], X[2][8];
 #pragma unroll
         for (int s = 0; s < 2; s++) {
-            const size_t rr = s ? r1 : r0;
 #pragma unroll
             for (int q = 0; q < 8; q++) {
-                const int k = t + q * TPL;
-                const int m = (k <= K) ? k : N - k;
                 A[s][q] = czero<T>();
                 X[s][q] = czero<T>();
-                if (valid && (k <= K || k >= N - K)) {
-                    A[s][q] = buf2[rr + m];
-                    X[s][q] = buf[rr + m];
-                }
+                if (empty(q)) continue;
+                const uint32_t c = col_off(q);
+                A[s][q] = bload<T>(rb2, c + (s ? o1 : o0), 0);
+                X[s][q] = bload<T>(rb, c + (s ? o1 : o0), 0);
             }
         }
 #pragma unroll
@@ -279,7 +304,8 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
             for (int q = 0; q < 8; q++) {
                 const int k = t + q * TPL;
                 cx<T> z = czero<T>();
-                if (k <= K) {
+                if (empty(q)) {
+                } else if ((DA && q <= 1) || (!(DA && q >= 6) && k <= K)) {
                     cx<T> Aq = A[s][q];
                     const T kk = (2 * k == N) ? T(0) : dkl * (T)k;
                     cx<T> B = {-kk * X[s][q].y, kk * X[s][q].x};
@@ -288,7 +314,8 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
                         B.y = T(0);
                     }
                     z = {Aq.x - B.y, Aq.y + B.x};
-                } else if (k >= N - K) {
+                } else {
+                    // mirrored bins (zeros where nothing is stored)
                     const T kk = dkl * (T)(N - k);
                     const cx<T> B = {-kk * X[s][q].y, kk * X[s][q].x};
                     z = {A[s][q].x + B.y, B.x - A[s][q].y};
@@ -305,22 +332,32 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
 #pragma unroll
         for (int q = 0; q < 8; q++) v[q] = {gsq[0][q], gsq[1][q]};
     } else {
+        cx<T> A[8], B[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            A[q] = czero<T>();
+            B[q] = czero<T>();
+            if (empty(q)) continue;
+            const uint32_t c = col_off(q);
+            A[q] = bload<T>(rb, c + o0, 0);
+            B[q] = bload<T>(rb, c + o1, 0);
+        }
 #pragma unroll
         for (int q = 0; q < 8; q++) {
             const int k = t + q * TPL;
-            cx<T> z = czero<T>();
-            if (valid) {
-                if (k <= K) {
-                    cx<T> A = buf[r0 + k], B = buf[r1 + k];
-                    if (k == 0 || 2 * k == N) {
-                        A.y = T(0);
-                        B.y = T(0);
-                    }
-                    z = {A.x - B.y, A.y + B.x};
-                } else if (k >= N - K) {
-                    const cx<T> A = buf[r0 + (N - k)], B = buf[r1 + (N - k)];
-                    z = {A.x + B.y, B.x - A.y};
+            cx<T> z;
+            if (empty(q)) {
+                z = czero<T>();
+            } else if ((DA && q <= 1) || (!(DA && q >= 6) && k <= K)) {
+                cx<T> a0 = A[q], b0 = B[q];
+                if (k == 0 || 2 * k == N) {
+                    a0.y = T(0);
+                    b0.y = T(0);
                 }
+                z = {a0.x - b0.y, a0.y + b0.x};
+            } else {
+                // mirrored bins (zeros where nothing is stored)
+                z = {A[q].x + B[q].y, B[q].x - A[q].y};
             }
             v[q] = z;
         }
@@ -340,12 +377,13 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 8; q++) {
+        // under the 2/3 rule only q <= 2 (k < 3N/8) can hold a stored mode
+        if (DA && q > 2) continue;
         const int k = t + q * TPL;
-        if (valid && k <= K) {
-            const cx<T> Zk = L[lds_slot<PAD>(k)], Zm = L[lds_slot<PAD>((N - k) & (N - 1))];
-            buf[r0 + k] = {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y - Zm.y)};
-            buf[r1 + k] = {T(0.5) * (Zk.y + Zm.y), T(0.5) * (Zm.x - Zk.x)};
-        }
+        const cx<T> Zk = L[lds_slot<PAD>(k)], Zm = L[lds_slot<PAD>((N - k) & (N - 1))];
+        const uint32_t c = (valid && ((DA && q <= 1) || k <= K)) ? (uint32_t)k * ES : BUF_OOB;
+        bstore<T>(rb, c + o0, 0, {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y - Zm.y)});
+        bstore<T>(rb, c + o1, 0, {T(0.5) * (Zk.y + Zm.y), T(0.5) * (Zm.x - Zk.x)});
     }
 }
 
@@ -368,7 +406,18 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
     LineTw<T, N> tw;
     line_tw_load(tw, t, twid<T>(last == 1 ? it.tw1 : it.tw2));
     const int kept = g.kept[last], kp = g.kp[last];
-    cx<T>* __restrict__ buf = reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big) + (size_t)line * g.pitch;
+    constexpr uint32_t ES = sizeof(cx<T>);
+    // buffer resource over the block's lines that exist; per-lane offset of
+    // this lane's line, BUF_OOB for bins without a stored mode
+    const int line0 = blockIdx.x * a.lpw;
+    const int nline = min(a.lpw, a.nrows - line0);
+    const rsrc_t rb = make_rsrc(reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big) + (size_t)line0 * g.pitch,
+                                (uint32_t)nline * (uint32_t)g.pitch * ES);
+    const uint32_t lo = (uint32_t)l * (uint32_t)g.pitch * ES;
+    auto col_off = [&](int q) -> uint32_t {
+        const int i = stored_idx(t + q * TPL, N, kept, kp);
+        return (valid && i >= 0) ? lo + (uint32_t)i * ES : BUF_OOB;
+    };
     const T inv = (T)it.inv_vol;
     cx<T> v[8];
     if constexpr (IC) {
@@ -385,10 +434,7 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
         }
     } else {
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int i = stored_idx(t + q * TPL, N, kept, kp);
-            v[q] = (valid && i >= 0) ? buf[i] : czero<T>();
-        }
+        for (int q = 0; q < 8; q++) v[q] = bload<T>(rb, col_off(q), 0);
         fft_line<T, N, +1, PAD>(v, t, L, 1, tw);
         // |A|^2 A in real space (CGL)
 #pragma unroll
@@ -400,10 +446,7 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
     }
     fft_line<T, N, -1, PAD>(v, t, L, 1, tw);
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
-        const int i = stored_idx(t + q * TPL, N, kept, kp);
-        if (valid && i >= 0) buf[i] = v[q];
-    }
+    for (int q = 0; q < 8; q++) bstore<T>(rb, col_off(q), 0, v[q]);
 }
 
 // ---------------------------------------------------------------- axis-0 pass
@@ -627,10 +670,10 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
 // before it starts, and the unit noise is drawn while they are in flight (a
 // rolled loop with one Philox call site, its results rotated through a
 // register array); the coefficient table (L2-resident, shared by all
-// realizations) is read after the transform.  There is no LDS sweep.  (With
-// 512-thread blocks at four waves per SIMD the register budget allows only the
-// noise to be prepared early; state and history are then read after the
-// forward transform.)
+// realizations) is read after the transform.  There is no LDS sweep.  (At
+// four waves per SIMD the register budget allows only the noise to be
+// prepared early; state and history are then read after the forward
+// transform.)
 //
 // Under the 2/3 rule the bins of q = 0, 1, 6, 7 are always stored, those of
 // q = 3, 4 (3N0/8 <= j < 5N0/8) never, those of q = 2, 5 in part; a stored
@@ -641,14 +684,17 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
 // are still transformed: every column is an independent line.
 // KIND: 0 real field, 1 real field with the KPZ gradient, 2 complex field
 // (complex coefficient entries).
-// Occupancy target in waves per SIMD: at least two resident blocks per CU
-// (a CU has 4 SIMDs), so that one block's transforms overlap another's memory
-// traffic; three for small blocks of single precision.
+// Occupancy target in waves per SIMD (a CU has 4 SIMDs): resident blocks per
+// CU times waves per block over 4, with two blocks of 512 threads (one
+// block's transforms overlapping another's memory traffic), three of 256, and
+// one of 1024; double precision, with twice the registers, one block of 512
+// or two of 256.
 template <typename T, int NTHR>
 constexpr int axis0r_waves()
 {
     constexpr int w = NTHR / 64;   // waves per block
-    return sizeof(T) == 8 ? (w >= 4 ? w / 2 : 2) : (w >= 8 ? w / 2 : 3);
+    constexpr int blocks = sizeof(T) == 8 ? (w >= 8 ? 1 : 2) : (w >= 16 ? 1 : (w >= 8 ? 2 : 3));
+    return blocks * w / 4 > 1 ? blocks * w / 4 : 1;
 }
 
 template <typename T, int N0, int TILE, int PAD, int KIND>

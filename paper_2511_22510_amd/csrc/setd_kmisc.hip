@@ -163,7 +163,7 @@ __global__ void k_obs_mean(int nb, const double* skacc, double* out)
 void axis_shape(int precision, int n, int var, int* tile, int* lpt)
 {
     const int tm = (precision == 32) ? (n <= 512 ? 16 : 8) : (n <= 512 ? 8 : 4);
-    static const int tl[6] = {1, 1, 1, 2, 2, 4};
+    static const int tl[6] = {1, 1, 1, 2, 2, 1};
     static const int lp[6] = {2, 1, 4, 1, 1, 1};
     const int v = (var >= 0 && var < 6) ? var : 0;
     *tile = tm / tl[v] > 0 ? tm / tl[v] : 1;

@@ -7,7 +7,7 @@
 //              {(tm, 2), (tm, 1), (tm, 4), (tm/2, 1)}, tm = tile_max, with LDS
 //              padding whenever the padded tile still fits 64 KiB; the axis-0
 //              time step also has the register-update kernel k_axis0r with
-//              tile tm/2 (variant 4) or tm/4 (variant 5)
+//              tile tm/2 (variant 4) or tm (variant 5)
 #pragma once
 
 #include "setd_kernels.hpp"
@@ -49,11 +49,14 @@ static hipError_t launch_row_np(const Geo& g, const Item* items, int nitems, int
         if (mode == MODE_IC) hipLaunchKernelGGL((k_row_cplx<T, N, PAD, true>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((k_row_cplx<T, N, PAD, false>), grid, block, lds, s, a);
     } else if (mode == MODE_IC) {
-        hipLaunchKernelGGL((k_row_real<T, N, PAD, 2>), grid, block, lds, s, a);
+        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 2, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_row_real<T, N, PAD, 2, false>), grid, block, lds, s, a);
     } else if (kpz) {
-        hipLaunchKernelGGL((k_row_real<T, N, PAD, 1>), grid, block, lds, s, a);
+        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, false>), grid, block, lds, s, a);
     } else {
-        hipLaunchKernelGGL((k_row_real<T, N, PAD, 0>), grid, block, lds, s, a);
+        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, false>), grid, block, lds, s, a);
     }
     return hipGetLastError();
 }
@@ -144,8 +147,8 @@ static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int
             if (reg) return launch_axis0r<T, N, (TM >= 2 ? TM / 2 : 1)>(g, items, nitems, mode, sub, kpz, s);
             var = 3;
         } else if (var == 5) {
-            if (reg) return launch_axis0r<T, N, (TM >= 4 ? TM / 4 : 1)>(g, items, nitems, mode, sub, kpz, s);
-            var = 3;
+            if (reg) return launch_axis0r<T, N, TM>(g, items, nitems, mode, sub, kpz, s);
+            var = 0;
         }
     }
     switch (var) {
