@@ -104,11 +104,6 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-// cache-policy bits of the streaming stores
-#ifndef SETD_STORE_AUX
-#define SETD_STORE_AUX 0
-#endif
-
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -131,7 +126,7 @@ __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, c
         u32x2 u;
         u.x = __float_as_uint(v.x);
         u.y = __float_as_uint(v.y);
-        __builtin_amdgcn_raw_buffer_store_b64(u, r, (int)voff, (int)soff, SETD_STORE_AUX);
+        __builtin_amdgcn_raw_buffer_store_b64(u, r, (int)voff, (int)soff, 0);
     } else {
         const unsigned long long a = (unsigned long long)__double_as_longlong(v.x);
         const unsigned long long b = (unsigned long long)__double_as_longlong(v.y);
@@ -140,7 +135,7 @@ __device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, c
         u.y = (unsigned)(a >> 32);
         u.z = (unsigned)b;
         u.w = (unsigned)(b >> 32);
-        __builtin_amdgcn_raw_buffer_store_b128(u, r, (int)voff, (int)soff, SETD_STORE_AUX);
+        __builtin_amdgcn_raw_buffer_store_b128(u, r, (int)voff, (int)soff, 0);
     }
 }
 
@@ -376,67 +371,6 @@ template <typename T, int N, int SIGN, int PAD>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[8], int t, cx<T>* lds, int stride, const LineTw<T, N>& tw)
 {
     fft_lines<T, N, SIGN, PAD, 1>(reinterpret_cast<cx<T>(&)[1][8]>(v), t, lds, stride, 0, tw);
-}
-
-// Twiddle powers w^r (r = 1..7) of the radix-8 stage after NS combined points,
-// w = exp(-2 pi i (t mod NS) / (8 NS)): each is the table entry
-// tab[r (t mod NS) N / (8 NS)] (index below N), so all seven are read instead
-// of formed by products.
-template <typename T, int N, int NS>
-__device__ __forceinline__ void tw_powers(cx<T> (&p)[7], const cx<T>* tab, int t)
-{
-    const uint32_t b = (uint32_t)((t & (NS - 1)) * (N / (8 * NS)));
-#pragma unroll
-    for (int r = 1; r < 8; r++) p[r - 1] = gload<T>(tab, (uint32_t)r * b * (uint32_t)sizeof(cx<T>));
-}
-
-template <typename T, int SIGN>
-__device__ __forceinline__ void fft_stage8_pw(cx<T>* v, const cx<T> (&p)[7])
-{
-#pragma unroll
-    for (int r = 1; r < 8; r++) v[r] = (SIGN < 0) ? cmul(v[r], p[r - 1]) : cmulc(v[r], p[r - 1]);
-    dft8<SIGN>(v);
-}
-
-// The same transform as fft_lines with the twiddle powers read from the table
-// tab[k] = exp(-2 pi i k / N): fewer arithmetic instructions, more loads (each
-// stage's powers are requested before the exchange that precedes the stage).
-template <typename T, int N, int SIGN, int PAD, int NL>
-__device__ __forceinline__ void fft_lines_tab(cx<T> (&v)[NL][8], int t, cx<T>* lds, int stride, int lstep,
-                                              const cx<T>* tab)
-{
-    static_assert(N >= 8 && (N & (N - 1)) == 0, "power-of-two line length >= 8");
-    constexpr int R0 = FftPlan<N>::R0;
-    constexpr int NST = FftPlan<N>::NST;
-#pragma unroll
-    for (int k = 0; k < NL; k++) fft_stage0<T, N, R0, SIGN>(v[k]);
-    if constexpr (NST > 1) {
-        cx<T> p[7];
-        tw_powers<T, N, R0>(p, tab, t);
-        fft_exchange<T, N, R0, 1, PAD, NL>(v, t, lds, stride, lstep);
-#pragma unroll
-        for (int k = 0; k < NL; k++) fft_stage8_pw<T, SIGN>(v[k], p);
-    }
-    if constexpr (NST > 2) {
-        cx<T> p[7];
-        tw_powers<T, N, R0 * 8>(p, tab, t);
-        fft_exchange<T, N, 8, R0, PAD, NL>(v, t, lds, stride, lstep);
-#pragma unroll
-        for (int k = 0; k < NL; k++) fft_stage8_pw<T, SIGN>(v[k], p);
-    }
-    if constexpr (NST > 3) {
-        cx<T> p[7];
-        tw_powers<T, N, R0 * 64>(p, tab, t);
-        fft_exchange<T, N, 8, R0 * 8, PAD, NL>(v, t, lds, stride, lstep);
-#pragma unroll
-        for (int k = 0; k < NL; k++) fft_stage8_pw<T, SIGN>(v[k], p);
-    }
-}
-
-template <typename T, int N, int SIGN, int PAD>
-__device__ __forceinline__ void fft_line_tab(cx<T> (&v)[8], int t, cx<T>* lds, int stride, const cx<T>* tab)
-{
-    fft_lines_tab<T, N, SIGN, PAD, 1>(reinterpret_cast<cx<T>(&)[1][8]>(v), t, lds, stride, 0, tab);
 }
 
 // ---------------------------------------------------------------- Philox
