@@ -164,6 +164,18 @@ setd_status Plan::init(const setd_desc& desc)
     S = (size_t)g.kept[0] * k1 * g.pitch;
     P = (size_t)g.n[0] * k1 * g.pitch;
     B = (d.ndim == 3) ? (size_t)g.n[0] * g.n[1] * g.pitch : 0;
+    // Realizations of an array lie an odd multiple of 256 bytes apart: blocks
+    // that work on the same columns of different realizations at the same
+    // time then reach different HBM channels instead of addresses that agree
+    // in all low bits (the unpadded sizes are multiples of 64 KiB).
+    auto real_stride = [](size_t bytes) {
+        size_t s = round_up(bytes ? bytes : 1, 256);
+        if ((s / 256) % 2 == 0) s += 256;
+        return s;
+    };
+    Sb = real_stride(S * elt);
+    Pb = real_stride(P * elt);
+    Bb = B ? real_stride(B * elt) : 0;
 
     // workspace layout, every buffer 256-byte aligned
     size_t off = 0;
@@ -184,12 +196,12 @@ setd_status Plan::init(const setd_desc& desc)
     lay.acc = take((size_t)3 * nbins * 8);
     lay.skacc = take((size_t)(2 * nbins + 1) * 8);
     lay.out = take((size_t)3 * nbins * 8);
-    lay.phi = take((size_t)R * S * elt);
-    lay.prev = (d.order == 2) ? take((size_t)R * S * elt) : 0;
-    lay.pre0 = take((size_t)R * P * elt);
-    lay.pre1 = (d.nl == NL_KPZ) ? take((size_t)R * P * elt) : 0;
-    lay.big = B ? take((size_t)R * B * elt) : 0;
-    lay.snap = take((size_t)R * S * elt);
+    lay.phi = take((size_t)R * Sb);
+    lay.prev = (d.order == 2) ? take((size_t)R * Sb) : 0;
+    lay.pre0 = take((size_t)R * Pb);
+    lay.pre1 = (d.nl == NL_KPZ) ? take((size_t)R * Pb) : 0;
+    lay.big = B ? take((size_t)R * Bb) : 0;
+    lay.snap = take((size_t)R * Sb);
     lay.total = off;
     return SETD_OK;
 }
@@ -303,12 +315,12 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
     items.assign(R, Item{});
     for (int r = 0; r < R; r++) {
         Item& it = items[r];
-        it.phi = ws + lay.phi + (size_t)r * S * elt;
-        it.prev = (d.order == 2) ? ws + lay.prev + (size_t)r * S * elt : nullptr;
-        it.pre0 = ws + lay.pre0 + (size_t)r * P * elt;
-        it.pre1 = (d.nl == NL_KPZ) ? ws + lay.pre1 + (size_t)r * P * elt : nullptr;
-        it.big = B ? ws + lay.big + (size_t)r * B * elt : nullptr;
-        it.snap = ws + lay.snap + (size_t)r * S * elt;
+        it.phi = ws + lay.phi + (size_t)r * Sb;
+        it.prev = (d.order == 2) ? ws + lay.prev + (size_t)r * Sb : nullptr;
+        it.pre0 = ws + lay.pre0 + (size_t)r * Pb;
+        it.pre1 = (d.nl == NL_KPZ) ? ws + lay.pre1 + (size_t)r * Pb : nullptr;
+        it.big = B ? ws + lay.big + (size_t)r * Bb : nullptr;
+        it.snap = ws + lay.snap + (size_t)r * Sb;
         it.coef = ws + ((d.precision == 32) ? lay.coef32 : lay.coef64);
         const size_t* tw = (d.precision == 32) ? lay.tw32 : lay.tw64;
         it.tw0 = ws + tw[0];
@@ -383,12 +395,12 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
         return SETD_OK;
     };
     setd_status st;
-    if ((st = zero(lay.phi, (size_t)R * S * elt)) != SETD_OK) return st;
-    if (d.order == 2 && (st = zero(lay.prev, (size_t)R * S * elt)) != SETD_OK) return st;
-    if ((st = zero(lay.pre0, (size_t)R * P * elt)) != SETD_OK) return st;
-    if (d.nl == NL_KPZ && (st = zero(lay.pre1, (size_t)R * P * elt)) != SETD_OK) return st;
-    if (B && (st = zero(lay.big, (size_t)R * B * elt)) != SETD_OK) return st;
-    if ((st = zero(lay.snap, (size_t)R * S * elt)) != SETD_OK) return st;
+    if ((st = zero(lay.phi, (size_t)R * Sb)) != SETD_OK) return st;
+    if (d.order == 2 && (st = zero(lay.prev, (size_t)R * Sb)) != SETD_OK) return st;
+    if ((st = zero(lay.pre0, (size_t)R * Pb)) != SETD_OK) return st;
+    if (d.nl == NL_KPZ && (st = zero(lay.pre1, (size_t)R * Pb)) != SETD_OK) return st;
+    if (B && (st = zero(lay.big, (size_t)R * Bb)) != SETD_OK) return st;
+    if ((st = zero(lay.snap, (size_t)R * Sb)) != SETD_OK) return st;
 
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
     if (d.ic_kind == 1) {
@@ -627,7 +639,7 @@ setd_status Plan::observe(int kind, double* out, size_t cap, size_t* len)
         n_out = (size_t)3 * nb;
         break;
     case SETD_OBS_SNAPSHOT: {
-        SETD_HIP(launch_copy(ws + lay.snap, ws + lay.phi, (size_t)R * S * elt, stream));
+        SETD_HIP(launch_copy(ws + lay.snap, ws + lay.phi, (size_t)R * Sb, stream));
         have_snap = true;
         Ctrl c0;
         SETD_HIP(hipMemcpyAsync(&c0, ws + lay.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
@@ -672,7 +684,7 @@ setd_status Plan::get_block(size_t off, int r, double* out, size_t cap)
     if (r < 0 || r >= R) return fail(SETD_E_INVAL, "realization %d out of range", r);
     if (!out || cap < 2 * nspec) return fail(SETD_E_INVAL, "output needs %zu doubles", 2 * nspec);
     std::vector<char> host(S * elt);
-    SETD_HIP(hipMemcpyAsync(host.data(), ws + off + (size_t)r * S * elt, S * elt, hipMemcpyDeviceToHost, stream));
+    SETD_HIP(hipMemcpyAsync(host.data(), ws + off + (size_t)r * Sb, S * elt, hipMemcpyDeviceToHost, stream));
     SETD_HIP(hipStreamSynchronize(stream));
     scatter(host.data(), out);
     return SETD_OK;
@@ -740,7 +752,7 @@ setd_status Plan::set_field(int r, const double* in, size_t len)
             }
         }
     }
-    SETD_HIP(hipMemcpyAsync(ws + lay.phi + (size_t)r * S * elt, host.data(), S * elt, hipMemcpyHostToDevice, stream));
+    SETD_HIP(hipMemcpyAsync(ws + lay.phi + (size_t)r * Sb, host.data(), S * elt, hipMemcpyHostToDevice, stream));
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items) + r;
     setd_status st = (d.precision == 32) ? launch_sync_t<float>(*this, items_dev, 1, stream)
                                          : launch_sync_t<double>(*this, items_dev, 1, stream);

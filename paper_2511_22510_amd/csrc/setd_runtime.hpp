@@ -47,6 +47,7 @@ struct Plan {
     double dk[3] = {0, 0, 0};
     double lat = 1.0, vol = 1.0;
     size_t S = 0, P = 0, B = 0;   // complex elements per realization: state, pre, big
+    size_t Sb = 0, Pb = 0, Bb = 0;// bytes from one realization's array to the next
     size_t elt = 0;               // bytes per complex element
     size_t nspec = 0;             // unpruned spectral length per realization
     size_t nreal = 0;             // lattice sites per realization

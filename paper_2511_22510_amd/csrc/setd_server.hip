@@ -200,7 +200,7 @@ void setd_server::finish(Job* j)
     st = p.observe(SETD_OBS_STEP, buf.data(), buf.size(), &len);
     if (st == SETD_OK || st == SETD_E_NONFINITE) j->obs_step.assign(buf.begin(), buf.begin() + len);
     if (p.nonfinite_any(&flag) != SETD_OK) st = SETD_E_DEVICE;
-    std::vector<char> raw((size_t)p.R * p.S * p.elt);
+    std::vector<char> raw((size_t)p.R * p.Sb);
     if (hipMemcpyAsync(raw.data(), p.ws + p.lay.phi, raw.size(), hipMemcpyDeviceToHost, stream) == hipSuccess &&
         hipStreamSynchronize(stream) == hipSuccess) {
         j->final_state.swap(raw);
@@ -424,7 +424,7 @@ setd_status setd_job_get_field(setd_server* s, setd_job job, int realization, do
     const Plan& p = *j->plan;
     if (realization < 0 || realization >= p.R) return fail(SETD_E_INVAL, "realization out of range");
     if (cap < 2 * p.nspec) return fail(SETD_E_INVAL, "output needs %zu doubles", 2 * p.nspec);
-    p.scatter(j->final_state.data() + (size_t)realization * p.S * p.elt, host_out);
+    p.scatter(j->final_state.data() + (size_t)realization * p.Sb, host_out);
     return SETD_OK;
 }
 
