@@ -108,6 +108,18 @@ typedef struct {
     int ic_kind;              /* 0: phi = 0; 1: i.i.d. N(0, ic_sigma^2) per site
                                  (complex fields: ic_sigma (z1 + i z2))             */
     double ic_sigma;
+    int history_readback;     /* SETD2 storage.  0 (default): each realization
+                                 keeps, beside pre, only the carry
+                                 Y_n = E phi_n + w_b F_{n-1} + G eta_n (Eq. SETD2
+                                 regrouped, the noise of step n drawn one step
+                                 early), so a step moves one stored array less;
+                                 phi is recovered from pre when read, and
+                                 setd_get_history returns SETD_E_UNSUPPORTED.
+                                 1: phi and F_{n-1} are stored separately and
+                                 setd_get_history works.  Plans without the 2/3
+                                 rule, SETD1 plans, and plans whose per-
+                                 realization arrays reach 2 GiB always use the
+                                 separate storage.                                 */
 } setd_desc;
 
 /* Derived sizes of a plan (filled by setd_plan_info). */
@@ -187,7 +199,9 @@ setd_status setd_get_field(setd_plan* plan, int realization, double* host_out, s
 setd_status setd_set_field(setd_plan* plan, int realization, const double* host_in, size_t len);
 
 /* Copy realization r's previous nonlinear term F_{n-1} (SETD2 history, layout
-   above, already multiplied by the model prefactor) into host_out. */
+   above, already multiplied by the model prefactor) into host_out.
+   SETD_E_UNSUPPORTED when the plan keeps only the combined carry
+   (history_readback 0, see setd_desc). */
 setd_status setd_get_history(setd_plan* plan, int realization, double* host_out, size_t cap);
 
 /* Set the step index n of every realization (checkpoint restart); the next

@@ -193,6 +193,8 @@ struct LinArgs {
     const Item* items;
     int total;   // stored elements per realization
     int sub;
+    int mode;          // LIN_STEP / LIN_CARRY / LIN_RENOISE
+    int64_t new_step;  // LIN_RENOISE: the step index the carry's noise is re-drawn for
 };
 
 template <typename T>
@@ -460,6 +462,9 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
 //            noise of step n -> phi, F_{n-1} -> inverse FFT -> pre.
 // MODE_IC:   pre (forward-transformed initial field) -> forward FFT -> phi.
 // MODE_SYNC: phi -> inverse FFT -> pre.
+// MODE_RECOVER: pre -> forward FFT / N0 -> phi, pre left as it is (the state
+//            of a plan that keeps the SETD2 carry instead of phi; pre holds
+//            the unscaled axis-0 inverse of phi, N0 a power of two).
 template <typename T, int N0, int TILE, int PAD, bool KPZ, int LPT>
 __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
 {
@@ -588,6 +593,9 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
                 const size_t si = (size_t)i0 * lstride + plane + cc;
                 if (a.mode == MODE_IC) {
                     phi[si] = *slot;
+                } else if (a.mode == MODE_RECOVER) {
+                    // pre holds the unscaled axis-0 inverse of phi: divide by N0
+                    phi[si] = (T(1) / T(N0)) * *slot;
                 } else {
                     int jlm, alm;
                     last_pos(colm, jlm, alm);
@@ -618,6 +626,8 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
         }
         // one flag update per block
         if (__syncthreads_or(bad) && tid == 0) atomicOr(&it.ctrl->nonfinite, 1);
+        // recovery reads pre and writes phi only
+        if (a.mode == MODE_RECOVER) return;
 #pragma unroll
         for (int k = 0; k < LPT; k++) {
 #pragma unroll
@@ -684,6 +694,14 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
 // are still transformed: every column is an independent line.
 // KIND: 0 real field, 1 real field with the KPZ gradient, 2 complex field
 // (complex coefficient entries).
+//
+// LEAN (SETD2 only): the realization stores, in place of phi and F_{n-1}, the
+// carry Y_n = E phi_n + w_b F_{n-1} + G eta_n (Eq. SETD2 regrouped; the array
+// of F_{n-1} holds it).  A step computes phi_{n+1} = Y_n + w_a F_n (w_a + w_b on
+// a first step, where F_{-1} = F_0), transforms phi_{n+1} back into pre, and
+// stores Y_{n+1} = E phi_{n+1} + w_b F_n + G eta_{n+1}, the noise of the next
+// step drawn now: one stored array read and written instead of two.
+//
 // Occupancy target in waves per SIMD (a CU has 4 SIMDs): resident blocks per
 // CU times waves per block over 4, with two blocks of 512 threads (one
 // block's transforms overlapping another's memory traffic), three of 256, and
@@ -697,7 +715,7 @@ constexpr int axis0r_waves()
     return blocks * w / 4 > 1 ? blocks * w / 4 : 1;
 }
 
-template <typename T, int N0, int TILE, int PAD, int KIND>
+template <typename T, int N0, int TILE, int PAD, int KIND, bool LEAN>
 __global__ void __launch_bounds__(TILE * N0 / 8)
 __attribute__((amdgpu_waves_per_eu(axis0r_waves<T, TILE * N0 / 8>())))
 k_axis0r(AxisArgs a)
@@ -764,14 +782,19 @@ k_axis0r(AxisArgs a)
     // forward transform, with the coefficients, to stay within the register
     // budget
     constexpr bool EARLY = axis0r_waves<T, TILE * N0 / 8>() < 4;
+    // state and history; with LEAN the carry Y_n in place of the state
     auto load_state = [&]() {
 #pragma unroll
         for (int q = 0; q < 8; q++) {
             ph[q] = czero<T>();
             pv[q] = czero<T>();
             if (live(q)) {
-                ph[q] = bload<T>(rphi, voff(q), soff(q));
-                if (it.order == 2) pv[q] = bload<T>(rprev, voff(q), soff(q));
+                if constexpr (LEAN) {
+                    ph[q] = bload<T>(rprev, voff(q), soff(q));
+                } else {
+                    ph[q] = bload<T>(rphi, voff(q), soff(q));
+                    if (it.order == 2) pv[q] = bload<T>(rprev, voff(q), soff(q));
+                }
             }
         }
     };
@@ -785,7 +808,8 @@ k_axis0r(AxisArgs a)
     for (int k = 0; k < 6; k++) {
         const int j0 = t + (k < 3 ? k : k + 2) * TPL;
         cx<T> e = czero<T>();
-        if (cv && stored_idx(j0, N0, kept0, kp0) >= 0) e = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)nstep);
+        if (cv && stored_idx(j0, N0, kept0, kp0) >= 0)
+            e = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)(LEAN ? nstep + 1 : nstep));
 #pragma unroll
         for (int s = 0; s < 5; s++) ez[s] = ez[s + 1];
         ez[5] = e;
@@ -850,6 +874,9 @@ k_axis0r(AxisArgs a)
             if constexpr (EARLY) {
                 gph[u] = ph[q];
                 gpv[u] = pv[q];
+            } else if constexpr (LEAN) {
+                gph[u] = bload<T>(rprev, voff(q), soff(q));
+                gpv[u] = czero<T>();
             } else {
                 gph[u] = bload<T>(rphi, voff(q), soff(q));
                 gpv[u] = it.order == 2 ? bload<T>(rprev, voff(q), soff(q)) : czero<T>();
@@ -865,15 +892,30 @@ k_axis0r(AxisArgs a)
             const T k2 = k0 * k0 + km * km + kl * kl;
             const cx<T> F = cmul(nl_pref<T>(it, k2), v[0][q]);
             cx<T> nw;
-            if constexpr (CC) {
-                nw = cmul(cf[u].E, gph[u]) + cmul(cf[u].wa, F) + cf[u].G * eta[q];
-                if (it.order == 2) nw = nw + cmul(cf[u].wb, use_prev ? gpv[u] : F);
+            if constexpr (LEAN) {
+                // phi_{n+1} = Y_n + w F_n, Y_{n+1} = E phi_{n+1} + w_b F_n + G eta_{n+1}
+                cx<T> y;
+                if constexpr (CC) {
+                    const cx<T> w = hp ? cf[u].wa : cf[u].wa + cf[u].wb;
+                    nw = gph[u] + cmul(w, F);
+                    y = cmul(cf[u].E, nw) + cmul(cf[u].wb, F) + cf[u].G * eta[q];
+                } else {
+                    const T w = hp ? cf[u].wa.x : cf[u].wa.x + cf[u].wb.x;
+                    nw = gph[u] + w * F;
+                    y = cf[u].E.x * nw + cf[u].wb.x * F + cf[u].G * eta[q];
+                }
+                bstore<T>(rprev, voff(q), soff(q), y);
             } else {
-                nw = cf[u].E.x * gph[u] + cf[u].wa.x * F + cf[u].G * eta[q];
-                if (it.order == 2) nw = nw + cf[u].wb.x * (use_prev ? gpv[u] : F);
+                if constexpr (CC) {
+                    nw = cmul(cf[u].E, gph[u]) + cmul(cf[u].wa, F) + cf[u].G * eta[q];
+                    if (it.order == 2) nw = nw + cmul(cf[u].wb, use_prev ? gpv[u] : F);
+                } else {
+                    nw = cf[u].E.x * gph[u] + cf[u].wa.x * F + cf[u].G * eta[q];
+                    if (it.order == 2) nw = nw + cf[u].wb.x * (use_prev ? gpv[u] : F);
+                }
+                if (it.order == 2) bstore<T>(rprev, voff(q), soff(q), F);
+                bstore<T>(rphi, voff(q), soff(q), nw);
             }
-            if (it.order == 2) bstore<T>(rprev, voff(q), soff(q), F);
-            bstore<T>(rphi, voff(q), soff(q), nw);
             bad |= st && !(isfinite(nw.x) && isfinite(nw.y));
             v[0][q] = st ? nw : czero<T>();
         }
@@ -1006,13 +1048,23 @@ __global__ void __launch_bounds__(256) k_linear(LinArgs a)
             const Coef<T> cf = load_coef<T>(it, key);
             const cx<T> eta = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)nstep);
             cx<T>* phi = reinterpret_cast<cx<T>*>(it.phi);
-            const cx<T> nw = cmul(cf.E, phi[idx]) + cf.G * eta;
-            phi[idx] = nw;
+            cx<T>* carry = reinterpret_cast<cx<T>*>(it.prev);
+            cx<T> nw;
+            if (a.mode == LIN_RENOISE) {
+                // the carry drew G eta_n; it gets G eta_new instead
+                const cx<T> eta2 = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)a.new_step);
+                nw = carry[idx] + cf.G * (eta2 - eta);
+                carry[idx] = nw;
+            } else {
+                nw = cmul(cf.E, phi[idx]) + cf.G * eta;
+                if (a.mode == LIN_CARRY) carry[idx] = nw;
+                else phi[idx] = nw;
+            }
             bad = !(isfinite(nw.x) && isfinite(nw.y));
         }
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&it.ctrl->nonfinite, 1);
-    if (threadIdx.x == 0) advance_step(it.ctrl, gridDim.x, nstep);
+    if (a.mode == LIN_STEP && threadIdx.x == 0) advance_step(it.ctrl, gridDim.x, nstep);
 }
 
 // ---------------------------------------------------------------- FP64 observables

@@ -17,13 +17,25 @@ constexpr int pitch_align() { return sizeof(T) == 4 ? 16 : 8; }
 template <typename T>
 hipError_t launch_row(const Geo& g, const Item* items, int nitems, int mode, int sub, int var, int kpz,
                       hipStream_t s);
+// whether the register-update axis-0 kernel (buffer accesses into arrays of
+// under 2 GiB per realization, 2/3 rule on) can run a plan's time step
+inline bool axis0_register_ok(const Geo& g, size_t real_bytes)
+{
+    const size_t pre_bytes = (size_t)g.n[0] * (g.ndim == 3 ? g.kept[1] : 1) * g.pitch * 2 * real_bytes;
+    return g.dealias && pre_bytes < ((size_t)1 << 31);
+}
+
+// lean: the plan keeps the SETD2 carry instead of phi and F_{n-1} (needs
+// axis0_register_ok)
 template <typename T>
 hipError_t launch_axis0(const Geo& g, const Item* items, int nitems, int mode, int sub, int var, int kpz,
-                        hipStream_t s);
+                        int lean, hipStream_t s);
 template <typename T>
 hipError_t launch_axis1(const Geo& g, const Item* items, int nitems, int dir, int sub, int var, hipStream_t s);
+// mode LIN_STEP / LIN_CARRY / LIN_RENOISE (new_step: the re-drawn step index)
 template <typename T>
-hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, hipStream_t s);
+hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, int mode, int64_t new_step,
+                         hipStream_t s);
 template <typename T>
 hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind, int nbins, double vol,
                           double* acc, hipStream_t s);

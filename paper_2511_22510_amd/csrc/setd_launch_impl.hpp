@@ -113,7 +113,7 @@ static hipError_t launch_axis_nt(const Geo& g, const Item* items, int nitems, in
 // axis-0 pass with the update in registers (k_axis0r), one column per thread group
 template <typename T, int N, int TILE>
 static hipError_t launch_axis0r(const Geo& g, const Item* items, int nitems, int mode, int sub, bool kpz,
-                                hipStream_t s)
+                                bool lean, hipStream_t s)
 {
     constexpr int PAD = tile_pad<T, N, TILE>();
     AxisArgs a;
@@ -126,28 +126,36 @@ static hipError_t launch_axis0r(const Geo& g, const Item* items, int nitems, int
     dim3 grid(a.per_item * nitems);
     dim3 block(TILE * (N / 8));
     const size_t lds = (size_t)TILE * lds_len<N, PAD>() * 2 * sizeof(T);
-    if (g.cplx) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 2>), grid, block, lds, s, a);
-    else if (kpz) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 1>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 0>), grid, block, lds, s, a);
+    if (lean) {
+        if (g.cplx) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 2, true>), grid, block, lds, s, a);
+        else if (kpz) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 1, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 0, true>), grid, block, lds, s, a);
+    } else {
+        if (g.cplx) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 2, false>), grid, block, lds, s, a);
+        else if (kpz) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 1, false>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 0, false>), grid, block, lds, s, a);
+    }
     return hipGetLastError();
 }
 
 template <typename T, int N, bool AX0>
 static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int mode, int sub, int var,
-                                bool kpz, hipStream_t s)
+                                bool kpz, bool lean, hipStream_t s)
 {
     constexpr int TM = tile_max<T>(N);
     if constexpr (AX0) {
         // the register-update kernel does the time step under the 2/3 rule,
-        // with buffer accesses into arrays of under 2 GiB per realization;
-        // other modes and plans take the tile-sweep kernel
-        const size_t pre_bytes = (size_t)g.n[0] * (g.ndim == 3 ? g.kept[1] : 1) * g.pitch * 2 * sizeof(T);
-        const bool reg = mode == MODE_STEP && g.dealias && pre_bytes < ((size_t)1 << 31);
+        // with buffer accesses into arrays of under 2 GiB per realization
+        // (axis0_register_ok); other modes and plans take the tile-sweep
+        // kernel.  A plan keeping the SETD2 carry steps with the register
+        // kernel only.
+        const bool reg = mode == MODE_STEP && axis0_register_ok(g, sizeof(T));
+        if (reg && lean && var < 4) var = 4;
         if (var == 4) {
-            if (reg) return launch_axis0r<T, N, (TM >= 2 ? TM / 2 : 1)>(g, items, nitems, mode, sub, kpz, s);
+            if (reg) return launch_axis0r<T, N, (TM >= 2 ? TM / 2 : 1)>(g, items, nitems, mode, sub, kpz, lean, s);
             var = 3;
         } else if (var == 5) {
-            if (reg) return launch_axis0r<T, N, TM>(g, items, nitems, mode, sub, kpz, s);
+            if (reg) return launch_axis0r<T, N, TM>(g, items, nitems, mode, sub, kpz, lean, s);
             var = 0;
         }
     }
@@ -161,27 +169,31 @@ static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int
 
 template <typename T>
 hipError_t launch_axis0(const Geo& g, const Item* items, int nitems, int mode, int sub, int var, int kpz,
-                        hipStream_t s)
+                        int lean, hipStream_t s)
 {
-    SETD_DISPATCH_N(g.n[0], return (launch_axis_n<T, NN, true>(g, items, nitems, mode, sub, var, kpz != 0, s)));
+    SETD_DISPATCH_N(g.n[0], return (launch_axis_n<T, NN, true>(g, items, nitems, mode, sub, var, kpz != 0,
+                                                                lean != 0, s)));
     return hipSuccess;
 }
 
 template <typename T>
 hipError_t launch_axis1(const Geo& g, const Item* items, int nitems, int dir, int sub, int var, hipStream_t s)
 {
-    SETD_DISPATCH_N(g.n[1], return (launch_axis_n<T, NN, false>(g, items, nitems, dir, sub, var, false, s)));
+    SETD_DISPATCH_N(g.n[1], return (launch_axis_n<T, NN, false>(g, items, nitems, dir, sub, var, false, false, s)));
     return hipSuccess;
 }
 
 template <typename T>
-hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, hipStream_t s)
+hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, int mode, int64_t new_step,
+                         hipStream_t s)
 {
     LinArgs a;
     a.g = g;
     a.items = items;
     a.total = g.kept[0] * (g.ndim == 3 ? g.kept[1] : 1) * g.pitch;
     a.sub = sub;
+    a.mode = mode;
+    a.new_step = new_step;
     dim3 grid((a.total + 255) / 256, nitems);
     hipLaunchKernelGGL((k_linear<T>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
@@ -210,9 +222,9 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
 
 #define SETD_INSTANTIATE(T)                                                                                     \
     template hipError_t launch_row<T>(const Geo&, const Item*, int, int, int, int, int, hipStream_t);           \
-    template hipError_t launch_axis0<T>(const Geo&, const Item*, int, int, int, int, int, hipStream_t);         \
+    template hipError_t launch_axis0<T>(const Geo&, const Item*, int, int, int, int, int, int, hipStream_t);    \
     template hipError_t launch_axis1<T>(const Geo&, const Item*, int, int, int, int, hipStream_t);              \
-    template hipError_t launch_linear<T>(const Geo&, const Item*, int, int, hipStream_t);                       \
+    template hipError_t launch_linear<T>(const Geo&, const Item*, int, int, int, int64_t, hipStream_t);         \
     template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, hipStream_t);
 
 }  // namespace setd

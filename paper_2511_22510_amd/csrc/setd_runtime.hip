@@ -176,6 +176,8 @@ setd_status Plan::init(const setd_desc& desc)
     Sb = real_stride(S * elt);
     Pb = real_stride(P * elt);
     Bb = B ? real_stride(B * elt) : 0;
+    // SETD2 keeps only the carry unless F_{n-1} must stay readable
+    lean = d.order == 2 && !d.history_readback && d.nl != NL_NONE && axis0_register_ok(g, elt / 2);
 
     // workspace layout, every buffer 256-byte aligned
     size_t off = 0;
@@ -221,7 +223,7 @@ void Plan::pass_bytes(double* out) const
     const double e = (double)elt * R;
     const double kl = (double)g.kept[g.ndim - 1];
     const double st = (double)kept_modes;                 // stored modes
-    const double hist = (d.order == 2) ? 2.0 : 0.0;       // read + write F_{n-1}
+    const double hist = (d.order == 2 && !lean) ? 2.0 : 0.0;   // read + write F_{n-1} (lean: one carry array)
     if (d.nl == NL_NONE) {
         out[0] = 2.0 * st * e;
         return;
@@ -253,19 +255,19 @@ static setd_status launch_pass_t(const Plan& p, int i, const Item* items_dev, in
 {
     const Geo& g = p.g;
     if (p.d.nl == NL_NONE) {
-        SETD_HIP((launch_linear<T>(g, items_dev, nitems, sub, s)));
+        SETD_HIP((launch_linear<T>(g, items_dev, nitems, sub, LIN_STEP, 0, s)));
         return SETD_OK;
     }
     if (g.ndim == 2) {
         if (i == 0) SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.row, p.d.nl == NL_KPZ, s)));
-        else SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.ax0, p.d.nl == NL_KPZ, s)));
+        else SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.ax0, p.d.nl == NL_KPZ, p.lean, s)));
         return SETD_OK;
     }
     switch (i) {
     case 0: SETD_HIP((launch_axis1<T>(g, items_dev, nitems, +1, sub, p.tune.ax1, s))); break;
     case 1: SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.row, p.d.nl == NL_KPZ, s))); break;
     case 2: SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -1, sub, p.tune.ax1, s))); break;
-    default: SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.ax0, p.d.nl == NL_KPZ, s))); break;
+    default: SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.ax0, p.d.nl == NL_KPZ, p.lean, s))); break;
     }
     return SETD_OK;
 }
@@ -291,14 +293,40 @@ static setd_status launch_ic_t(const Plan& p, const Item* items_dev, int nitems,
     const Geo& g = p.g;
     SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_IC, 0, p.tune.row, 0, s)));
     if (g.ndim == 3) SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -1, 0, p.tune.ax1, s)));
-    SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_IC, 0, p.tune.ax0, p.d.nl == NL_KPZ, s)));
+    SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_IC, 0, p.tune.ax0, p.d.nl == NL_KPZ, 0, s)));
     return SETD_OK;
 }
 
 template <typename T>
 static setd_status launch_sync_t(const Plan& p, const Item* items_dev, int nitems, hipStream_t s)
 {
-    SETD_HIP((launch_axis0<T>(p.g, items_dev, nitems, MODE_SYNC, 0, p.tune.ax0, p.d.nl == NL_KPZ, s)));
+    SETD_HIP((launch_axis0<T>(p.g, items_dev, nitems, MODE_SYNC, 0, p.tune.ax0, p.d.nl == NL_KPZ, 0, s)));
+    return SETD_OK;
+}
+
+template <typename T>
+static setd_status launch_recover_t(const Plan& p, const Item* items_dev, int nitems, hipStream_t s)
+{
+    SETD_HIP((launch_axis0<T>(p.g, items_dev, nitems, MODE_RECOVER, 0, p.tune.ax0, p.d.nl == NL_KPZ, 0, s)));
+    return SETD_OK;
+}
+
+setd_status Plan::ensure_phi()
+{
+    if (!lean || phi_valid) return SETD_OK;
+    const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
+    setd_status st = (d.precision == 32) ? launch_recover_t<float>(*this, items_dev, R, stream)
+                                         : launch_recover_t<double>(*this, items_dev, R, stream);
+    if (st != SETD_OK) return st;
+    phi_valid = true;
+    return SETD_OK;
+}
+
+setd_status Plan::carry_init(const Item* items_dev, int nitems)
+{
+    if (!lean) return SETD_OK;
+    if (d.precision == 32) SETD_HIP((launch_linear<float>(g, items_dev, nitems, 0, LIN_CARRY, 0, stream)));
+    else SETD_HIP((launch_linear<double>(g, items_dev, nitems, 0, LIN_CARRY, 0, stream)));
     return SETD_OK;
 }
 
@@ -407,6 +435,8 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
         st = (d.precision == 32) ? launch_ic_t<float>(*this, items_dev, R, s) : launch_ic_t<double>(*this, items_dev, R, s);
         if (st != SETD_OK) return st;
     }
+    phi_valid = true;
+    if ((st = carry_init(items_dev, R)) != SETD_OK) return st;
     SETD_HIP(hipStreamSynchronize(s));
     bound = true;
     step_host = 0;
@@ -457,7 +487,7 @@ setd_status Plan::autotune()
         int r = 0, a0 = 0, a1 = 0;
         if (sscanf(pin, "%d,%d,%d", &r, &a0, &a1) == 3 && r >= 0 && r < 4 && a0 >= 0 && a0 < 6 && a1 >= 0 && a1 < 4) {
             tune.row = r;
-            tune.ax0 = a0;
+            tune.ax0 = (lean && a0 < 4) ? 4 : a0;   // a lean plan steps with the register kernel
             tune.ax1 = a1;
             return SETD_OK;
         }
@@ -483,16 +513,19 @@ setd_status Plan::autotune()
     // pass index in launch order for each tunable knob
     const int row_pass = (d.ndim == 2) ? 0 : 1;
     const int ax0_pass = (d.ndim == 2) ? 1 : 3;
-    struct Knob { int* var; int nvar; int pass; int pass2; };
-    // axis-0 variants 4 and 5 (register update) exist for dealiased plans
-    Knob knobs[3] = {{&tune.row, 4, row_pass, -1}, {&tune.ax0, g.dealias ? 6 : 4, ax0_pass, -1}, {&tune.ax1, 4, 0, 2}};
+    struct Knob { int* var; int first; int nvar; int pass; int pass2; };
+    // axis-0 variants 4 and 5 (register update) exist for dealiased plans, and
+    // are the only ones a plan keeping the SETD2 carry can step with
+    Knob knobs[3] = {{&tune.row, 0, 4, row_pass, -1},
+                     {&tune.ax0, lean ? 4 : 0, g.dealias ? 6 : 4, ax0_pass, -1},
+                     {&tune.ax1, 0, 4, 0, 2}};
     const int nknobs = (d.ndim == 3) ? 3 : 2;
     setd_status st = SETD_OK;
     for (int k = 0; k < nknobs && st == SETD_OK; k++) {
         Knob& kb = knobs[k];
         float best = 1e30f;
-        int best_v = 0;
-        for (int v = 0; v < kb.nvar && st == SETD_OK; v++) {
+        int best_v = kb.first;
+        for (int v = kb.first; v < kb.nvar && st == SETD_OK; v++) {
             *kb.var = v;
             auto run = [&]() -> setd_status {
                 setd_status s1 = launch_pass(kb.pass, items_dev, R, 0, stream);
@@ -533,6 +566,7 @@ setd_status Plan::step(int64_t n)
     if (n < 0) return fail(SETD_E_INVAL, "negative step count");
     if (step_host + n >= (int64_t)1 << 32) return fail(SETD_E_INVAL, "step index would exceed 2^32");
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
+    if (n > 0) phi_valid = !lean;
     for (int64_t i = 0; i < n; i++) {
         if (!profiling) {
             setd_status st = launch_step(items_dev, R, 0, stream);
@@ -601,6 +635,10 @@ setd_status Plan::observe(int kind, double* out, size_t cap, size_t* len)
     double* dout = reinterpret_cast<double*>(ws + lay.out);
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
     size_t n_out = 0;
+    if (kind != SETD_OBS_STEP && kind != SETD_OBS_SK_MEAN) {
+        const setd_status st0 = ensure_phi();
+        if (st0 != SETD_OK) return st0;
+    }
     auto reduce = [&](int red) -> setd_status {
         SETD_HIP(launch_fill64(acc, 3 * nb, 0.0, stream));
         if (d.precision == 32) SETD_HIP((launch_observe<float>(g, items_dev, R, red, nb, vol, acc, stream)));
@@ -758,6 +796,8 @@ setd_status Plan::set_field(int r, const double* in, size_t len)
                                          : launch_sync_t<double>(*this, items_dev, 1, stream);
     if (st != SETD_OK) return st;
     SETD_HIP(launch_ctrl_set(reinterpret_cast<Ctrl*>(ws + lay.ctrl) + r, 1, 0, 1, stream));
+    // a fresh state has no F_{n-1}: the carry restarts as E phi + G eta_n
+    if ((st = carry_init(items_dev, 1)) != SETD_OK) return st;
     SETD_HIP(hipStreamSynchronize(stream));
     return SETD_OK;
 }
@@ -766,6 +806,12 @@ setd_status Plan::set_step(int64_t s)
 {
     if (!bound) return fail(SETD_E_STATE, "plan not bound");
     if (s < 0 || s >= ((int64_t)1 << 32)) return fail(SETD_E_INVAL, "step index out of range");
+    if (lean) {
+        // the carry holds G eta of the old step index: re-draw it for step s
+        const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
+        if (d.precision == 32) SETD_HIP((launch_linear<float>(g, items_dev, R, 0, LIN_RENOISE, s, stream)));
+        else SETD_HIP((launch_linear<double>(g, items_dev, R, 0, LIN_RENOISE, s, stream)));
+    }
     SETD_HIP(launch_ctrl_set(reinterpret_cast<Ctrl*>(ws + lay.ctrl), R, s, 0, stream));
     SETD_HIP(hipStreamSynchronize(stream));
     step_host = s;
@@ -776,8 +822,8 @@ std::string class_key(const Plan& p)
 {
     char buf[160];
     const int kind = p.d.nl == NL_NONE ? 1 : (p.d.nl == NL_KPZ ? 2 : 0);
-    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%d|%d|%d", p.g.ndim, p.g.cplx, p.g.prec, p.g.dealias, p.g.n[0],
-             p.g.n[1], p.g.n[2], kind);
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%d|%d|%d|%d", p.g.ndim, p.g.cplx, p.g.prec, p.g.dealias, p.g.n[0],
+             p.g.n[1], p.g.n[2], kind, p.lean ? 1 : 0);
     return buf;
 }
 
@@ -868,6 +914,10 @@ setd_status setd_observe(setd_plan* plan, int kind, double* host_out, size_t cap
 setd_status setd_get_field(setd_plan* plan, int realization, double* host_out, size_t cap)
 {
     if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
+    if (plan->p.bound) {
+        const setd_status st = plan->p.ensure_phi();
+        if (st != SETD_OK) return st;
+    }
     return plan->p.get_block(plan->p.lay.phi, realization, host_out, cap);
 }
 
@@ -875,6 +925,8 @@ setd_status setd_get_history(setd_plan* plan, int realization, double* host_out,
 {
     if (!plan) return setd::fail(SETD_E_INVAL, "null plan");
     if (plan->p.d.order != 2) return setd::fail(SETD_E_INVAL, "SETD1 keeps no history");
+    if (plan->p.lean)
+        return setd::fail(SETD_E_UNSUPPORTED, "the plan keeps the SETD2 carry, not F_{n-1} (history_readback 0)");
     return plan->p.get_block(plan->p.lay.prev, realization, host_out, cap);
 }
 

@@ -33,7 +33,7 @@ struct Layout {
 // Kernel variants of a plan's passes (see setd_launch_impl.hpp).
 struct Tune {
     int row = 0;   // 0..3
-    int ax0 = 0;   // 0..3
+    int ax0 = 0;   // 0..5
     int ax1 = 0;   // 0..3
 };
 
@@ -57,6 +57,10 @@ struct Plan {
     hipStream_t stream = nullptr;
     bool bound = false;
     bool have_snap = false;
+    // SETD2 storage: the carry Y_n = E phi_n + w_b F_{n-1} + G eta_n in the
+    // F_{n-1} array, phi recovered from pre when read (phi_valid tracks it)
+    bool lean = false;
+    bool phi_valid = true;
     int64_t step_host = 0;        // steps queued so far (mirror of the device counter)
     std::vector<Item> items;      // host copy of the device item table
     // kernel timing (setd_profile)
@@ -83,6 +87,12 @@ struct Plan {
     setd_status set_field(int r, const double* in, size_t len);
     setd_status set_step(int64_t step);
     setd_status nonfinite_any(int* flag);
+    // lean plans: recover phi from pre for every realization if a step has
+    // run since the last recovery (other plans: nothing to do)
+    setd_status ensure_phi();
+    // lean plans: carry Y = E phi + G eta_n of nitems items from items_dev,
+    // n each realization's step index
+    setd_status carry_init(const Item* items_dev, int nitems);
     double alg_bytes_per_step() const;
     int passes_per_step() const;
 };

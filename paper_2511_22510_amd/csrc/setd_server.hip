@@ -192,6 +192,8 @@ void setd_server::finish(Job* j)
     int flag = 0;
     std::vector<double> buf(3 * (size_t)p.nbins + 8);
     size_t len = 0;
+    // a plan keeping the SETD2 carry recovers phi before it is read
+    const setd_status rec = p.ensure_phi();
     setd_status st = SETD_OK;
     if (p.iso && p.observe(SETD_OBS_SK, buf.data(), buf.size(), &len) != SETD_E_DEVICE)
         j->obs_sk.assign(buf.begin(), buf.begin() + len);
@@ -199,7 +201,7 @@ void setd_server::finish(Job* j)
         j->obs_width.assign(buf.begin(), buf.begin() + len);
     st = p.observe(SETD_OBS_STEP, buf.data(), buf.size(), &len);
     if (st == SETD_OK || st == SETD_E_NONFINITE) j->obs_step.assign(buf.begin(), buf.begin() + len);
-    if (p.nonfinite_any(&flag) != SETD_OK) st = SETD_E_DEVICE;
+    if (p.nonfinite_any(&flag) != SETD_OK || rec != SETD_OK) st = SETD_E_DEVICE;
     std::vector<char> raw((size_t)p.R * p.Sb);
     if (hipMemcpyAsync(raw.data(), p.ws + p.lay.phi, raw.size(), hipMemcpyDeviceToHost, stream) == hipSuccess &&
         hipStreamSynchronize(stream) == hipSuccess) {
@@ -262,7 +264,10 @@ setd_status setd_server::tick(std::vector<Job*>& act, int* steps_taken)
         const double per = dt / maxk;
         est_step_s = (est_step_s > 0) ? 0.7 * est_step_s + 0.3 * per : per;
     }
-    for (Job* j : act) j->done_steps += j->steps_tick;
+    for (Job* j : act) {
+        j->done_steps += j->steps_tick;
+        if (j->steps_tick > 0 && j->plan->lean) j->plan->phi_valid = false;
+    }
     *steps_taken = maxk;
     return SETD_OK;
 }

@@ -75,7 +75,10 @@ enum { NL_PHI3 = 0, NL_PHI3_CONS = 1, NL_KPZ = 2, NL_CGL = 3, NL_NONE = 4 };
 enum { COEF_SEPARABLE = 0, COEF_ISO = 1, COEF_PER_MODE = 2 };
 
 // modes of the passes
-enum { MODE_STEP = 0, MODE_IC = 1, MODE_SYNC = 2 };
+enum { MODE_STEP = 0, MODE_IC = 1, MODE_SYNC = 2, MODE_RECOVER = 3 };
+// k_linear: a step of F = 0 in place; the SETD2 carry Y = E phi + G eta_n;
+// re-drawing the carry's noise for another step index
+enum { LIN_STEP = 0, LIN_CARRY = 1, LIN_RENOISE = 2 };
 
 // observable reductions
 enum { RED_SK = 0, RED_WIDTH = 1, RED_TWOTIME = 2 };

@@ -43,6 +43,7 @@ class setd_desc(ctypes.Structure):
         ("h", ctypes.c_double), ("order", ctypes.c_int), ("precision", ctypes.c_int),
         ("realizations", ctypes.c_int), ("seed", ctypes.c_uint64), ("dealias", ctypes.c_int),
         ("ic_kind", ctypes.c_int), ("ic_sigma", ctypes.c_double),
+        ("history_readback", ctypes.c_int),
     ]
 
 
@@ -153,6 +154,7 @@ def make_desc(p):
     d.dealias = int(p.get("dealias", 1))
     d.ic_kind = int(p.get("ic_kind", 0))
     d.ic_sigma = float(p.get("ic_sigma", 0.0))
+    d.history_readback = int(p.get("history_readback", 0))
     return d
 
 

@@ -8,7 +8,8 @@ A problem is a plain dict with the fields of the paper's problem statement
 (Sec. 4, Eq. general_fourier; lattice of App. A):
     ndim, n, dx, complex_field, c0, c2, c4 (complex as (re, im)), nl, nl_par,
     noise_D, noise_kpow, h, order, realizations, seed, dealias, ic_kind,
-    ic_sigma, precision.
+    ic_sigma, precision, and optionally history_readback (SETD2 storage: 0,
+    the default, keeps only the combined carry; 1 keeps F_{n-1} readable).
 c(k) = c0 + c2 k^2 + c4 k^4 and D(k) = noise_D k^noise_kpow.
 
 The models of Sec. 5 map onto it as

@@ -126,7 +126,7 @@ def test_fp64_plain_model_b_full_size():
 
 def test_set_field_history_and_restart():
     S = _setd()
-    p = W.model_b([64, 64], precision=64, realizations=2)
+    p = W.model_b([64, 64], precision=64, realizations=2, history_readback=1)
     g = S.Plan(p)
     o = O.Sim(p)
     x = W.random_spectrum(p, 11, 0.05)
@@ -144,6 +144,59 @@ def test_set_field_history_and_restart():
     assert max(relerr(g.get(r), o.get(r)) for r in range(2)) <= 1e-10
     out = g.observe(S.OBS_STEP)
     assert out[0] == 1003 and out[1] == 0
+
+
+def test_lean_set_field_and_set_step_match_oracle():
+    """SETD2 keeping only the carry E phi_n + w_b F_{n-1} + G eta_n: a state set
+    mid-run restarts the carry (F_{-1} = F_0), a new step index re-draws the
+    carry's noise, and F_{n-1} is not readable."""
+    S = _setd()
+    for prec, tol in ((64, 1e-10), (32, 2e-4)):
+        p = W.model_b([64, 64], precision=prec, realizations=2)
+        g = S.Plan(p)
+        o = O.Sim(p)
+        g.step(4)
+        o.step(4)
+        x = W.random_spectrum(p, 11, 0.05)
+        g.set(1, x)
+        o.set(1, x)
+        g.step(7)
+        o.step(7)
+        assert max(relerr(g.get(r), o.get(r)) for r in range(2)) <= tol
+        g.set_step(1000)
+        o.set_step(1000)
+        g.step(3)
+        o.step(3)
+        assert max(relerr(g.get(r), o.get(r)) for r in range(2)) <= tol
+        with pytest.raises(S.SetdError) as e:
+            g.history(0)
+        assert e.value.status == S.SETD_E_UNSUPPORTED
+        g.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_lean_and_separate_storage_agree(prec):
+    """The two SETD2 storages compute Eq. SETD2 with different groupings: the
+    trajectories agree to rounding, and reading phi from the carry plan (a
+    recovery from pre) leaves its trajectory bitwise unchanged."""
+    S = _setd()
+    base = W.kpz([64, 64], precision=prec, realizations=2, ic_kind=1, ic_sigma=0.2)
+    lean = S.Plan(dict(base, history_readback=0))
+    sep = S.Plan(dict(base, history_readback=1))
+    quiet = S.Plan(dict(base, history_readback=0))
+    worst = 0.0
+    for _ in range(5):
+        lean.step(6)
+        sep.step(6)
+        quiet.step(6)
+        for r in range(2):
+            worst = max(worst, relerr(lean.get(r), sep.get(r)))
+    say("lean vs separate storage, f%d: %.3g" % (prec, worst))
+    assert worst <= (1e-12 if prec == 64 else 2e-5)
+    for r in range(2):
+        assert np.array_equal(quiet.get(r), lean.get(r))
+    for g in (lean, sep, quiet):
+        g.close()
 
 
 def test_observables_match_oracle():
@@ -233,12 +286,15 @@ VARIANT_CASES = [
 
 
 @pytest.mark.parametrize("variant", ["0,0,0", "1,1,1", "2,2,2", "3,3,3", "1,2,3", "3,0,1", "0,4,0", "2,5,3"])
-def test_every_kernel_variant_matches_oracle(variant, monkeypatch):
+@pytest.mark.parametrize("history", [0, 1])
+def test_every_kernel_variant_matches_oracle(variant, history, monkeypatch):
     """Each autotuner choice (row: LDS padding x block size; axis passes: tile
     width x columns per thread; axis-0 variants 4 and 5: the register-update
-    kernel at two tile widths) gives the same trajectory."""
+    kernel at two tile widths) gives the same trajectory, with either SETD2
+    storage (the carry-only storage always steps with variants 4 or 5)."""
     monkeypatch.setenv("SETD_VARIANT", variant)
     for p in VARIANT_CASES:
+        p = dict(p, history_readback=history)
         err = run_pair(p, steps=12, every=6)
-        say("variant", variant, p["nl"], p["n"], "err", err)
+        say("variant", variant, "history", history, p["nl"], p["n"], "err", err)
         assert err <= TOL[p["precision"]]
