@@ -857,7 +857,12 @@ k_axis0r(AxisArgs a)
     const T dk0 = (T)it.dk[0], dk1 = (T)it.dk[1], dk2 = (T)it.dk[2];
     const T kl = (g.ndim == 3) ? dk2 * (T)al : dk1 * (T)al;
     const T km = (g.ndim == 3) ? dk1 * (T)a1 : T(0);
-    bool bad = false;
+    // Fourier prefactor of the nonlinearity, affine in k^2: P0 + P2 k^2 (real
+    // for real fields)
+    const cx<T> P0 = nl_pref<T>(it, T(0)), P2 = nl_pref<T>(it, T(1)) - P0;
+    // non-finite detection without branches: x - x is 0 for finite x and NaN
+    // for NaN or infinity
+    T nfacc = T(0);
     v[0][3] = czero<T>();
     v[0][4] = czero<T>();
     // the six bins in two groups of three (q = 0..2, then 5..7): each group
@@ -890,7 +895,9 @@ k_axis0r(AxisArgs a)
             const bool st = cv && stored(q);
             const T k0 = dk0 * (T)sgn_idx(t + q * TPL, N0);
             const T k2 = k0 * k0 + km * km + kl * kl;
-            const cx<T> F = cmul(nl_pref<T>(it, k2), v[0][q]);
+            cx<T> F;
+            if constexpr (CC) F = cmul(P0 + k2 * P2, v[0][q]);
+            else F = (P0.x + k2 * P2.x) * v[0][q];
             cx<T> nw;
             if constexpr (LEAN) {
                 // phi_{n+1} = Y_n + w F_n, Y_{n+1} = E phi_{n+1} + w_b F_n + G eta_{n+1}
@@ -916,11 +923,12 @@ k_axis0r(AxisArgs a)
                 if (it.order == 2) bstore<T>(rprev, voff(q), soff(q), F);
                 bstore<T>(rphi, voff(q), soff(q), nw);
             }
-            bad |= st && !(isfinite(nw.x) && isfinite(nw.y));
             v[0][q] = st ? nw : czero<T>();
+            nfacc += (v[0][q].x - v[0][q].x) + (v[0][q].y - v[0][q].y);
         }
     }
     // one flag update per block
+    const bool bad = !(nfacc == nfacc);
     if (__syncthreads_or(bad) && tid == 0) atomicOr(&it.ctrl->nonfinite, 1);
 
     cx<T> v2[1][8];
