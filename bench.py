@@ -15,10 +15,11 @@ with Philox noise and dealiasing, inverse FFT).
 Printed: one JSON line with site-updates/s (a timed segment with no
 instrumentation), the roofline record of the dominant kernel (a second timed
 segment of the same length, HIP events around every pass on the library's
-stream), the
-plain per-realization FP64 rate of the same model on the same GPU, a short
-continuous-batching serving run (p50/p99 job latency), and the FP64 oracle
-timed on the host cores over a bounded sample.
+stream), the plain per-realization FP64 rate of the same model on the same
+GPU, the step rates of the KPZ and CGL workloads, a continuous-batching
+serving run (p50/p99 job latency, throughput against the same jobs run alone
+in FP64, and an audit of 5% of the jobs against solo runs and the oracle), and
+the FP64 oracle timed on the host cores over a bounded sample.
 """
 import argparse
 import hashlib
@@ -93,9 +94,12 @@ def time_plan(setd, p, steps, warmup, profile):
     return t1 - t0, prof, info, ok, t_prof
 
 
-def serving_run(setd, W, n_jobs, seed):
+def serving_run(setd, W, n_jobs, seed, audit=True):
     """A Poisson stream of mixed SETD2 FP32 jobs through the continuous-batching
-    server; returns latency percentiles and throughput."""
+    server; returns latency percentiles and throughput, the same jobs' rate as
+    plain per-job FP64 runs (each job alone, 100 steps), and an audit of the two
+    cheapest jobs (5% of 40): the served state against a solo run of the same
+    job (bitwise) and against the FP64 oracle (realization 0, all steps)."""
     import numpy as np
     import torch
     trace = W.serving_trace(n_jobs=n_jobs, rate=20.0, seed=seed, steps_range=(1000, 10000))
@@ -113,14 +117,63 @@ def serving_run(setd, W, n_jobs, seed):
         times = srv.times(jid)
         lat.append(times[2] - times[0])
         su += W.site_updates(job["problem"], job["steps"])
-    srv.close()
-    torch.cuda.synchronize()
+    out = {"jobs": len(ids), "arrival_rate_per_s": 20.0}
     lat = np.array(lat)
-    return {
-        "jobs": len(ids), "arrival_rate_per_s": 20.0,
+    out.update({
         "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
         "makespan_s": float(t_end - t_start), "site_updates_per_s": float(su / (t_end - t_start)),
-    }
+    })
+    if audit:
+        from oracle import oracle as O
+        cheap = sorted(ids, key=lambda x: W.site_updates(x[1]["problem"], x[1]["steps"]))[:max(1, n_jobs // 20)]
+        rows = []
+        for jid, job in cheap:
+            p, n = job["problem"], job["steps"]
+            served = srv.get(jid, 0)
+            solo = setd.Plan(p)
+            solo.step(n)
+            same = bool(np.array_equal(served, solo.get(0)))
+            solo.close()
+            o = O.Sim(p, r_first=0, r_count=1)
+            o.step(n)
+            ref = o.get(0)
+            err = float(np.linalg.norm(served - ref) / max(np.linalg.norm(ref), 1e-300))
+            rows.append({"job": int(job["id"]), "model": job["model"], "n": list(p["n"]),
+                         "realizations": int(p["realizations"]), "steps": int(n),
+                         "served_equals_solo": same, "fp32_rel_err_vs_oracle": err})
+        out["audit"] = rows
+    srv.close()
+    torch.cuda.synchronize()
+    # plain per-job FP64: every job alone, 100 timed steps after 5 untimed
+    su64, t64 = 0, 0.0
+    for _, job in ids:
+        p = dict(job["problem"], precision=64)
+        plan = setd.Plan(p)
+        plan.step(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(100)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t0
+        su64 += W.site_updates(p, 100)
+        plan.close()
+    out["fp64_per_job_site_updates_per_s"] = su64 / t64
+    out["served_fp32_over_fp64_per_job"] = out["site_updates_per_s"] / (su64 / t64)
+    return out
+
+
+def other_workloads(setd, W, steps):
+    """Step rate of the KPZ (1024^2 x 16) and CGL (256^3 x 4) workloads."""
+    res = []
+    for name, cfg in (("KPZ 1024x1024, SETD2, FP32, 16 realizations", W.CONFIG_KPZ),
+                      ("CGL 256x256x256, SETD2, complex64, 4 realizations", W.CONFIG_CGL)):
+        p = W.problem(cfg)
+        el, _, info, ok, _ = time_plan(setd, p, steps, 5, profile=False)
+        sec = el / steps
+        res.append({"workload": name, "site_updates_per_s": float(info.site_updates_per_step) / sec,
+                    "ms_per_step": 1e3 * sec, "alg_bytes_per_step": float(info.alg_bytes_per_step),
+                    "step_frac": float(info.alg_bytes_per_step / sec / 1e9 / PEAK_HBM_GBS), "ok": bool(ok)})
+    return res
 
 
 def main():
@@ -131,6 +184,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--serving-jobs", type=int, default=40, help="0 skips the serving run")
+    ap.add_argument("--no-other", action="store_true", help="skip the KPZ and CGL step rates")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 512 MiB device-to-device (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -205,8 +259,11 @@ def main():
                               "value": v64, "ms_per_step": 1e3 * e64 / k64, "ok": bool(ok64)}
         line["fp32_batched_over_fp64_plain"] = value / v64
 
+    if not args.no_other:
+        line["other_workloads"] = other_workloads(setd, W, 50)
+
     if args.serving_jobs > 0 and hasattr(setd, "Server"):
-        line["serving"] = serving_run(setd, W, args.serving_jobs, seed=2024)
+        line["serving"] = serving_run(setd, W, args.serving_jobs, seed=2024, audit=not args.no_cpu)
 
     if not args.no_cpu:
         from oracle import oracle as O

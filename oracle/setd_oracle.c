@@ -348,6 +348,34 @@ static void unlin(const orc_sim* s, size_t e, int* j)
     for (int d = s->d.ndim - 1; d >= 0; d--) { j[d] = (int)(e % (size_t)s->nh[d]); e /= (size_t)s->nh[d]; }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Hermitian symmetry of a real field (App. A): phi_{-a} = conj(phi_a).  On the
+   planes a_d in {0, N_d/2} of the half spectrum both members of a conjugate
+   pair are stored.  Round-off in the transforms breaks the pairing slightly,
+   and the anti-Hermitian part is invisible to the real-space nonlinearity, so
+   it evolves with e^{c h} alone and grows where Re c > 0.  As for the noise
+   (App. B), the member with the smaller linear index is independent and its
+   partner is set to its conjugate; self-conjugate modes are made real.       */
+/* ------------------------------------------------------------------------ */
+static void hermitian_planes(const orc_sim* s, cplx* ph)
+{
+    const orc_desc* d = &s->d;
+    if (d->complex_field) return;
+    const int last = d->ndim - 1;
+    for (size_t e = 0; e < s->nspec; e++) {
+        int j[3] = { 0, 0, 0 };
+        unlin(s, e, j);
+        if (!(j[last] == 0 || 2 * j[last] == d->n[last])) continue;
+        int jp[3] = { 0, 0, 0 };
+        for (int i = 0; i < last; i++) jp[i] = (j[i] == 0) ? 0 : d->n[i] - j[i];
+        jp[last] = j[last];
+        size_t ep = lin_index(s, jp);
+        if (ep == e) ph[e] = creal(ph[e]);
+        else if (ep < e) ph[e] = conj(ph[ep]);
+    }
+}
+
+
 static int isqrt_ceil(long m)
 {
     if (m <= 0) return 0;
@@ -467,6 +495,7 @@ orc_sim* orc_create_subset(const orc_desc* d, int r_first, int r_count)
                 }
                 rfftn(s->rwork, ph, d->ndim, d->n, s->work);
                 for (size_t e = 0; e < s->nspec; e++) if (!s->mask[e]) ph[e] = 0;
+                hermitian_planes(s, ph);
             }
         }
     }
@@ -595,6 +624,7 @@ static void update(orc_sim* s, int rr, const cplx* xi)
         ph[e] = v;
         fp[e] = F[e];
     }
+    hermitian_planes(s, ph);
 }
 
 static int step_once(orc_sim* s, const cplx* xi_all)
@@ -642,6 +672,7 @@ int orc_set(orc_sim* s, int rr, const double* in)
     cplx* dst = s->phi + (size_t)rr * s->nspec;
     const cplx* src = (const cplx*)in;
     for (size_t e = 0; e < s->nspec; e++) dst[e] = s->mask[e] ? src[e] : 0;
+    hermitian_planes(s, dst);
     s->have_prev[rr] = 0;
     return 0;
 }

@@ -865,6 +865,7 @@ k_axis0r(AxisArgs a)
     T nfacc = T(0);
     v[0][3] = czero<T>();
     v[0][4] = czero<T>();
+    cx<T> ysv[3];   // LEAN: the new carry of bins q = 0..2 (Hermitian column below)
     // the six bins in two groups of three (q = 0..2, then 5..7): each group
     // reads its coefficients (and, when not read early, state and history)
     // and is updated and stored before the next group's reads
@@ -912,6 +913,7 @@ k_axis0r(AxisArgs a)
                     y = cf[u].E.x * nw + cf[u].wb.x * F + cf[u].G * eta[q];
                 }
                 bstore<T>(rprev, voff(q), soff(q), y);
+                if (grp == 0) ysv[u] = y;
             } else {
                 if constexpr (CC) {
                     nw = cmul(cf[u].E, gph[u]) + cmul(cf[u].wa, F) + cf[u].G * eta[q];
@@ -930,6 +932,45 @@ k_axis0r(AxisArgs a)
     // one flag update per block
     const bool bad = !(nfacc == nfacc);
     if (__syncthreads_or(bad) && tid == 0) atomicOr(&it.ctrl->nonfinite, 1);
+
+    // Hermitian column a_last = 0 of a 2D real field (the rule of
+    // k_hermitian): rows j and N0 - j are both in this block, the lower one
+    // (q <= 2) independent; row 0 is self-conjugate.  LDS is free between the
+    // barrier above and the one that opens the inverse transform.
+    if constexpr (!CC) {
+        if (g.ndim == 2 && tile == 0) {
+            if (c0 == 0) {
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    if (!stored(q)) continue;
+                    const int sl = lds_slot<PAD>(t + q * TPL) * TILE;
+                    lds[sl] = v[0][q];
+                    if constexpr (LEAN) lds[sl + 1] = ysv[q];
+                }
+            }
+            __syncthreads();
+            if (c0 == 0) {
+#pragma unroll
+                for (int q = 5; q < 8; q++) {
+                    if (!stored(q)) continue;
+                    const int sl = lds_slot<PAD>(N0 - (t + q * TPL)) * TILE;
+                    const cx<T> pv = lds[sl];
+                    v[0][q] = {pv.x, -pv.y};
+                    if constexpr (LEAN) {
+                        const cx<T> py = lds[sl + 1];
+                        bstore<T>(rprev, voff(q), soff(q), {py.x, -py.y});
+                    } else {
+                        bstore<T>(rphi, voff(q), soff(q), v[0][q]);
+                    }
+                }
+                if (t == 0) {
+                    v[0][0].y = T(0);
+                    if constexpr (LEAN) bstore<T>(rprev, voff(0), soff(0), {ysv[0].x, T(0)});
+                    else bstore<T>(rphi, voff(0), soff(0), v[0][0]);
+                }
+            }
+        }
+    }
 
     cx<T> v2[1][8];
     if constexpr (KPZ) {
@@ -1073,6 +1114,61 @@ __global__ void __launch_bounds__(256) k_linear(LinArgs a)
     }
     if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&it.ctrl->nonfinite, 1);
     if (a.mode == LIN_STEP && threadIdx.x == 0) advance_step(it.ctrl, gridDim.x, nstep);
+}
+
+// ---------------------------------------------------------------- Hermitian planes
+// A real field's spectrum is Hermitian, phi_{-a} = conj(phi_a) (App. A).  On
+// the planes a_last in {0, N_last/2} of the stored half spectrum both members
+// of a conjugate pair are stored; transform round-off breaks the pairing, and
+// the anti-Hermitian part, invisible to the real-space nonlinearity, would
+// grow like e^{c h} per step where Re c > 0.  As for the noise (App. B), the
+// member with the smaller linear index is independent and its partner takes
+// its conjugate; self-conjugate modes are made real.  One thread per stored
+// mode of the planes; partners only read independent members, which no
+// thread writes.
+struct HermArgs {
+    Geo g;
+    const Item* items;
+    int which;    // 0: phi, 1: the F_{n-1} array (the SETD2 carry of lean plans)
+    int nplane;   // stored modes per plane and realization
+    int ncol;     // planes: 1 (a_last = 0), or 2 when a_last = N_last/2 is stored
+    int sub;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_hermitian(HermArgs a)
+{
+    const Item it = a.items[blockIdx.y];
+    if (a.sub >= it.steps) return;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.nplane * a.ncol) return;
+    const Geo& g = a.g;
+    const int last = g.ndim - 1;
+    const int c = idx / a.nplane, rest = idx % a.nplane;
+    const int jl = c == 0 ? 0 : g.n[last] / 2;
+    const int col = c == 0 ? 0 : g.kept[last] - 1;
+    const int i1 = (g.ndim == 3) ? rest % g.kept[1] : 0;
+    const int i0 = (g.ndim == 3) ? rest / g.kept[1] : rest;
+    const int j0 = fft_pos(i0, g.n[0], g.kept[0], g.kp[0]);
+    const int j1 = (g.ndim == 3) ? fft_pos(i1, g.n[1], g.kept[1], g.kp[1]) : 0;
+    const int p0 = j0 ? g.n[0] - j0 : 0;
+    const int p1 = (g.ndim == 3 && j1) ? g.n[1] - j1 : 0;
+    const uint32_t nh = (uint32_t)g.nh_last;
+    const uint32_t e = (g.ndim == 3) ? ((uint32_t)j0 * (uint32_t)g.n[1] + (uint32_t)j1) * nh + (uint32_t)jl
+                                     : (uint32_t)j0 * nh + (uint32_t)jl;
+    const uint32_t ep = (g.ndim == 3) ? ((uint32_t)p0 * (uint32_t)g.n[1] + (uint32_t)p1) * nh + (uint32_t)jl
+                                      : (uint32_t)p0 * nh + (uint32_t)jl;
+    cx<T>* arr = reinterpret_cast<cx<T>*>(a.which ? it.prev : it.phi);
+    const size_t lstride = (g.ndim == 3) ? (size_t)g.kept[1] * g.pitch : (size_t)g.pitch;
+    const size_t own = (size_t)i0 * lstride + (size_t)i1 * g.pitch + col;
+    if (ep == e) {
+        arr[own].y = T(0);
+    } else if (ep < e) {
+        const int ip0 = stored_idx(p0, g.n[0], g.kept[0], g.kp[0]);
+        const int ip1 = (g.ndim == 3) ? stored_idx(p1, g.n[1], g.kept[1], g.kp[1]) : 0;
+        const cx<T> v = arr[(size_t)ip0 * lstride + (size_t)ip1 * g.pitch + col];
+        arr[own] = {v.x, -v.y};
+    }
 }
 
 // ---------------------------------------------------------------- FP64 observables

@@ -32,6 +32,10 @@ hipError_t launch_axis0(const Geo& g, const Item* items, int nitems, int mode, i
                         int lean, hipStream_t s);
 template <typename T>
 hipError_t launch_axis1(const Geo& g, const Item* items, int nitems, int dir, int sub, int var, hipStream_t s);
+// keep the stored a_last = 0 (and N_last/2) planes of a real field Hermitian
+// (which: 0 phi, 1 the F_{n-1} array / SETD2 carry); no-op for complex fields
+template <typename T>
+hipError_t launch_hermitian(const Geo& g, const Item* items, int nitems, int which, hipStream_t s);
 // mode LIN_STEP / LIN_CARRY / LIN_RENOISE (new_step: the re-drawn step index)
 template <typename T>
 hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, int mode, int64_t new_step,

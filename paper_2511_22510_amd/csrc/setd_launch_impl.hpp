@@ -110,6 +110,24 @@ static hipError_t launch_axis_nt(const Geo& g, const Item* items, int nitems, in
     return hipGetLastError();
 }
 
+// Hermitian planes of a real field's state array (which: 0 phi, 1 the F_{n-1}
+// array / SETD2 carry); no-op for complex fields
+template <typename T>
+static hipError_t launch_hermitian_t(const Geo& g, const Item* items, int nitems, int which, int sub, hipStream_t s)
+{
+    if (g.cplx) return hipSuccess;
+    HermArgs a;
+    a.g = g;
+    a.items = items;
+    a.which = which;
+    a.nplane = g.kept[0] * (g.ndim == 3 ? g.kept[1] : 1);
+    a.ncol = (2 * g.kp[g.ndim - 1] == g.n[g.ndim - 1]) ? 2 : 1;
+    a.sub = sub;
+    dim3 grid((a.nplane * a.ncol + 255) / 256, nitems);
+    hipLaunchKernelGGL((k_hermitian<T>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 // axis-0 pass with the update in registers (k_axis0r), one column per thread group
 template <typename T, int N, int TILE>
 static hipError_t launch_axis0r(const Geo& g, const Item* items, int nitems, int mode, int sub, bool kpz,
@@ -151,20 +169,28 @@ static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int
         // kernel only.
         const bool reg = mode == MODE_STEP && axis0_register_ok(g, sizeof(T));
         if (reg && lean && var < 4) var = 4;
-        if (var == 4) {
-            if (reg) return launch_axis0r<T, N, (TM >= 2 ? TM / 2 : 1)>(g, items, nitems, mode, sub, kpz, lean, s);
-            var = 3;
-        } else if (var == 5) {
-            if (reg) return launch_axis0r<T, N, TM>(g, items, nitems, mode, sub, kpz, lean, s);
-            var = 0;
+        if (reg && (var == 4 || var == 5)) {
+            hipError_t e = (var == 4) ? launch_axis0r<T, N, (TM >= 2 ? TM / 2 : 1)>(g, items, nitems, mode, sub, kpz, lean, s)
+                                      : launch_axis0r<T, N, TM>(g, items, nitems, mode, sub, kpz, lean, s);
+            // the register kernel keeps a 2D real field's column a_last = 0
+            // Hermitian itself; 3D planes span several blocks
+            if (e == hipSuccess && g.ndim == 3) e = launch_hermitian_t<T>(g, items, nitems, lean ? 1 : 0, sub, s);
+            return e;
         }
+        if (var == 4) var = 3;
+        else if (var == 5) var = 0;
     }
+    hipError_t e;
     switch (var) {
-    case 0: return launch_axis_nt<T, N, TM, 2, AX0>(g, items, nitems, mode, sub, kpz, s);
-    case 1: return launch_axis_nt<T, N, TM, 1, AX0>(g, items, nitems, mode, sub, kpz, s);
-    case 2: return launch_axis_nt<T, N, TM, 4, AX0>(g, items, nitems, mode, sub, kpz, s);
-    default: return launch_axis_nt<T, N, TM / 2, 1, AX0>(g, items, nitems, mode, sub, kpz, s);
+    case 0: e = launch_axis_nt<T, N, TM, 2, AX0>(g, items, nitems, mode, sub, kpz, s); break;
+    case 1: e = launch_axis_nt<T, N, TM, 1, AX0>(g, items, nitems, mode, sub, kpz, s); break;
+    case 2: e = launch_axis_nt<T, N, TM, 4, AX0>(g, items, nitems, mode, sub, kpz, s); break;
+    default: e = launch_axis_nt<T, N, TM / 2, 1, AX0>(g, items, nitems, mode, sub, kpz, s); break;
     }
+    // the state a step or an initial condition wrote: Hermitian planes
+    if (AX0 && e == hipSuccess && (mode == MODE_STEP || mode == MODE_IC))
+        e = launch_hermitian_t<T>(g, items, nitems, 0, sub, s);
+    return e;
 }
 
 template <typename T>
@@ -174,6 +200,12 @@ hipError_t launch_axis0(const Geo& g, const Item* items, int nitems, int mode, i
     SETD_DISPATCH_N(g.n[0], return (launch_axis_n<T, NN, true>(g, items, nitems, mode, sub, var, kpz != 0,
                                                                 lean != 0, s)));
     return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_hermitian(const Geo& g, const Item* items, int nitems, int which, hipStream_t s)
+{
+    return launch_hermitian_t<T>(g, items, nitems, which, 0, s);
 }
 
 template <typename T>
@@ -225,6 +257,7 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
     template hipError_t launch_axis0<T>(const Geo&, const Item*, int, int, int, int, int, int, hipStream_t);    \
     template hipError_t launch_axis1<T>(const Geo&, const Item*, int, int, int, int, hipStream_t);              \
     template hipError_t launch_linear<T>(const Geo&, const Item*, int, int, int, int64_t, hipStream_t);         \
-    template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, hipStream_t);
+    template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, hipStream_t); \
+    template hipError_t launch_hermitian<T>(const Geo&, const Item*, int, int, hipStream_t);
 
 }  // namespace setd

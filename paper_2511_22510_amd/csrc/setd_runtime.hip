@@ -792,6 +792,9 @@ setd_status Plan::set_field(int r, const double* in, size_t len)
     }
     SETD_HIP(hipMemcpyAsync(ws + lay.phi + (size_t)r * Sb, host.data(), S * elt, hipMemcpyHostToDevice, stream));
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items) + r;
+    // a real field's spectrum is Hermitian on the a_last = 0 (and N/2) planes
+    if (d.precision == 32) SETD_HIP((launch_hermitian<float>(g, items_dev, 1, 0, stream)));
+    else SETD_HIP((launch_hermitian<double>(g, items_dev, 1, 0, stream)));
     setd_status st = (d.precision == 32) ? launch_sync_t<float>(*this, items_dev, 1, stream)
                                          : launch_sync_t<double>(*this, items_dev, 1, stream);
     if (st != SETD_OK) return st;

@@ -116,6 +116,29 @@ def test_config_cgl_full_size_sampled():
     assert err <= 2e-4
 
 
+@pytest.mark.parametrize("history", [0, 1])
+@pytest.mark.parametrize("prec", [32, 64])
+def test_long_model_a_stays_on_the_oracle(prec, history):
+    """Model A with r < 0 has Re c > 0 near k = 0, where an anti-Hermitian part
+    of the a_last = 0 plane (transform round-off, invisible in real space)
+    would grow like e^{c t}: without keeping the plane Hermitian the FP32 run
+    blows up near step 2000 (t = 20).  3000 steps stay within the bars."""
+    p = W.model_a([128, 128], order=2, precision=prec, realizations=1, seed=7373773241406430705,
+                  history_readback=history)
+    err = run_pair(p, steps=3000, every=1000)
+    say("long model A f%d history %d err %.3g" % (prec, history, err))
+    assert err <= TOL[prec]
+
+
+def test_long_model_a_3d_stays_on_the_oracle():
+    """The same for a 3D real field, whose a_last = 0 plane pairs span blocks
+    of the axis-0 pass (a separate Hermitian pass after each step)."""
+    p = W.model_a([32, 32, 32], order=2, precision=32, realizations=1, seed=11, h=0.02)
+    err = run_pair(p, steps=1500, every=500)
+    say("long model A 3D err %.3g" % err)
+    assert err <= 2e-4
+
+
 def test_fp64_plain_model_b_full_size():
     """The plain FP64 per-realization run the batched FP32 path is measured against."""
     p = W.problem(W.CONFIG_B, precision=64, realizations=1)

@@ -244,3 +244,23 @@ def test_strong_order_one_with_additive_noise(order):
     hs = np.array([32, 16, 8]) * h_ref
     slope = np.polyfit(np.log(hs), np.log(errs), 1)[0]
     assert 0.75 < slope < 1.35 if order == 1 else slope > 0.75, (errs, slope)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_real_field_spectrum_stays_hermitian_long_run(order):
+    """A real field has phi_{-a} = conj(phi_a) (App. A).  Model A with r < 0 has
+    Re c(k) > 0 near k = 0; an anti-Hermitian part there is invisible to the
+    real-space nonlinearity and would grow like e^{c t} from round-off (about
+    e^{75} here).  After t = 75 the a_last = 0 column is exactly Hermitian and
+    the real-space field stays bounded (ordered phase, |phi| near 1)."""
+    p = W.model_a([32, 32], r=-1.0, u=1.0, T=0.1, h=0.05, order=order, precision=64,
+                  ic_sigma=0.1, seed=5)
+    o = O.Sim(p)
+    o.step(1500)
+    ph = o.get(0)
+    col = ph[:, 0]
+    assert np.array_equal(col[1:], np.conj(col[1:][::-1]))
+    assert col[0].imag == 0.0
+    assert np.all(np.isfinite(ph)) and np.abs(ph).max() < 3.0 * 32 * 32
+    x = np.fft.irfft2(ph, s=(32, 32))
+    assert np.max(np.abs(x)) < 3.0
