@@ -134,7 +134,10 @@ typedef struct {
     double pass_bytes[4];     /* HBM bytes each kernel launch of a step must move,
                                  in launch order (unused entries 0)                */
     int variants[3];          /* kernel variants in use (row, axis 0, axis 1) after
-                                 the autotuner; meaningful once bound; axis-0
+                                 the autotuner; meaningful once bound; row
+                                 variant bits: 0 LDS padding, 1 256-thread
+                                 workgroups, 2-3 log2 of the row-pair groups a
+                                 workgroup takes in turn (real fields); axis-0
                                  variants 4 and 5 update in registers           */
     int axis_tile[2];         /* axis-0 pass: column tile width, columns per thread */
 } setd_plan_info_t;

@@ -54,6 +54,10 @@ def lib():
         L.orc_normal_pair.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_uint32, ctypes.c_uint32, dp, dp]
         L.orc_normal_pair.restype = None
+        L.orc_noise_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_uint32, ctypes.c_int, dp, dp]
+        L.orc_noise_normals.restype = None
+        L.orc_noise_slot.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint32), ip, ip]
         L.orc_phi12.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         L.orc_phi12.restype = None
         L.orc_create_subset.argtypes = [ctypes.POINTER(_Desc), ctypes.c_int, ctypes.c_int]
@@ -132,6 +136,15 @@ def normal_pair(seed, e, n, r, tag):
     z1 = ctypes.c_double()
     z2 = ctypes.c_double()
     lib().orc_normal_pair(ctypes.c_uint64(seed), e, n, r, tag, ctypes.byref(z1), ctypes.byref(z2))
+    return z1.value, z2.value
+
+
+def noise_normals(seed, P, n, r, half):
+    """Box-Muller normals of the Fourier-space noise from words (x0, x1)
+    (half 0) or (x2, x3) (half 1) of the Philox block (P, n, r, 0)."""
+    z1 = ctypes.c_double()
+    z2 = ctypes.c_double()
+    lib().orc_noise_normals(ctypes.c_uint64(seed), P, n, r, int(half), ctypes.byref(z1), ctypes.byref(z2))
     return z1.value, z2.value
 
 
@@ -228,6 +241,15 @@ class Sim:
         out = np.zeros((self.R,) + self.spec_shape, dtype=np.complex128)
         lib().orc_noise_xi(self._h, int(n), _dptr(out.view(np.float64)))
         return out
+
+    def noise_slot(self, e):
+        """(P, half, kind) of stored element e: the Philox slot its noise is
+        drawn from and how eta follows from the normals (App. B)."""
+        P = ctypes.c_uint32()
+        half = ctypes.c_int()
+        kind = ctypes.c_int()
+        lib().orc_noise_slot(self._h, int(e), ctypes.byref(P), ctypes.byref(half), ctypes.byref(kind))
+        return P.value, half.value, kind.value
 
     def step_xi(self, xi):
         a = np.ascontiguousarray(xi, dtype=np.complex128).reshape((self.R,) + self.spec_shape)

@@ -30,11 +30,17 @@
  *    |x| < 1 (replacing the "use Euler-Maruyama for small c" advice of Sec. 4)
  *    and closed forms otherwise.  The first SETD2 step uses F_{-1} = F_0.
  *  - Fourier-space noise (App. B): Philox4x32-10 (Salmon et al., SC'11) keyed
- *    by the seed, counter (element index, step, realization, tag), two 53-bit
- *    uniforms, Box-Muller.  Complex modes get (z1 + i z2)/sqrt2, self-conjugate
- *    modes of a real field get z1, a conjugate pair on the a_d in {0, N_d/2}
- *    planes draws once at the smaller linear index and the partner takes the
- *    conjugate.  Masked modes draw nothing.
+ *    by the seed.  Complex modes get (z1 + i z2)/sqrt2, self-conjugate modes
+ *    of a real field get z1, a conjugate pair on the a_d in {0, N_d/2} planes
+ *    draws once at the smaller linear index and the partner takes the
+ *    conjugate.  Masked modes draw nothing.  The paper fixes the distribution,
+ *    not the generator; here one Philox block serves two drawing modes that
+ *    differ only in the axis-0 position, j and j' = (j mod M) + (7 - j div M) M
+ *    with M = N_0/8 (1 if N_0 < 8): counter (P, step, realization, 0) with P
+ *    the linear index of the member with j div M < 4 over an axis-0 extent of
+ *    N_0/2; that member takes words (x0, x1), the other (x2, x3), each word a
+ *    uniform (x + 1/2) 2^-32, then Box-Muller.  The initial condition draws
+ *    per site: counter (site, 0, realization, 1), two 53-bit uniforms.
  */
 #include <complex.h>
 #include <math.h>
@@ -261,6 +267,22 @@ void orc_normal_pair(uint64_t seed, uint32_t e, uint32_t n, uint32_t r, uint32_t
     uint64_t m2 = ((uint64_t)x[2] << 21) | (uint64_t)(x[3] >> 11);
     double u1 = ((double)m1 + 0.5) * 0x1p-53;
     double u2 = ((double)m2 + 0.5) * 0x1p-53;
+    double rad = sqrt(-2.0 * log(u1));
+    *z1 = rad * cos(2.0 * M_PI * u2);
+    *z2 = rad * sin(2.0 * M_PI * u2);
+}
+
+/* Box-Muller normals of the Fourier-space noise: words (x0, x1) (half 0) or
+   (x2, x3) (half 1) of the Philox block with counter (P, n, r, 0), each word
+   a uniform u = (x + 1/2) 2^-32 in (0, 1) */
+void orc_noise_normals(uint64_t seed, uint32_t P, uint32_t n, uint32_t r, int half, double* z1, double* z2)
+{
+    uint32_t ctr[4] = { P, n, r, 0u };
+    uint32_t key[2] = { (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
+    uint32_t x[4];
+    orc_philox(ctr, key, x);
+    double u1 = ((double)x[half ? 2 : 0] + 0.5) * 0x1p-32;
+    double u2 = ((double)x[half ? 3 : 1] + 0.5) * 0x1p-32;
     double rad = sqrt(-2.0 * log(u1));
     *z1 = rad * cos(2.0 * M_PI * u2);
     *z2 = rad * sin(2.0 * M_PI * u2);
@@ -563,40 +585,50 @@ static void nonlinear_term(orc_sim* s, const cplx* ph, cplx* F)
     for (size_t e = 0; e < ns; e++) F[e] = s->mask[e] ? s->pref[e] * F[e] : 0;
 }
 
+/* App. B: the mode whose draw gives eta_a of mode e (e itself, or on the
+   a_d in {0, N_d/2} planes of a real field the member of the conjugate pair
+   with the smaller linear index), how eta_a follows from it (0: (z1 + i z2)
+   /sqrt2, 1: z1, 2: the conjugate of kind 0), and its Philox slot */
+int orc_noise_slot(const orc_sim* s, size_t e, uint32_t* P, int* half, int* kind)
+{
+    const orc_desc* d = &s->d;
+    int last = d->ndim - 1;
+    int j[3] = { 0, 0, 0 };
+    unlin(s, e, j);
+    size_t ed = e;
+    *kind = 0;
+    if (!d->complex_field && !(j[last] > 0 && 2 * j[last] < d->n[last])) {
+        int jp[3] = { 0, 0, 0 };
+        for (int i = 0; i < last; i++) jp[i] = (j[i] == 0) ? 0 : d->n[i] - j[i];
+        jp[last] = j[last];
+        size_t ep = lin_index(s, jp);
+        if (ep == e) *kind = 1;
+        else if (ep < e) { *kind = 2; ed = ep; }
+    }
+    /* pair the drawing mode's axis-0 position j0 with (j0 mod M) + (7 - j0 div M) M */
+    size_t S = s->nspec / (size_t)s->nh[0];   /* elements per axis-0 position */
+    size_t j0 = ed / S, rest = ed % S;
+    size_t M = d->n[0] >= 8 ? (size_t)d->n[0] / 8 : 1;
+    size_t q = j0 / M;
+    size_t row = j0 % M + (q < 4 ? q : 7 - q) * M;
+    *P = (uint32_t)(row * S + rest);
+    *half = q >= 4;
+    return 0;
+}
+
 /* Step 2 of Sec. 4 with App. B: eta_a for realization r at step n */
 static cplx noise_eta(const orc_sim* s, size_t e, int64_t n, uint32_t r)
 {
-    const orc_desc* d = &s->d;
     const double rs2 = 0.70710678118654752440;
     double z1, z2;
+    uint32_t P;
+    int half, kind;
     if (!s->mask[e]) return 0;
-    if (d->complex_field) {
-        orc_normal_pair(d->seed, (uint32_t)e, (uint32_t)n, r, 0u, &z1, &z2);
-        return (z1 + I * z2) * rs2;
-    }
-    int j[3] = { 0, 0, 0 };
-    unlin(s, e, j);
-    int last = d->ndim - 1;
-    int ad = j[last];
-    if (ad > 0 && 2 * ad < d->n[last]) {
-        orc_normal_pair(d->seed, (uint32_t)e, (uint32_t)n, r, 0u, &z1, &z2);
-        return (z1 + I * z2) * rs2;
-    }
-    /* a_d in {0, N_d/2}: the conjugate partner -a on this plane */
-    int jp[3] = { 0, 0, 0 };
-    for (int i = 0; i < last; i++) jp[i] = (j[i] == 0) ? 0 : d->n[i] - j[i];
-    jp[last] = ad;
-    size_t ep = lin_index(s, jp);
-    if (ep == e) {
-        orc_normal_pair(d->seed, (uint32_t)e, (uint32_t)n, r, 0u, &z1, &z2);
-        return z1;
-    }
-    if (e < ep) {
-        orc_normal_pair(d->seed, (uint32_t)e, (uint32_t)n, r, 0u, &z1, &z2);
-        return (z1 + I * z2) * rs2;
-    }
-    orc_normal_pair(d->seed, (uint32_t)ep, (uint32_t)n, r, 0u, &z1, &z2);
-    return conj((z1 + I * z2) * rs2);
+    orc_noise_slot(s, e, &P, &half, &kind);
+    orc_noise_normals(s->d.seed, P, (uint32_t)n, r, half, &z1, &z2);
+    if (kind == 1) return z1;
+    if (kind == 2) return conj((z1 + I * z2) * rs2);
+    return (z1 + I * z2) * rs2;
 }
 
 /* the additive noise term G_a eta_a of step n for all realizations */

@@ -7,9 +7,12 @@
 //    Thread t holds elements t + q N/8 (q = 0..7) on entry and output bins
 //    t + q N/8 on exit, so the first stage reads and the last stage writes in
 //    the layout in which lines are loaded from and stored to global memory.
-//    Each thread keeps one base twiddle per radix-8 stage in registers.
+//    Each thread keeps one base twiddle per radix-8 stage in registers
+//    (LineTw) or, for kernels that run several transforms, all seven powers
+//    of it (LineTwP).
 //  * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller normals
-//    for the Fourier-space noise of App. B.
+//    for the Fourier-space noise of App. B (two modes per Philox block) and
+//    the initial condition (one block per site).
 //  * phi1(x) = (e^x - 1)/x and phi2(x) = (e^x - 1 - x)/x^2 in FP64 for the ETD
 //    coefficients of Eq. SETD1/SETD2, by Taylor series for |x| < 1 and closed
 //    forms otherwise.
@@ -278,21 +281,56 @@ __device__ __forceinline__ void fft_stage0(cx<T>* v)
     }
 }
 
-// Radix-8 stage with base twiddle w: input r is multiplied by w^r (forward)
-// or conj(w)^r (inverse) before the butterfly.
-template <typename T, int SIGN>
-__device__ __forceinline__ void fft_stage8(cx<T>* v, cx<T> w)
+// Powers w, w^2, ..., w^7 of a stage's base twiddle.
+template <typename T>
+__device__ __forceinline__ void tw_powers(cx<T> w, cx<T> (&p)[7])
 {
-    const cx<T> w2 = cmul(w, w), w3 = cmul(w2, w), w4 = cmul(w2, w2);
-    const cx<T> w5 = cmul(w4, w), w6 = cmul(w3, w3), w7 = cmul(w4, w3);
-    if constexpr (SIGN < 0) {
-        v[1] = cmul(v[1], w); v[2] = cmul(v[2], w2); v[3] = cmul(v[3], w3); v[4] = cmul(v[4], w4);
-        v[5] = cmul(v[5], w5); v[6] = cmul(v[6], w6); v[7] = cmul(v[7], w7);
-    } else {
-        v[1] = cmulc(v[1], w); v[2] = cmulc(v[2], w2); v[3] = cmulc(v[3], w3); v[4] = cmulc(v[4], w4);
-        v[5] = cmulc(v[5], w5); v[6] = cmulc(v[6], w6); v[7] = cmulc(v[7], w7);
-    }
+    p[0] = w;
+    p[1] = cmul(w, w);
+    p[2] = cmul(p[1], w);
+    p[3] = cmul(p[1], p[1]);
+    p[4] = cmul(p[3], w);
+    p[5] = cmul(p[2], p[2]);
+    p[6] = cmul(p[3], p[2]);
+}
+
+// Radix-8 stage: input r is multiplied by w^r (forward) or conj(w)^r
+// (inverse) before the butterfly, p holding w^1..w^7.
+template <typename T, int SIGN>
+__device__ __forceinline__ void fft_stage8(cx<T>* v, const cx<T> (&p)[7])
+{
+#pragma unroll
+    for (int r = 1; r < 8; r++) v[r] = (SIGN < 0) ? cmul(v[r], p[r - 1]) : cmulc(v[r], p[r - 1]);
     dft8<SIGN>(v);
+}
+
+// Twiddles of a line transform with every power formed once per thread (for
+// kernels that run several transforms with the same t and have the registers).
+template <typename T, int N>
+struct LineTwP {
+    cx<T> p[FftPlan<N>::NST > 1 ? FftPlan<N>::NST - 1 : 1][7];
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void line_tw_expand(LineTwP<T, N>& P, const LineTw<T, N>& L)
+{
+#pragma unroll
+    for (int s = 0; s + 1 < FftPlan<N>::NST; s++) tw_powers(L.w[s], P.p[s]);
+}
+
+// twiddle multiplication and butterfly of radix-8 stage s (s >= 0 after the first)
+template <typename T, int N, int SIGN>
+__device__ __forceinline__ void tw_stage(cx<T>* v, const LineTw<T, N>& L, int s)
+{
+    cx<T> p[7];
+    tw_powers(L.w[s], p);
+    fft_stage8<T, SIGN>(v, p);
+}
+
+template <typename T, int N, int SIGN>
+__device__ __forceinline__ void tw_stage(cx<T>* v, const LineTwP<T, N>& P, int s)
+{
+    fft_stage8<T, SIGN>(v, P.p[s]);
 }
 
 // Slot distance of element e0 + d from element e0 for a power-of-two d when no
@@ -340,9 +378,8 @@ __device__ __forceinline__ void fft_exchange(cx<T> (&v)[NL][8], int t, cx<T>* ld
 // NL independent line transforms X_k = sum_m x_m exp(SIGN 2 pi i k m / N),
 // unscaled, held by the same threads (same t, same twiddles).  Every thread of
 // the block must call it (it contains block barriers).
-template <typename T, int N, int SIGN, int PAD, int NL>
-__device__ __forceinline__ void fft_lines(cx<T> (&v)[NL][8], int t, cx<T>* lds, int stride, int lstep,
-                                          const LineTw<T, N>& tw)
+template <typename T, int N, int SIGN, int PAD, int NL, typename TW>
+__device__ __forceinline__ void fft_lines(cx<T> (&v)[NL][8], int t, cx<T>* lds, int stride, int lstep, const TW& tw)
 {
     static_assert(N >= 8 && (N & (N - 1)) == 0, "power-of-two line length >= 8");
     constexpr int R0 = FftPlan<N>::R0;
@@ -352,23 +389,23 @@ __device__ __forceinline__ void fft_lines(cx<T> (&v)[NL][8], int t, cx<T>* lds, 
     if constexpr (NST > 1) {
         fft_exchange<T, N, R0, 1, PAD, NL>(v, t, lds, stride, lstep);
 #pragma unroll
-        for (int k = 0; k < NL; k++) fft_stage8<T, SIGN>(v[k], tw.w[0]);
+        for (int k = 0; k < NL; k++) tw_stage<T, N, SIGN>(v[k], tw, 0);
     }
     if constexpr (NST > 2) {
         fft_exchange<T, N, 8, R0, PAD, NL>(v, t, lds, stride, lstep);
 #pragma unroll
-        for (int k = 0; k < NL; k++) fft_stage8<T, SIGN>(v[k], tw.w[1]);
+        for (int k = 0; k < NL; k++) tw_stage<T, N, SIGN>(v[k], tw, 1);
     }
     if constexpr (NST > 3) {
         fft_exchange<T, N, 8, R0 * 8, PAD, NL>(v, t, lds, stride, lstep);
 #pragma unroll
-        for (int k = 0; k < NL; k++) fft_stage8<T, SIGN>(v[k], tw.w[2]);
+        for (int k = 0; k < NL; k++) tw_stage<T, N, SIGN>(v[k], tw, 2);
     }
 }
 
 // One line held by the calling thread group.
-template <typename T, int N, int SIGN, int PAD>
-__device__ __forceinline__ void fft_line(cx<T> (&v)[8], int t, cx<T>* lds, int stride, const LineTw<T, N>& tw)
+template <typename T, int N, int SIGN, int PAD, typename TW>
+__device__ __forceinline__ void fft_line(cx<T> (&v)[8], int t, cx<T>* lds, int stride, const TW& tw)
 {
     fft_lines<T, N, SIGN, PAD, 1>(reinterpret_cast<cx<T>(&)[1][8]>(v), t, lds, stride, 0, tw);
 }
@@ -440,6 +477,52 @@ __device__ __forceinline__ void normal_pair(uint64_t seed, uint32_t e, uint32_t 
     }
     const float rad = __builtin_amdgcn_sqrtf(-2.0f * lg);
     const float u2 = fmaf((float)c2, 0x1p-32f, ((float)(c3 >> 11) + 0.5f) * 0x1p-53f);
+    z1 = rad * __builtin_amdgcn_cosf(u2);
+    z2 = rad * __builtin_amdgcn_sinf(u2);
+}
+
+// ---------------------------------------------------------------- noise normals
+// The Fourier-space noise takes two modes' normals from one Philox block: the
+// words are used in pairs (x0, x1) and (x2, x3), each word a uniform
+// u = (x + 1/2) 2^-32 in (0, 1), and Box-Muller gives
+// z1 = sqrt(-2 ln u1) cos(2 pi u2), z2 = sqrt(-2 ln u1) sin(2 pi u2).
+__device__ __forceinline__ void philox_block(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t (&x)[4])
+{
+    philox4x32_10(c0, c1, c2, c3, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+    x[0] = c0;
+    x[1] = c1;
+    x[2] = c2;
+    x[3] = c3;
+}
+
+__device__ __forceinline__ void box_muller32(uint32_t a, uint32_t b, double& z1, double& z2)
+{
+    const double u1 = ((double)a + 0.5) * 0x1p-32;
+    const double u2 = ((double)b + 0.5) * 0x1p-32;
+    const double rad = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    z1 = rad * c;
+    z2 = rad * s;
+}
+
+// Single precision, without branches: u1 < 1/2 is formed directly; for
+// u1 >= 1/2 the exactly formed om = 1 - u1 (from the complement of the word)
+// gives ln u1 by the series -om (1 + om/2 + om^2/3 + ...) when om < 1/64 and
+// by the hardware logarithm of 1 - om otherwise.
+__device__ __forceinline__ void box_muller32(uint32_t a, uint32_t b, float& z1, float& z2)
+{
+    const float ln2 = 0.69314718055994530942f;
+    const bool hi = a >= 0x80000000u;
+    const float u1 = fmaf((float)a, 0x1p-32f, 0x1p-33f);
+    const float om = fmaf((float)(0xffffffffu - a), 0x1p-32f, 0x1p-33f);
+    const float p = fmaf(om, fmaf(om, fmaf(om, fmaf(om, 1.0f / 6.0f, 0.2f), 0.25f), 1.0f / 3.0f), 0.5f);
+    const float lser = -om * fmaf(om, p, 1.0f);
+    const float llog = __builtin_amdgcn_logf(hi ? 1.0f - om : u1) * ln2;
+    const float lg = (hi && om < 0.015625f) ? lser : llog;
+    const float rad = __builtin_amdgcn_sqrtf(-2.0f * lg);
+    const float u2 = fmaf((float)b, 0x1p-32f, 0x1p-33f);
     z1 = rad * __builtin_amdgcn_cosf(u2);
     z2 = rad * __builtin_amdgcn_sinf(u2);
 }

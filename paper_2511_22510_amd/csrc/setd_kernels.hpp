@@ -118,37 +118,64 @@ __device__ __forceinline__ cx<T> nl_pref(const Item& it, T k2)
 }
 
 // ---------------------------------------------------------------- noise (App. B)
-// Unit noise eta_a of the stored mode at FFT positions (j0, j1, jl) for step n.
-// Complex modes draw (z1 + i z2)/sqrt2 at their own linear index e; on the
-// a_d in {0, N_d/2} planes of a real field a self-conjugate mode takes z1 and a
-// conjugate pair draws once at the smaller of the two indices, the partner
-// taking the conjugate.  One Philox evaluation per mode.
-template <typename T>
-__device__ __forceinline__ cx<T> noise_eta(const Geo& g, const Item& it, int j0, int j1, int jl, uint32_t n)
+// Unit noise eta_a of the stored modes for step n.  Complex modes draw
+// (z1 + i z2)/sqrt2; on the a_d in {0, N_d/2} planes of a real field a
+// self-conjugate mode takes z1 and a conjugate pair draws once, at the member
+// with the smaller linear index, the other taking the conjugate.
+// Draws are made for pairs of modes that differ only in the axis-0 position,
+// j and j' = (j mod M) + (7 - j div M) M with M = N0/8 (bins q and 7 - q of
+// one thread of the axis-0 pass): the pair's Philox counter is (P, n, r, 0),
+// P the linear index of the member with j div M < 4 over the axis-0 extent
+// N0/2, and that member takes words (x0, x1), the other (x2, x3).
+struct NoiseSlot {
+    uint32_t P;      // Philox counter word 0
+    uint32_t half;   // 0: words (x0, x1), 1: words (x2, x3)
+    int kind;        // 0: (z1 + i z2)/sqrt2, 1: z1, 2: (z1 - i z2)/sqrt2 drawn at the partner
+};
+
+__device__ __forceinline__ NoiseSlot noise_slot(const Geo& g, int j0, int j1, int jl)
 {
-    const T rs2 = T(0.70710678118654752440084436210484903928);
     const int last = g.ndim - 1;
-    const uint32_t nh = (uint32_t)g.nh_last;
-    const uint32_t e = (g.ndim == 3) ? ((uint32_t)j0 * (uint32_t)g.n[1] + (uint32_t)j1) * nh + (uint32_t)jl
-                                     : (uint32_t)j0 * nh + (uint32_t)jl;
-    uint32_t ectr = e;
-    int kind = 0;   // 0: (z1 + i z2)/sqrt2, 1: z1, 2: (z1 - i z2)/sqrt2 drawn at the partner
+    int d0 = j0, d1 = j1, kind = 0;
     if (!g.cplx && !(jl > 0 && 2 * jl < g.n[last])) {
         const int p0 = j0 ? g.n[0] - j0 : 0;
         const int p1 = (g.ndim == 3 && j1) ? g.n[1] - j1 : 0;
-        const uint32_t ep = (g.ndim == 3) ? ((uint32_t)p0 * (uint32_t)g.n[1] + (uint32_t)p1) * nh + (uint32_t)jl
-                                          : (uint32_t)p0 * nh + (uint32_t)jl;
-        if (ep == e) {
+        if (p0 == j0 && p1 == j1) {
             kind = 1;
-        } else if (ep < e) {
+        } else if (p0 < j0 || (p0 == j0 && p1 < j1)) {
             kind = 2;
-            ectr = ep;
+            d0 = p0;
+            d1 = p1;
         }
     }
+    const int M = g.n[0] >= 8 ? g.n[0] / 8 : 1;
+    const int q = d0 / M;
+    const uint32_t row = (uint32_t)(d0 - q * M + (q < 4 ? q : 7 - q) * M);
+    NoiseSlot s;
+    s.P = ((g.ndim == 3) ? row * (uint32_t)g.n[1] + (uint32_t)d1 : row) * (uint32_t)g.nh_last + (uint32_t)jl;
+    s.half = q >= 4 ? 1u : 0u;
+    s.kind = kind;
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> eta_of(const uint32_t (&x)[4], const NoiseSlot& s)
+{
+    const T rs2 = T(0.70710678118654752440084436210484903928);
     T z1, z2;
-    normal_pair(it.seed, ectr, n, it.r, 0u, z1, z2);
-    if (kind == 1) return {z1, T(0)};
-    return {rs2 * z1, (kind == 2) ? -rs2 * z2 : rs2 * z2};
+    box_muller32(s.half ? x[2] : x[0], s.half ? x[3] : x[1], z1, z2);
+    if (s.kind == 1) return {z1, T(0)};
+    return {rs2 * z1, (s.kind == 2) ? -rs2 * z2 : rs2 * z2};
+}
+
+// one mode (one Philox block)
+template <typename T>
+__device__ __forceinline__ cx<T> noise_eta(const Geo& g, const Item& it, int j0, int j1, int jl, uint32_t n)
+{
+    const NoiseSlot s = noise_slot(g, j0, j1, jl);
+    uint32_t x[4];
+    philox_block(it.seed, s.P, n, it.r, 0u, x);
+    return eta_of<T>(x, s);
 }
 
 // ---------------------------------------------------------------- step counter
@@ -175,6 +202,7 @@ struct RowArgs {
     const Item* items;
     int nrows;   // lines of the last axis per realization (n0 or n0*n1)
     int lpw;     // line groups per workgroup (row pairs for real fields)
+    int iter;    // real fields: groups of lpw pairs a workgroup takes in turn
     int mode;    // MODE_STEP or MODE_IC
     int sub;     // sub-step of the scheduler tick
 };
@@ -213,7 +241,12 @@ __device__ __forceinline__ unsigned xcd_logical(unsigned L, unsigned G)
 // Two real rows a, b travel as one complex line z = a + i b: the inverse uses
 // Z_k = A_k + i B_k (k <= N/2) and conj(A_{N-k}) + i conj(B_{N-k}) above; the
 // forward splits Z back into A_k = (Z_k + conj Z_{N-k})/2 and
-// B_k = (Z_k - conj Z_{N-k})/(2i).  Block: lpw row pairs x N/8 threads.
+// B_k = (Z_k - conj Z_{N-k})/(2i).  Block: lpw row pairs x N/8 threads; it
+// takes iter consecutive groups of lpw pairs in turn.  With PF (prefetch) the
+// loads of the next group are issued, into the registers the current group
+// has just consumed, before the current group's transforms, so that the
+// block's memory traffic overlaps its arithmetic (at the price of those
+// registers).
 // Rows are read and written with buffer accesses relative to the block's first
 // row (the resource covers the block's rows that exist); a lane whose bin has
 // no stored mode uses BUF_OOB, reads zero and writes nothing, so the loads are
@@ -222,7 +255,7 @@ __device__ __forceinline__ unsigned xcd_logical(unsigned L, unsigned G)
 // DA: the 2/3 rule is on; then bins q = 0, 1 (k < N/4) always hold a stored
 // mode, q = 6, 7 (k >= 3N/4) always its mirror, q = 3, 4 never any, and only
 // q = 0..2 are written back, all decided at compile time.
-template <typename T, int N, int PAD, int KIND, bool DA>
+template <typename T, int N, int PAD, int KIND, bool DA, bool PF>
 __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
 {
     const Item it = a.items[blockIdx.y];
@@ -233,28 +266,39 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
     constexpr uint32_t ES = sizeof(cx<T>);
     const int tid = threadIdx.x;
     const int l = tid / TPL, t = tid - l * TPL;
-    const int pair = blockIdx.x * a.lpw + l;
-    const bool valid = 2 * pair < a.nrows;
-    cx<T>* L = lds + l * lds_len<N, PAD>();
+    // KPZ steps hold two lines per row pair in LDS
+    cx<T>* L = lds + l * (KIND == 1 ? 2 : 1) * lds_len<N, PAD>();
     const Geo& g = a.g;
     const int last = g.ndim - 1;
     LineTw<T, N> tw;
     line_tw_load(tw, t, twid<T>(last == 1 ? it.tw1 : it.tw2));
+    // the transforms of a step share their twiddle powers
+    LineTwP<T, N> twp;
+    line_tw_expand(twp, tw);
     const int pitch = g.pitch;
     const int K = g.kp[last];
-    // rows of this block: 2 lpw from row 2 blockIdx.x lpw, clipped to the array
-    const int row0 = 2 * blockIdx.x * a.lpw;
-    const int nrow = min(2 * a.lpw, a.nrows - row0);
+    // pair groups blockIdx.x iter + i, i < niter (the same count in every lane)
+    const int npair = (a.nrows + 1) / 2;
+    const int ngrp = (npair + a.lpw - 1) / a.lpw;
+    const int grp0 = blockIdx.x * a.iter;
+    // without prefetch the launch gives every workgroup one group
+    const int niter = PF ? min(a.iter, ngrp - grp0) : 1;
+    // rows of this block, clipped to the array
+    const int row0 = 2 * grp0 * a.lpw;
+    const int nrow = min(2 * a.lpw * niter, a.nrows - row0);
     const size_t boff = (size_t)row0 * pitch;
     cx<T>* const bufp = reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big) + boff;
     const rsrc_t rb = make_rsrc(bufp, (uint32_t)nrow * (uint32_t)pitch * ES);
-    // byte offsets of the pair's two rows within the block (per lane: a
-    // wavefront can hold several pairs); BUF_OOB plus a row offset stays out
-    // of range
-    const uint32_t o0 = (uint32_t)(2 * l) * (uint32_t)pitch * ES, o1 = o0 + (uint32_t)pitch * ES;
+    const uint32_t RS = (uint32_t)pitch * ES;   // bytes per row
+    // the pair of lane group l in group i, whether it exists, and the byte
+    // offset of its first row within the block (a wavefront can hold several
+    // pairs); BUF_OOB plus a row offset stays out of range
+    auto pair_of = [&](int i) { return (grp0 + i) * a.lpw + l; };
+    auto pair_ok = [&](int i) { return 2 * pair_of(i) < a.nrows; };
+    auto row_off = [&](int i) { return (uint32_t)(2 * (i * a.lpw + l)) * RS; };
     // stored column read for bin k (k itself, or N - k for the mirrored upper
     // half), BUF_OOB where the bin has no stored mode
-    auto col_off = [&](int q) -> uint32_t {
+    auto col_off = [&](int q, bool valid) -> uint32_t {
         const int k = t + q * TPL;
         if (!valid) return BUF_OOB;
         if (DA && q <= 1) return (uint32_t)k * ES;
@@ -264,30 +308,14 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
         return BUF_OOB;
     };
     auto empty = [](int q) { return DA && (q == 3 || q == 4); };   // no stored mode in any lane
+    // bin q of the lower half (k <= N/2 side) in the packing below
+    auto lower = [&](int q) { return (DA && q <= 1) || (!(DA && q >= 6) && t + q * TPL <= K); };
     const T inv = (T)it.inv_vol;
-    cx<T> v[8];
-
-    if constexpr (KIND == 2) {
-        // i.i.d. N(0, sigma^2) per site, Philox counter (site, 0, r, 1)
-        const T sig = (T)it.ic_sigma;
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int n = t + q * TPL;
-            v[q] = czero<T>();
-            if (valid) {
-                T za, zb, zc, zd;
-                const uint32_t s0 = (uint32_t)(2 * pair) * (uint32_t)N + (uint32_t)n;
-                normal_pair(it.seed, s0, 0u, it.r, 1u, za, zb);
-                normal_pair(it.seed, s0 + (uint32_t)N, 0u, it.r, 1u, zc, zd);
-                v[q] = {sig * za, sig * zc};
-            }
-        }
-    } else if constexpr (KIND == 1) {
-        // |grad h|^2 with d0 h = IFFT[i k0 h] (from pre1) and d1 h = IFFT[i k1 h]
-        const rsrc_t rb2 = make_rsrc(reinterpret_cast<cx<T>*>(it.pre1) + boff, (uint32_t)nrow * (uint32_t)pitch * ES);
-        const T dkl = (T)it.dk[last];
-        T gsq[2][8];
-        cx<T> A[2][8], X[2][8];
+    // Model A/B: rows a, b of a pair; KPZ: pre1 (d0 h) and pre (h) rows
+    cx<T> A[2][8], X[2][8];
+    auto load_rows = [&](int i) {
+        const bool vi = pair_ok(i);
+        const uint32_t oa = row_off(i);
 #pragma unroll
         for (int s = 0; s < 2; s++) {
 #pragma unroll
@@ -295,97 +323,129 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
                 A[s][q] = czero<T>();
                 X[s][q] = czero<T>();
                 if (empty(q)) continue;
-                const uint32_t c = col_off(q);
-                A[s][q] = bload<T>(rb2, c + (s ? o1 : o0), 0);
-                X[s][q] = bload<T>(rb, c + (s ? o1 : o0), 0);
+                const uint32_t c = col_off(q, vi) + oa + (s ? RS : 0u);
+                if constexpr (KIND == 1) {
+                    const rsrc_t rb2 = make_rsrc(reinterpret_cast<cx<T>*>(it.pre1) + boff, (uint32_t)nrow * RS);
+                    A[s][q] = bload<T>(rb2, c, 0);
+                    X[s][q] = bload<T>(rb, c, 0);
+                } else {
+                    A[s][q] = bload<T>(rb, c, 0);
+                }
             }
         }
+    };
+    if constexpr (KIND != 2 && PF) load_rows(0);
+
+#pragma unroll 1
+    for (int i = 0; i < niter; i++) {
+        const int pair = pair_of(i);
+        const bool valid = pair_ok(i);
+        const uint32_t o0 = row_off(i), o1 = o0 + RS;
+        cx<T> v[8];
+        if constexpr (KIND != 2 && !PF) load_rows(i);
+        if constexpr (KIND == 2) {
+            // i.i.d. N(0, sigma^2) per site, Philox counter (site, 0, r, 1)
+            const T sig = (T)it.ic_sigma;
 #pragma unroll
-        for (int s = 0; s < 2; s++) {
+            for (int q = 0; q < 8; q++) {
+                const int n = t + q * TPL;
+                v[q] = czero<T>();
+                if (valid) {
+                    T za, zb, zc, zd;
+                    const uint32_t s0 = (uint32_t)(2 * pair) * (uint32_t)N + (uint32_t)n;
+                    normal_pair(it.seed, s0, 0u, it.r, 1u, za, zb);
+                    normal_pair(it.seed, s0 + (uint32_t)N, 0u, it.r, 1u, zc, zd);
+                    v[q] = {sig * za, sig * zc};
+                }
+            }
+        } else if constexpr (KIND == 1) {
+            // |grad h|^2 with d0 h = IFFT[i k0 h] (from pre1) and d1 h = IFFT[i k1 h];
+            // the two rows' lines go through the stages together (one set of
+            // barriers, twice the independent work per exchange), interleaved in LDS
+            const T dkl = (T)it.dk[last];
+            cx<T> w[2][8];
+#pragma unroll
+            for (int s = 0; s < 2; s++) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const int k = t + q * TPL;
+                    cx<T> z = czero<T>();
+                    if (empty(q)) {
+                    } else if (lower(q)) {
+                        cx<T> Aq = A[s][q];
+                        const T kk = (2 * k == N) ? T(0) : dkl * (T)k;
+                        cx<T> B = {-kk * X[s][q].y, kk * X[s][q].x};
+                        if (k == 0 || 2 * k == N) {
+                            Aq.y = T(0);
+                            B.y = T(0);
+                        }
+                        z = {Aq.x - B.y, Aq.y + B.x};
+                    } else {
+                        // mirrored bins (zeros where nothing is stored)
+                        const T kk = dkl * (T)(N - k);
+                        const cx<T> B = {-kk * X[s][q].y, kk * X[s][q].x};
+                        z = {A[s][q].x + B.y, B.x - A[s][q].y};
+                    }
+                    w[s][q] = z;
+                }
+            }
+            if (PF && i + 1 < niter) load_rows(i + 1);
+            fft_lines<T, N, +1, PAD, 2>(w, t, L, 2, 1, twp);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const T x0 = w[0][q].x * inv, y0 = w[0][q].y * inv;
+                const T x1 = w[1][q].x * inv, y1 = w[1][q].y * inv;
+                v[q] = {x0 * x0 + y0 * y0, x1 * x1 + y1 * y1};
+            }
+        } else {
 #pragma unroll
             for (int q = 0; q < 8; q++) {
                 const int k = t + q * TPL;
-                cx<T> z = czero<T>();
+                cx<T> z;
                 if (empty(q)) {
-                } else if ((DA && q <= 1) || (!(DA && q >= 6) && k <= K)) {
-                    cx<T> Aq = A[s][q];
-                    const T kk = (2 * k == N) ? T(0) : dkl * (T)k;
-                    cx<T> B = {-kk * X[s][q].y, kk * X[s][q].x};
+                    z = czero<T>();
+                } else if (lower(q)) {
+                    cx<T> a0 = A[0][q], b0 = A[1][q];
                     if (k == 0 || 2 * k == N) {
-                        Aq.y = T(0);
-                        B.y = T(0);
+                        a0.y = T(0);
+                        b0.y = T(0);
                     }
-                    z = {Aq.x - B.y, Aq.y + B.x};
+                    z = {a0.x - b0.y, a0.y + b0.x};
                 } else {
                     // mirrored bins (zeros where nothing is stored)
-                    const T kk = dkl * (T)(N - k);
-                    const cx<T> B = {-kk * X[s][q].y, kk * X[s][q].x};
-                    z = {A[s][q].x + B.y, B.x - A[s][q].y};
+                    z = {A[0][q].x + A[1][q].y, A[1][q].x - A[0][q].y};
                 }
                 v[q] = z;
             }
-            fft_line<T, N, +1, PAD>(v, t, L, 1, tw);
+            if (PF && i + 1 < niter) load_rows(i + 1);
+            fft_line<T, N, +1, PAD>(v, t, L, 1, twp);
+            // phi^3 in real space (Model A and B)
 #pragma unroll
             for (int q = 0; q < 8; q++) {
                 const T x = v[q].x * inv, y = v[q].y * inv;
-                gsq[s][q] = x * x + y * y;
+                v[q] = {x * x * x, y * y * y};
             }
         }
-#pragma unroll
-        for (int q = 0; q < 8; q++) v[q] = {gsq[0][q], gsq[1][q]};
-    } else {
-        cx<T> A[8], B[8];
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-            A[q] = czero<T>();
-            B[q] = czero<T>();
-            if (empty(q)) continue;
-            const uint32_t c = col_off(q);
-            A[q] = bload<T>(rb, c + o0, 0);
-            B[q] = bload<T>(rb, c + o1, 0);
-        }
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int k = t + q * TPL;
-            cx<T> z;
-            if (empty(q)) {
-                z = czero<T>();
-            } else if ((DA && q <= 1) || (!(DA && q >= 6) && k <= K)) {
-                cx<T> a0 = A[q], b0 = B[q];
-                if (k == 0 || 2 * k == N) {
-                    a0.y = T(0);
-                    b0.y = T(0);
-                }
-                z = {a0.x - b0.y, a0.y + b0.x};
-            } else {
-                // mirrored bins (zeros where nothing is stored)
-                z = {A[q].x + B[q].y, B[q].x - A[q].y};
-            }
-            v[q] = z;
-        }
-        fft_line<T, N, +1, PAD>(v, t, L, 1, tw);
-        // phi^3 in real space (Model A and B)
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const T x = v[q].x * inv, y = v[q].y * inv;
-            v[q] = {x * x * x, y * y * y};
-        }
-    }
 
-    fft_line<T, N, -1, PAD>(v, t, L, 1, tw);
-    __syncthreads();
+        fft_line<T, N, -1, PAD>(v, t, L, 1, twp);
+        __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; q++) L[lds_slot<PAD>(t + q * TPL)] = v[q];
-    __syncthreads();
+        for (int q = 0; q < 8; q++) {
+            // under the 2/3 rule the split below reads bins k < 3N/8 and N - k > 5N/8 only
+            if (DA && (q == 3 || q == 4)) continue;
+            L[lds_slot<PAD>(t + q * TPL)] = v[q];
+        }
+        __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
-        // under the 2/3 rule only q <= 2 (k < 3N/8) can hold a stored mode
-        if (DA && q > 2) continue;
-        const int k = t + q * TPL;
-        const cx<T> Zk = L[lds_slot<PAD>(k)], Zm = L[lds_slot<PAD>((N - k) & (N - 1))];
-        const uint32_t c = (valid && ((DA && q <= 1) || k <= K)) ? (uint32_t)k * ES : BUF_OOB;
-        bstore<T>(rb, c + o0, 0, {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y - Zm.y)});
-        bstore<T>(rb, c + o1, 0, {T(0.5) * (Zk.y + Zm.y), T(0.5) * (Zm.x - Zk.x)});
+        for (int q = 0; q < 8; q++) {
+            // under the 2/3 rule only q <= 2 (k < 3N/8) can hold a stored mode
+            if (DA && q > 2) continue;
+            const int k = t + q * TPL;
+            const cx<T> Zk = L[lds_slot<PAD>(k)], Zm = L[lds_slot<PAD>((N - k) & (N - 1))];
+            const uint32_t c = (valid && ((DA && q <= 1) || k <= K)) ? (uint32_t)k * ES : BUF_OOB;
+            bstore<T>(rb, c + o0, 0, {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y - Zm.y)});
+            bstore<T>(rb, c + o1, 0, {T(0.5) * (Zk.y + Zm.y), T(0.5) * (Zm.x - Zk.x)});
+        }
     }
 }
 
@@ -800,22 +860,33 @@ k_axis0r(AxisArgs a)
     };
     if constexpr (EARLY) load_state();
     // unit noise of the six bins that can hold a stored mode (q = 0, 1, 2,
-    // 5, 6, 7), while the loads are in flight
-    cx<T> ez[6];
+    // 5, 6, 7), while the loads are in flight: bins k and 7 - k share a Philox
+    // block (a second one only where a Hermitian partner draws for one of
+    // them, in the a_last = 0 plane of a real field)
+    cx<T> elo[3], ehi[3];
 #pragma unroll
-    for (int k = 0; k < 6; k++) ez[k] = czero<T>();
+    for (int k = 0; k < 3; k++) elo[k] = ehi[k] = czero<T>();
+    const uint32_t nn = (uint32_t)(LEAN ? nstep + 1 : nstep);
 #pragma unroll 1
-    for (int k = 0; k < 6; k++) {
-        const int j0 = t + (k < 3 ? k : k + 2) * TPL;
-        cx<T> e = czero<T>();
-        if (cv && stored_idx(j0, N0, kept0, kp0) >= 0)
-            e = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)(LEAN ? nstep + 1 : nstep));
-#pragma unroll
-        for (int s = 0; s < 5; s++) ez[s] = ez[s + 1];
-        ez[5] = e;
+    for (int k = 0; k < 3; k++) {
+        const int ja = t + k * TPL, jb = t + (7 - k) * TPL;
+        const NoiseSlot sa = noise_slot(g, ja, j1, jl), sb = noise_slot(g, jb, j1, jl);
+        uint32_t x[4];
+        philox_block(it.seed, sa.P, nn, it.r, 0u, x);
+        cx<T> ea = eta_of<T>(x, sa);
+        if (sb.P != sa.P) philox_block(it.seed, sb.P, nn, it.r, 0u, x);
+        cx<T> eb = eta_of<T>(x, sb);
+        if (!(cv && stored_idx(ja, N0, kept0, kp0) >= 0)) ea = czero<T>();
+        if (!(cv && stored_idx(jb, N0, kept0, kp0) >= 0)) eb = czero<T>();
+        elo[0] = elo[1];
+        elo[1] = elo[2];
+        elo[2] = ea;
+        ehi[2] = ehi[1];
+        ehi[1] = ehi[0];
+        ehi[0] = eb;
     }
 #pragma unroll
-    for (int q = 0; q < 8; q++) eta[q] = live(q) ? ez[q < 3 ? q : q - 2] : czero<T>();
+    for (int q = 0; q < 8; q++) eta[q] = q < 3 ? elo[q] : (q > 4 ? ehi[q - 5] : czero<T>());
     LineTw<T, N0> tw;
     line_tw_load(tw, t, twid<T>(it.tw0));
     cx<T>* L = lds + c0;   // element e of the column at L + e * TILE

@@ -30,7 +30,7 @@ namespace setd {
 
 template <typename T, int N, int PAD>
 static hipError_t launch_row_np(const Geo& g, const Item* items, int nitems, int mode, int sub, int big_block,
-                                bool kpz, hipStream_t s)
+                                int iter, bool kpz, hipStream_t s)
 {
     constexpr int tpl = N / 8;
     const int lpw = big_block ? (tpl >= 256 ? 1 : 256 / tpl) : (tpl >= 64 ? 1 : 64 / tpl);
@@ -39,40 +39,53 @@ static hipError_t launch_row_np(const Geo& g, const Item* items, int nitems, int
     a.items = items;
     a.nrows = (g.ndim == 3) ? g.n[0] * g.n[1] : g.n[0];
     a.lpw = lpw;
+    a.iter = (g.cplx || mode != MODE_STEP) ? 1 : iter;
     a.mode = mode;
     a.sub = sub;
-    const int lines = g.cplx ? a.nrows : a.nrows / 2;
-    dim3 grid((lines + lpw - 1) / lpw, nitems);
+    const int lines = g.cplx ? a.nrows : (a.nrows + 1) / 2;
+    const int groups = (lines + lpw - 1) / lpw;
+    dim3 grid((groups + a.iter - 1) / a.iter, nitems);
     dim3 block(lpw * tpl);
-    const size_t lds = (size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T);
+    // KPZ steps hold two lines per row pair
+    const size_t lds = (size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T) * ((kpz && !g.cplx) ? 2 : 1);
     if (g.cplx) {
         if (mode == MODE_IC) hipLaunchKernelGGL((k_row_cplx<T, N, PAD, true>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((k_row_cplx<T, N, PAD, false>), grid, block, lds, s, a);
     } else if (mode == MODE_IC) {
-        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 2, true>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_row_real<T, N, PAD, 2, false>), grid, block, lds, s, a);
+        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 2, true, false>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_row_real<T, N, PAD, 2, false, false>), grid, block, lds, s, a);
     } else if (kpz) {
-        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, true>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, false>), grid, block, lds, s, a);
+        if (a.iter > 1) {
+            if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, true, true>), grid, block, lds, s, a);
+            else hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, false, true>), grid, block, lds, s, a);
+        } else {
+            if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, true, false>), grid, block, lds, s, a);
+            else hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, false, false>), grid, block, lds, s, a);
+        }
+    } else if (a.iter > 1) {
+        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, true, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, false, true>), grid, block, lds, s, a);
     } else {
-        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, true>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, false>), grid, block, lds, s, a);
+        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, true, false>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, false, false>), grid, block, lds, s, a);
     }
     return hipGetLastError();
 }
 
-// var: bit 0 = LDS padding, bit 1 = 256-thread blocks
+// var: bit 0 = LDS padding, bit 1 = 256-thread blocks, bits 2-3 = log2 of the
+// pair groups a workgroup takes in turn (real-field steps)
 template <typename T>
 hipError_t launch_row(const Geo& g, const Item* items, int nitems, int mode, int sub, int var, int kpz,
                       hipStream_t s)
 {
     const int N = g.n[g.ndim - 1];
     const int big = (var >> 1) & 1;
+    const int iter = 1 << ((var >> 2) & 3);
     const bool kp = kpz && mode == MODE_STEP;
     if (var & 1) {
-        SETD_DISPATCH_N(N, return (launch_row_np<T, NN, 3>(g, items, nitems, mode, sub, big, kp, s)));
+        SETD_DISPATCH_N(N, return (launch_row_np<T, NN, 3>(g, items, nitems, mode, sub, big, iter, kp, s)));
     } else {
-        SETD_DISPATCH_N(N, return (launch_row_np<T, NN, 0>(g, items, nitems, mode, sub, big, kp, s)));
+        SETD_DISPATCH_N(N, return (launch_row_np<T, NN, 0>(g, items, nitems, mode, sub, big, iter, kp, s)));
     }
     return hipSuccess;
 }

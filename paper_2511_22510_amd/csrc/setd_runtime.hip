@@ -485,13 +485,13 @@ setd_status Plan::autotune()
     // SETD_VARIANT="row,axis0,axis1" pins the variants (tests, reproducible timing)
     if (const char* pin = std::getenv("SETD_VARIANT")) {
         int r = 0, a0 = 0, a1 = 0;
-        if (sscanf(pin, "%d,%d,%d", &r, &a0, &a1) == 3 && r >= 0 && r < 4 && a0 >= 0 && a0 < 6 && a1 >= 0 && a1 < 4) {
+        if (sscanf(pin, "%d,%d,%d", &r, &a0, &a1) == 3 && r >= 0 && r < 16 && a0 >= 0 && a0 < 6 && a1 >= 0 && a1 < 4) {
             tune.row = r;
             tune.ax0 = (lean && a0 < 4) ? 4 : a0;   // a lean plan steps with the register kernel
             tune.ax1 = a1;
             return SETD_OK;
         }
-        return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row and axis1 in 0..3, axis0 in 0..5");
+        return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row in 0..15, axis0 in 0..5, axis1 in 0..3");
     }
     const char* env = std::getenv("SETD_AUTOTUNE");
     if (env && env[0] == '0') return SETD_OK;
@@ -514,9 +514,10 @@ setd_status Plan::autotune()
     const int row_pass = (d.ndim == 2) ? 0 : 1;
     const int ax0_pass = (d.ndim == 2) ? 1 : 3;
     struct Knob { int* var; int first; int nvar; int pass; int pass2; };
-    // axis-0 variants 4 and 5 (register update) exist for dealiased plans, and
-    // are the only ones a plan keeping the SETD2 carry can step with
-    Knob knobs[3] = {{&tune.row, 0, 4, row_pass, -1},
+    // row variants 4..15 (several pair groups per workgroup) exist for real
+    // fields; axis-0 variants 4 and 5 (register update) for dealiased plans,
+    // and are the only ones a plan keeping the SETD2 carry can step with
+    Knob knobs[3] = {{&tune.row, 0, d.complex_field ? 4 : 16, row_pass, -1},
                      {&tune.ax0, lean ? 4 : 0, g.dealias ? 6 : 4, ax0_pass, -1},
                      {&tune.ax1, 0, 4, 0, 2}};
     const int nknobs = (d.ndim == 3) ? 3 : 2;

@@ -32,7 +32,7 @@ struct Layout {
 
 // Kernel variants of a plan's passes (see setd_launch_impl.hpp).
 struct Tune {
-    int row = 0;   // 0..3
+    int row = 0;   // 0..15 (0..3 for complex fields)
     int ax0 = 0;   // 0..5
     int ax1 = 0;   // 0..3
 };

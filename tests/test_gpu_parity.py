@@ -308,13 +308,15 @@ VARIANT_CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", ["0,0,0", "1,1,1", "2,2,2", "3,3,3", "1,2,3", "3,0,1", "0,4,0", "2,5,3"])
+@pytest.mark.parametrize("variant", ["0,0,0", "1,1,1", "2,2,2", "3,3,3", "1,2,3", "3,0,1", "0,4,0", "2,5,3",
+                                     "5,4,0", "14,1,1", "11,5,2", "15,0,3"])
 @pytest.mark.parametrize("history", [0, 1])
 def test_every_kernel_variant_matches_oracle(variant, history, monkeypatch):
-    """Each autotuner choice (row: LDS padding x block size; axis passes: tile
-    width x columns per thread; axis-0 variants 4 and 5: the register-update
-    kernel at two tile widths) gives the same trajectory, with either SETD2
-    storage (the carry-only storage always steps with variants 4 or 5)."""
+    """Each autotuner choice (row: LDS padding x block size x row-pair groups
+    per workgroup; axis passes: tile width x columns per thread; axis-0
+    variants 4 and 5: the register-update kernel at two tile widths) gives
+    the same trajectory, with either SETD2 storage (the carry-only storage
+    always steps with variants 4 or 5)."""
     monkeypatch.setenv("SETD_VARIANT", variant)
     for p in VARIANT_CASES:
         p = dict(p, history_readback=history)

@@ -39,6 +39,53 @@ def test_hermitian_structure_and_count(shape):
     assert draws == int(np.prod(shape))
 
 
+@pytest.mark.parametrize("kind,shape", [("real", (64, 16)), ("real", (16, 8, 16)), ("cplx", (32, 16)),
+                                        ("real", (4, 8))])
+def test_noise_slots(kind, shape):
+    """Every draw has a Philox slot of its own; the conjugate member of a pair
+    reuses its partner's; one block serves the axis-0 positions j and
+    (j mod M) + (7 - j div M) M, M = N0/8 (1 for N0 < 8), the lower one taking
+    half 0; and eta is Box-Muller of that slot's words (App. B)."""
+    if kind == "real":
+        p = W.model_a(list(shape), dealias=0, ic_kind=0, T=1.0, r=1.0, seed=11)
+    else:
+        p = W.cgl(list(shape), dealias=0, ic_kind=0, T=1.0, seed=11)
+    s = O.Sim(p)
+    G = s.coef(3)
+    n = 5
+    eta = (s.noise_xi(n)[0] / np.where(G > 0, G, 1)).reshape(-1)
+    spec = s.spec_shape
+    S = int(np.prod(spec[1:]))
+    N0 = shape[0]
+    M = N0 // 8 if N0 >= 8 else 1
+    owners = {}
+    blocks = {}
+    for e in range(int(np.prod(spec))):
+        P, half, kd = s.noise_slot(e)
+        idx = np.unravel_index(e, spec)
+        if kd == 2:
+            # the conjugate partner -a on the a_last plane draws
+            partner = tuple((-idx[i]) % shape[i] for i in range(len(shape) - 1)) + (idx[-1],)
+            ep = int(np.ravel_multi_index(partner, spec))
+            assert ep < e and s.noise_slot(ep) == (P, half, 0)
+            continue
+        assert (P, half) not in owners, "two draws share a slot"
+        owners[(P, half)] = e
+        blocks.setdefault(P, []).append((idx[0], half, e % S))
+        assert P < (N0 // 2 if N0 >= 8 else N0) * S
+        z1, z2 = O.noise_normals(11, P, n, 0, half)
+        want = z1 if kd == 1 else (z1 + 1j * z2) / np.sqrt(2)
+        assert eta[e] == pytest.approx(want, abs=1e-15)
+    for P, members in blocks.items():
+        for j0, half, rest in members:
+            assert half == int(j0 // M >= 4)
+            q = j0 // M
+            assert P == (j0 % M + min(q, 7 - q) * M) * S + rest
+        if len(members) == 2:
+            (ja, _, ra), (jb, _, rb) = members
+            assert ra == rb and jb == ja % M + (7 - ja // M) * M
+
+
 def test_noise_is_real_white_noise_in_real_space():
     """App. A sanity check: a unit-variance Hermitian eta_a is, after the inverse
     transform, real noise with per-site variance N^-d."""
