@@ -215,7 +215,8 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
 
     rv = int(info.variants[0])
-    pass_names = ["k_row_real<float,512,pad=%d,block=%d>" % (3 if rv & 1 else 0, 256 if rv & 2 else 64),
+    pass_names = ["k_row_real<float,512,pad=%d,block=%d,pair_groups=%d>" % (3 if rv & 1 else 0, 256 if rv & 2 else 64,
+                                                                           1 << ((rv >> 2) & 3)),
                   ("k_axis0r<float,512,tile=%d>" % info.axis_tile[0]) if int(info.variants[1]) >= 4 else
                   "k_axis0<float,512,tile=%d,cols_per_thread=%d>" % (info.axis_tile[0], info.axis_tile[1])]
     tot_ms = prof[:, 0]
