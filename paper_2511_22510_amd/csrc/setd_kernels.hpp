@@ -148,9 +148,10 @@ __device__ __forceinline__ NoiseSlot noise_slot(const Geo& g, int j0, int j1, in
             d1 = p1;
         }
     }
-    const int M = g.n[0] >= 8 ? g.n[0] / 8 : 1;
-    const int q = d0 / M;
-    const uint32_t row = (uint32_t)(d0 - q * M + (q < 4 ? q : 7 - q) * M);
+    // M = N0/8 is a power of two (lattice extents are)
+    const int sh = g.n[0] >= 8 ? __ffs(g.n[0]) - 4 : 0;
+    const int q = d0 >> sh;
+    const uint32_t row = (uint32_t)(d0 - (q << sh) + ((q < 4 ? q : 7 - q) << sh));
     NoiseSlot s;
     s.P = ((g.ndim == 3) ? row * (uint32_t)g.n[1] + (uint32_t)d1 : row) * (uint32_t)g.nh_last + (uint32_t)jl;
     s.half = q >= 4 ? 1u : 0u;
@@ -867,17 +868,31 @@ k_axis0r(AxisArgs a)
 #pragma unroll
     for (int k = 0; k < 3; k++) elo[k] = ehi[k] = czero<T>();
     const uint32_t nn = (uint32_t)(LEAN ? nstep + 1 : nstep);
+    // off the a_last in {0, N_last/2} planes of a real field the pair's block
+    // is the one of row t + k N0/8 (bin k half 0, bin 7 - k half 1); on them a
+    // Hermitian partner may draw instead (noise_slot)
+    const bool herm = !g.cplx && !(jl > 0 && 2 * jl < g.n[last]);
+    const uint32_t S = (g.ndim == 3) ? (uint32_t)g.n[1] * (uint32_t)g.nh_last : (uint32_t)g.nh_last;
+    const uint32_t rest = (g.ndim == 3) ? (uint32_t)j1 * (uint32_t)g.nh_last + (uint32_t)jl : (uint32_t)jl;
 #pragma unroll 1
     for (int k = 0; k < 3; k++) {
         const int ja = t + k * TPL, jb = t + (7 - k) * TPL;
-        const NoiseSlot sa = noise_slot(g, ja, j1, jl), sb = noise_slot(g, jb, j1, jl);
+        NoiseSlot sa, sb;
+        if (herm) {
+            sa = noise_slot(g, ja, j1, jl);
+            sb = noise_slot(g, jb, j1, jl);
+        } else {
+            sa = {(uint32_t)ja * S + rest, 0u, 0};
+            sb = {sa.P, 1u, 0};
+        }
         uint32_t x[4];
         philox_block(it.seed, sa.P, nn, it.r, 0u, x);
         cx<T> ea = eta_of<T>(x, sa);
         if (sb.P != sa.P) philox_block(it.seed, sb.P, nn, it.r, 0u, x);
         cx<T> eb = eta_of<T>(x, sb);
-        if (!(cv && stored_idx(ja, N0, kept0, kp0) >= 0)) ea = czero<T>();
-        if (!(cv && stored_idx(jb, N0, kept0, kp0) >= 0)) eb = czero<T>();
+        // bins 0, 1, 6, 7 always hold a stored mode, 2 and 5 as stored() says
+        if (!(cv && (k < 2 || stored(2)))) ea = czero<T>();
+        if (!(cv && (k < 2 || stored(5)))) eb = czero<T>();
         elo[0] = elo[1];
         elo[1] = elo[2];
         elo[2] = ea;
