@@ -140,6 +140,10 @@ typedef struct {
                                  workgroup takes in turn (real fields); axis-0
                                  variants 4 and 5 update in registers           */
     int axis_tile[2];         /* axis-0 pass: column tile width, columns per thread */
+    int streams;              /* 2 when setd_step runs the two halves of the
+                                 realizations on the bound stream and an
+                                 auxiliary one of the plan (joined again before
+                                 setd_step returns), else 1                      */
 } setd_plan_info_t;
 
 typedef struct setd_plan setd_plan;

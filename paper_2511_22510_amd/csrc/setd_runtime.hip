@@ -339,6 +339,11 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
     ws = (char*)dev;
     stream = s;
     const int last = d.ndim - 1;
+    if (R >= 2 && split_ok && !aux) {
+        SETD_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+        SETD_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+        SETD_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    }
 
     items.assign(R, Item{});
     for (int r = 0; r < R; r++) {
@@ -468,7 +473,7 @@ static void tune_cache_load()
     std::ifstream f(path);
     std::string key;
     Tune t;
-    while (f >> key >> t.row >> t.ax0 >> t.ax1) g_tune_cache[key] = t;
+    while (f >> key >> t.row >> t.ax0 >> t.ax1 >> t.split) g_tune_cache[key] = t;
 }
 
 static void tune_cache_store(const std::string& key, const Tune& t)
@@ -477,7 +482,7 @@ static void tune_cache_store(const std::string& key, const Tune& t)
     const char* path = std::getenv("SETD_TUNE_CACHE");
     if (!path) return;
     std::ofstream f(path, std::ios::app);
-    f << key << " " << t.row << " " << t.ax0 << " " << t.ax1 << "\n";
+    f << key << " " << t.row << " " << t.ax0 << " " << t.ax1 << " " << t.split << "\n";
 }
 
 setd_status Plan::autotune()
@@ -489,6 +494,9 @@ setd_status Plan::autotune()
             tune.row = r;
             tune.ax0 = (lean && a0 < 4) ? 4 : a0;   // a lean plan steps with the register kernel
             tune.ax1 = a1;
+            // SETD_SPLIT=2 pins split steps too
+            const char* sp = std::getenv("SETD_SPLIT");
+            tune.split = (sp && sp[0] == '2') ? 2 : 1;
             return SETD_OK;
         }
         return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row in 0..15, axis0 in 0..5, axis1 in 0..3");
@@ -552,6 +560,25 @@ setd_status Plan::autotune()
         }
         *kb.var = best_v;
     }
+    // whole steps with the realizations in one launch per pass, or split in
+    // halves over two streams
+    if (st == SETD_OK && aux && R >= 2) {
+        float ms_split[2] = {0.0f, 0.0f};
+        for (int sp = 1; sp <= 2 && st == SETD_OK; sp++) {
+            if ((st = run_steps(2, sp)) != SETD_OK) break;   // warm-up
+            if (hipEventRecord(e0, stream) != hipSuccess) { st = fail(SETD_E_DEVICE, "event record failed"); break; }
+            if ((st = run_steps(4, sp)) != SETD_OK) break;
+            if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                st = fail(SETD_E_DEVICE, "event wait failed");
+                break;
+            }
+            (void)hipEventElapsedTime(&ms_split[sp - 1], e0, e1);
+            if (const char* vb = std::getenv("SETD_TUNE_VERBOSE"))
+                if (vb[0] == '1') fprintf(stderr, "setd tune %s streams %d: %.1f us per step\n", key.c_str(), sp, ms_split[sp - 1] * 1e3f / 4);
+        }
+        // keep the split only for a clear gain
+        tune.split = (st == SETD_OK && ms_split[1] < 0.97f * ms_split[0]) ? 2 : 1;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != SETD_OK) return st;
@@ -561,6 +588,52 @@ setd_status Plan::autotune()
 }
 
 
+// The realizations of a plan are independent: with split = 2 the first half
+// steps on the plan's stream and the second on the auxiliary stream, forked
+// from and joined back into the plan's stream with events, so that the passes
+// of one half overlap those of the other.  Each realization runs the same
+// kernels on the same data either way.
+setd_status Plan::run_steps(int64_t n, int split)
+{
+    const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
+    if (split != 2 || !aux || R < 2 || n <= 0) {
+        for (int64_t i = 0; i < n; i++) {
+            setd_status st = launch_step(items_dev, R, 0, stream);
+            if (st != SETD_OK) return st;
+        }
+        return SETD_OK;
+    }
+    const int h = R / 2;
+    SETD_HIP(hipEventRecord(ev_fork, stream));
+    SETD_HIP(hipStreamWaitEvent(aux, ev_fork, 0));
+    setd_status st = SETD_OK;
+    for (int64_t i = 0; i < n && st == SETD_OK; i++) {
+        st = launch_step(items_dev, h, 0, stream);
+        if (st == SETD_OK) st = launch_step(items_dev + h, R - h, 0, aux);
+    }
+    // join even after a failed launch, so that nothing is left running on aux
+    SETD_HIP(hipEventRecord(ev_join, aux));
+    SETD_HIP(hipStreamWaitEvent(stream, ev_join, 0));
+    return st;
+}
+
+void Plan::release()
+{
+    for (auto& ev : events) {
+        (void)hipEventDestroy(ev.a);
+        (void)hipEventDestroy(ev.b);
+    }
+    events.clear();
+    if (aux) {
+        (void)hipStreamSynchronize(aux);
+        (void)hipStreamDestroy(aux);
+        aux = nullptr;
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    ev_fork = ev_join = nullptr;
+}
+
 setd_status Plan::step(int64_t n)
 {
     if (!bound) return fail(SETD_E_STATE, "plan not bound");
@@ -568,12 +641,13 @@ setd_status Plan::step(int64_t n)
     if (step_host + n >= (int64_t)1 << 32) return fail(SETD_E_INVAL, "step index would exceed 2^32");
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
     if (n > 0) phi_valid = !lean;
+    if (!profiling) {
+        setd_status st = run_steps(n, tune.split);
+        if (st != SETD_OK) return st;
+        step_host += n;
+        return SETD_OK;
+    }
     for (int64_t i = 0; i < n; i++) {
-        if (!profiling) {
-            setd_status st = launch_step(items_dev, R, 0, stream);
-            if (st != SETD_OK) return st;
-            continue;
-        }
         for (int k = 0; k < passes_per_step(); k++) {
             EvPair ev{k, nullptr, nullptr};
             SETD_HIP(hipEventCreate(&ev.a));
@@ -879,6 +953,7 @@ setd_status setd_plan_info(const setd_plan* plan, setd_plan_info_t* info)
     info->variants[0] = p.tune.row;
     info->variants[1] = p.tune.ax0;
     info->variants[2] = p.tune.ax1;
+    info->streams = (p.tune.split == 2 && p.aux) ? 2 : 1;
     setd::axis_shape(p.d.precision, p.g.n[0], p.tune.ax0, &info->axis_tile[0], &info->axis_tile[1]);
     return SETD_OK;
 }
@@ -948,12 +1023,7 @@ setd_status setd_set_step(setd_plan* plan, int64_t step)
 
 setd_status setd_plan_destroy(setd_plan* plan)
 {
-    if (plan) {
-        for (auto& ev : plan->p.events) {
-            (void)hipEventDestroy(ev.a);
-            (void)hipEventDestroy(ev.b);
-        }
-    }
+    if (plan) plan->p.release();
     delete plan;
     return SETD_OK;
 }

@@ -35,6 +35,7 @@ struct Tune {
     int row = 0;   // 0..15 (0..3 for complex fields)
     int ax0 = 0;   // 0..5
     int ax1 = 0;   // 0..3
+    int split = 1; // 1, or 2: the halves of the realizations on two streams
 };
 
 struct Plan {
@@ -55,6 +56,10 @@ struct Plan {
     Layout lay;
     char* ws = nullptr;
     hipStream_t stream = nullptr;
+    // second stream and fork/join events for split steps (Tune::split)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool split_ok = true;         // whether bind may create the auxiliary stream
     bool bound = false;
     bool have_snap = false;
     // SETD2 storage: the carry Y_n = E phi_n + w_b F_{n-1} + G eta_n in the
@@ -70,6 +75,7 @@ struct Plan {
     double prof_ms[4] = {0, 0, 0, 0};
     double prof_cnt[4] = {0, 0, 0, 0};
 
+    ~Plan() { release(); }
     setd_status init(const setd_desc& desc);
     setd_status bind(void* dev, size_t bytes, hipStream_t s);
     // queue the passes of one step for nitems items starting at items_dev
@@ -79,6 +85,10 @@ struct Plan {
     setd_status profile_read(double* out, size_t cap, size_t* len);
     void pass_bytes(double* out4) const;
     setd_status step(int64_t n);
+    // n steps of every realization without per-pass events, split over two
+    // streams when `split` is 2
+    setd_status run_steps(int64_t n, int split);
+    void release();
     // time every variant of every pass on the bound buffers and keep the fastest
     setd_status autotune();
     setd_status observe(int kind, double* out, size_t cap, size_t* len);

@@ -362,6 +362,8 @@ setd_status setd_submit(setd_server* s, const setd_desc* desc, int64_t nsteps, s
     j->plan.reset(new (std::nothrow) Plan());
     if (!j->plan) return fail(SETD_E_NOMEM, "host allocation failed");
     setd_status st = j->plan->init(*desc);
+    // the scheduler batches jobs into its own launches on the server stream
+    j->plan->split_ok = false;
     if (st != SETD_OK) return st;
     j->d = *desc;
     j->nsteps = nsteps;

@@ -222,6 +222,30 @@ def test_lean_and_separate_storage_agree(prec):
         g.close()
 
 
+@pytest.mark.parametrize("p", [W.model_b([64, 64], precision=32, realizations=5),
+                               W.cgl([32, 32, 32], precision=64, realizations=3),
+                               W.kpz([64, 64], precision=32, realizations=2, ic_kind=1, ic_sigma=0.2)])
+def test_split_streams_match_one_stream(p, monkeypatch):
+    """Stepping the two halves of the realizations on two streams runs the same
+    kernels on the same data: bitwise the trajectory of one stream, and the
+    observables after it agree (to the rounding of their FP64 atomic sums,
+    whose order depends on block timing)."""
+    S = _setd()
+    monkeypatch.setenv("SETD_VARIANT", "1,4,1")
+    one = S.Plan(p)
+    monkeypatch.setenv("SETD_SPLIT", "2")
+    two = S.Plan(p)
+    assert int(one.info.streams) == 1 and int(two.info.streams) == 2
+    for _ in range(3):
+        one.step(7)
+        two.step(7)
+        for r in range(p["realizations"]):
+            assert np.array_equal(one.get(r), two.get(r))
+    assert np.allclose(one.observe(S.OBS_SK), two.observe(S.OBS_SK), rtol=1e-12, atol=0)
+    one.close()
+    two.close()
+
+
 def test_observables_match_oracle():
     S = _setd()
     for p in [W.model_a([64, 64], precision=64, realizations=3, order=2),
