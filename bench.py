@@ -33,6 +33,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_axis0_model_b_512.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_model_b_512.txt")
+# VALU issue peak: 256 CUs x 4 SIMDs, a wave64 FP32 instruction (packed FP32
+# off) occupies a 16-lane SIMD for 4 cycles, at 2.4 GHz: 614.4e9
+# wave-instructions/s (x 64 lanes x 2 flops = 78.6 TFLOP/s, half the packed
+# FP32 vector peak of 157.3)
+PEAK_VALU_WINST = 256 * 4 / 4 * 2.4e9
 KERNEL_SOURCES = ["setd_device.hpp", "setd_kernels.hpp", "setd_launch_impl.hpp", "setd_types.hpp"]
 
 
@@ -60,6 +66,29 @@ def measured_traffic(kernel):
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def measured_valu():
+    """VALU wave-instructions per launch of each pass kernel from the committed
+    rocprofv3 counter summary ({kernel label: count}), empty when it is missing
+    or the kernel sources changed since."""
+    if not os.path.exists(VALU_FILE):
+        return {}
+    vals = {}
+    for line in open(VALU_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.pop("source_hash", None) != kernel_source_hash():
+        return {}
+    out = {}
+    for k, v in vals.items():
+        if k.startswith("valu_insts_per_launch "):
+            try:
+                out[k.split(" ", 1)[1]] = float(v)
+            except ValueError:
+                pass
+    return out
 
 
 def time_plan(setd, p, steps, warmup, profile):
@@ -176,6 +205,23 @@ def other_workloads(setd, W, steps):
     return res
 
 
+def valu_roofline(names, avg_s, dom):
+    """The ALU view of each pass: VALU wave-instructions per launch (committed
+    counter summary) over the measured launch time, against PEAK_VALU_WINST.
+    Transcendental and 64-bit integer multiply instructions take four issue
+    slots, so this rate understates how busy the SIMDs are."""
+    counts = measured_valu()
+    passes = []
+    for i, nm in enumerate(names):
+        c = counts.get(nm)
+        rate = c / avg_s[i] if c else None
+        passes.append({"kernel": nm, "valu_insts_per_launch": c, "achieved": rate,
+                       "frac": rate / PEAK_VALU_WINST if rate else None})
+    return {"bound": "alu", "unit": "wave-instructions/s", "peak": PEAK_VALU_WINST,
+            "achieved": passes[dom]["achieved"], "frac": passes[dom]["frac"], "kernel": names[dom],
+            "passes": passes}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +281,7 @@ def main():
                     "gbs": float(info.pass_bytes[i] / (tot_ms[i] / cnt[i] * 1e-3) / 1e9)}
                    for i in range(len(tot_ms))],
         "timed_with_events_ms_per_step": 1e3 * t_prof / args.steps,
+        "valu": valu_roofline(pass_names, tot_ms / cnt * 1e-3, dom),
         "step_alg_bytes": float(info.alg_bytes_per_step),
         "step_frac": float(info.alg_bytes_per_step / (elapsed / args.steps) / 1e9 / PEAK_HBM_GBS),
     }
