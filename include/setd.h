@@ -14,7 +14,10 @@
  *    gives a text for the last failing call of the calling thread.
  *  - Device memory and HIP streams belong to the caller.  The library only
  *    borrows the workspace and stream handed to setd_plan_bind /
- *    setd_server_create and never frees them.
+ *    setd_server_create and never frees them.  Work it queues on streams of
+ *    its own (a plan's second stream, a server's class streams) is forked
+ *    from and joined back into the caller's stream with events, so ordering
+ *    against the caller's stream is as if all of it ran there.
  *  - Fields cross the boundary as host arrays of interleaved (re, im) doubles
  *    in FFT order: a real field as its real-to-complex half spectrum
  *    n[0] x .. x (n[d-1]/2 + 1), a complex field as the full n[0] x .. x n[d-1]
@@ -232,7 +235,9 @@ setd_status setd_plan_destroy(setd_plan* plan);
  * the caller's device arena dev_arena[0, bytes) by their workspace footprint,
  * keeps their fields resident, and advances all admitted jobs together:
  * realizations of jobs with the same lattice class share one launch per pass,
- * and newly admitted jobs join the next scheduler tick (continuous batching).
+ * the classes of a tick run side by side on up to four streams of the server
+ * (SETD_SERVER_LANES, default 4; 0 or 1 keeps everything on hip_stream), and
+ * newly admitted jobs join the next scheduler tick (continuous batching).
  * A job's trajectory does not depend on what else is running.
  */
 setd_status setd_server_create(void* dev_arena, size_t bytes, void* hip_stream, setd_server** out);

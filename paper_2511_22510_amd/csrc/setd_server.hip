@@ -117,6 +117,14 @@ struct setd_server {
     char* arena = nullptr;
     size_t arena_bytes = 0;
     hipStream_t stream = nullptr;
+    // launch classes of a tick are independent: each runs on one of these
+    // streams, forked from and joined back into `stream` with events, so that
+    // small lattices of different classes share the GPU
+    static constexpr int NLANE = 4;
+    int nlanes = 0;
+    hipStream_t lanes[NLANE] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_lane[NLANE] = {};
     Arena alloc;
     // device item tables, one region per launch class of a tick
     size_t items_off = 0, items_cap = 0;
@@ -252,12 +260,26 @@ setd_status setd_server::tick(std::vector<Job*>& act, int* steps_taken)
     Item* items_dev = reinterpret_cast<Item*>(arena + items_off);
     SETD_HIP(hipMemcpyAsync(items_dev, items_host, nitems * sizeof(Item), hipMemcpyHostToDevice, stream));
     const double t0 = now_s();
-    for (int sub = 0; sub < maxk; sub++) {
-        for (const Launch& L : launches) {
-            setd_status st = L.rep->launch_step(items_dev + L.first, L.n, sub, stream);
-            if (st != SETD_OK) return st;
+    const int nl = std::min<int>(nlanes, (int)launches.size());
+    if (nl >= 2) {
+        SETD_HIP(hipEventRecord(ev_fork, stream));
+        for (int i = 0; i < nl; i++) SETD_HIP(hipStreamWaitEvent(lanes[i], ev_fork, 0));
+    }
+    setd_status lst = SETD_OK;
+    for (int sub = 0; sub < maxk && lst == SETD_OK; sub++) {
+        for (size_t c = 0; c < launches.size() && lst == SETD_OK; c++) {
+            const Launch& L = launches[c];
+            lst = L.rep->launch_step(items_dev + L.first, L.n, sub, nl >= 2 ? lanes[c % nl] : stream);
         }
     }
+    if (nl >= 2) {
+        // join even after a failed launch
+        for (int i = 0; i < nl; i++) {
+            SETD_HIP(hipEventRecord(ev_lane[i], lanes[i]));
+            SETD_HIP(hipStreamWaitEvent(stream, ev_lane[i], 0));
+        }
+    }
+    if (lst != SETD_OK) return lst;
     SETD_HIP(hipStreamSynchronize(stream));
     const double dt = now_s() - t0;
     if (maxk > 0) {
@@ -348,6 +370,19 @@ setd_status setd_server_create(void* dev_arena, size_t bytes, void* hip_stream, 
     s->aging_s = env_double("SETD_SERVER_AGING", 1.0);
     s->tick_target_s = env_double("SETD_SERVER_TICK", 0.005);
     s->keep_budget = (size_t)env_double("SETD_SERVER_KEEP_BYTES", (double)((size_t)2 << 30));
+    // SETD_SERVER_LANES (0..4, default 4) streams for the launch classes of a tick
+    const int want = std::max(0, std::min(setd_server::NLANE, (int)env_double("SETD_SERVER_LANES", 4)));
+    if (want >= 2 && hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess) {
+        for (int i = 0; i < want; i++) {
+            if (hipStreamCreateWithFlags(&s->lanes[i], hipStreamNonBlocking) != hipSuccess) break;
+            if (hipEventCreateWithFlags(&s->ev_lane[i], hipEventDisableTiming) != hipSuccess) {
+                (void)hipStreamDestroy(s->lanes[i]);
+                s->lanes[i] = nullptr;
+                break;
+            }
+            s->nlanes = i + 1;
+        }
+    }
     s->worker = std::thread([s] { s->run(); });
     *out = s;
     return SETD_OK;
@@ -459,6 +494,12 @@ setd_status setd_server_destroy(setd_server* s)
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
     (void)hipStreamSynchronize(s->stream);
+    for (int i = 0; i < s->nlanes; i++) {
+        (void)hipStreamSynchronize(s->lanes[i]);
+        (void)hipStreamDestroy(s->lanes[i]);
+        (void)hipEventDestroy(s->ev_lane[i]);
+    }
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     if (s->items_host) (void)hipHostFree(s->items_host);
     delete s;
     return SETD_OK;
