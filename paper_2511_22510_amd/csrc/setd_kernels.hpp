@@ -215,6 +215,7 @@ struct AxisArgs {
     int per_item;  // blocks per realization
     int mode;      // axis-0 pass: MODE_STEP / MODE_IC / MODE_SYNC; axis-1 pass: +1 inverse, -1 forward
     int sub;
+    int ctab;      // register axis-0 kernel, keyed coefficients: stage them in LDS (the launch sized it)
 };
 
 struct LinArgs {
@@ -909,9 +910,50 @@ k_axis0r(AxisArgs a)
     fft_lines<T, N0, -1, PAD, 1>(v, t, L, TILE, 0, tw);
     const bool per_mode = it.coef_mode == COEF_PER_MODE;
     const uint32_t vcoef = ((uint32_t)t * g.pitch + colm) * CS;
+    // Keyed coefficients (3D): the block needs the entries of |a0| = 0..K0 for
+    // its TILE columns only, and a0 and -a0 share one.  Each is gathered once
+    // into LDS, which the transform leaves free until the inverse starts.
+    constexpr int NW = CC ? 2 : 1;   // T4 words per entry
+    T4<T>* const ctab = reinterpret_cast<T4<T>*>(smem_raw);
+    const bool staged = !KPZ && !per_mode && a.ctab;   // KPZ lattices are 2D
+    if (staged) {
+        __syncthreads();   // every lane has read its last transform values
+        const int nent = (kp0 + 1) * TILE;
+        for (int e = tid; e < nent; e += (int)blockDim.x) {
+            const int m = e / TILE, c = e - m * TILE;
+            const int col = tile * TILE + c;
+            int alc = col;
+            if (CC) alc = sgn_idx(fft_pos(col, g.n[last], keptl, g.kp[last]), g.n[last]);
+            const int key = (g.ndim == 3) ? coef_key(it, m, a1, alc) : coef_key(it, m, alc, 0);
+            const uint32_t vo = col < keptl ? (uint32_t)key * CS : BUF_OOB;
+#pragma unroll
+            for (int w = 0; w < NW; w++) ctab[e * NW + w] = bload4<T>(rcoef, vo, (uint32_t)w * 4u * sizeof(T));
+        }
+        __syncthreads();
+    }
     auto load_coef_q = [&](int q) {
         // lanes without a stored mode read nothing
         const bool st = cv && stored(q);
+        if (staged) {
+            const int a0 = sgn_idx(t + q * TPL, N0);
+            const int m = st ? (a0 < 0 ? -a0 : a0) : 0;
+            const T4<T>* ce = ctab + (m * TILE + c0) * NW;
+            Coef<T> c;
+            const T4<T> u = ce[0];
+            if constexpr (CC) {
+                const T4<T> w = ce[1];
+                c.E = {u.a, u.b};
+                c.wa = {u.c, u.d};
+                c.wb = {w.a, w.b};
+                c.G = w.c;
+            } else {
+                c.E = {u.a, T(0)};
+                c.wa = {u.b, T(0)};
+                c.wb = {u.c, T(0)};
+                c.G = u.d;
+            }
+            return c;
+        }
         uint32_t vo, so;
         if (per_mode) {
             // entry (row, column) of the table in the state layout

@@ -107,7 +107,7 @@ static hipError_t launch_axis_nt(const Geo& g, const Item* items, int nitems, in
                                  hipStream_t s)
 {
     constexpr int PAD = tile_pad<T, N, TILE>();
-    AxisArgs a;
+    AxisArgs a{};
     a.g = g;
     a.items = items;
     a.ntiles = g.pitch / TILE;
@@ -147,7 +147,7 @@ static hipError_t launch_axis0r(const Geo& g, const Item* items, int nitems, int
                                 bool lean, hipStream_t s)
 {
     constexpr int PAD = tile_pad<T, N, TILE>();
-    AxisArgs a;
+    AxisArgs a{};
     a.g = g;
     a.items = items;
     a.ntiles = g.pitch / TILE;
@@ -156,7 +156,12 @@ static hipError_t launch_axis0r(const Geo& g, const Item* items, int nitems, int
     a.sub = sub;
     dim3 grid(a.per_item * nitems);
     dim3 block(TILE * (N / 8));
-    const size_t lds = (size_t)TILE * lds_len<N, PAD>() * 2 * sizeof(T);
+    size_t lds = (size_t)TILE * lds_len<N, PAD>() * 2 * sizeof(T);
+    // 3D lattices key their coefficients by |a|: the block stages the entries
+    // of |a0| <= K0 for its columns in LDS when they fit in 64 KiB
+    const size_t tab = (size_t)(g.kp[0] + 1) * TILE * (g.cplx ? 8 : 4) * sizeof(T);
+    a.ctab = (g.ndim == 3 && tab <= 65536) ? 1 : 0;
+    if (a.ctab && tab > lds) lds = tab;
     if (lean) {
         if (g.cplx) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 2, true>), grid, block, lds, s, a);
         else if (kpz) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 1, true>), grid, block, lds, s, a);
