@@ -654,9 +654,11 @@ setd_status Plan::step(int64_t n)
     }
     for (int64_t i = 0; i < n; i++) {
         for (int k = 0; k < passes_per_step(); k++) {
+            // timing-only events: no system-scope fence (an L2 writeback)
+            // between the passes they bracket
             EvPair ev{k, nullptr, nullptr};
-            SETD_HIP(hipEventCreate(&ev.a));
-            SETD_HIP(hipEventCreate(&ev.b));
+            SETD_HIP(hipEventCreateWithFlags(&ev.a, hipEventDisableSystemFence));
+            SETD_HIP(hipEventCreateWithFlags(&ev.b, hipEventDisableSystemFence));
             events.push_back(ev);
             SETD_HIP(hipEventRecord(ev.a, stream));
             setd_status st = launch_pass(k, items_dev, R, 0, stream);
