@@ -147,6 +147,10 @@ typedef struct {
                                  realizations on the bound stream and an
                                  auxiliary one of the plan (joined again before
                                  setd_step returns), else 1                      */
+    int graph_steps;          /* setd_step runs whole chunks of this many steps
+                                 as one HIP graph captured at the first such
+                                 call (environment SETD_GRAPH at bind time;
+                                 default 0: kernel launches only)                */
 } setd_plan_info_t;
 
 typedef struct setd_plan setd_plan;

@@ -419,6 +419,10 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
         SETD_HIP(launch_fill64(reinterpret_cast<double*>(ws + lay.phi), (int64_t)((lay.total - lay.phi) / 8), 0.0, s));
         setd_status tst = autotune();
         if (tst != SETD_OK) return tst;
+        // SETD_GRAPH: steps per captured graph (default 0: kernel launches;
+        // replaying graphs measured slower than launching on this runtime)
+        const char* ge = std::getenv("SETD_GRAPH");
+        graph_chunk = ge ? std::max(0, std::min(1024, atoi(ge))) : 0;
         SETD_HIP(launch_ctrl_init(ctrl, R, 0, s));
     }
     SETD_HIP(launch_fill64(reinterpret_cast<double*>(ws + lay.skacc), 2 * nbins + 1, 0.0, s));
@@ -598,28 +602,51 @@ setd_status Plan::autotune()
 // from and joined back into the plan's stream with events, so that the passes
 // of one half overlap those of the other.  Each realization runs the same
 // kernels on the same data either way.
-setd_status Plan::run_steps(int64_t n, int split)
+setd_status Plan::run_steps_on(int64_t n, int split, hipStream_t s)
 {
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
     if (split != 2 || !aux || R < 2 || n <= 0) {
         for (int64_t i = 0; i < n; i++) {
-            setd_status st = launch_step(items_dev, R, 0, stream);
+            setd_status st = launch_step(items_dev, R, 0, s);
             if (st != SETD_OK) return st;
         }
         return SETD_OK;
     }
     const int h = R / 2;
-    SETD_HIP(hipEventRecord(ev_fork, stream));
+    SETD_HIP(hipEventRecord(ev_fork, s));
     SETD_HIP(hipStreamWaitEvent(aux, ev_fork, 0));
     setd_status st = SETD_OK;
     for (int64_t i = 0; i < n && st == SETD_OK; i++) {
-        st = launch_step(items_dev, h, 0, stream);
+        st = launch_step(items_dev, h, 0, s);
         if (st == SETD_OK) st = launch_step(items_dev + h, R - h, 0, aux);
     }
     // join even after a failed launch, so that nothing is left running on aux
     SETD_HIP(hipEventRecord(ev_join, aux));
-    SETD_HIP(hipStreamWaitEvent(stream, ev_join, 0));
+    SETD_HIP(hipStreamWaitEvent(s, ev_join, 0));
     return st;
+}
+
+// The launches of graph_chunk steps, captured once on the plan's capture
+// stream (the auxiliary stream joins the capture through the fork event) and
+// replayed on the bound stream.  Every kernel reads its realization's step
+// from device memory and the launch arguments do not change after binding, so
+// each replay advances the state exactly as eager launches would.  The steps
+// hold only kernel nodes.
+setd_status Plan::build_graph()
+{
+    if (!cap) SETD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    SETD_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+    const setd_status st = run_steps_on(graph_chunk, tune.split, cap);
+    hipGraph_t g0 = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &g0);
+    if (st != SETD_OK) {
+        if (g0) (void)hipGraphDestroy(g0);
+        return st;
+    }
+    if (e != hipSuccess) return fail(SETD_E_DEVICE, "stream capture failed: %s", hipGetErrorString(e));
+    graph = g0;
+    SETD_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    return SETD_OK;
 }
 
 void Plan::release()
@@ -637,6 +664,12 @@ void Plan::release()
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     ev_fork = ev_join = nullptr;
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    if (cap) (void)hipStreamDestroy(cap);
+    cap = nullptr;
 }
 
 setd_status Plan::step(int64_t n)
@@ -647,7 +680,15 @@ setd_status Plan::step(int64_t n)
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
     if (n > 0) phi_valid = !lean;
     if (!profiling) {
-        setd_status st = run_steps(n, tune.split);
+        int64_t left = n;
+        if (graph_chunk > 0 && left >= graph_chunk) {
+            if (!gexec) {
+                setd_status st = build_graph();
+                if (st != SETD_OK) return st;
+            }
+            for (; left >= graph_chunk; left -= graph_chunk) SETD_HIP(hipGraphLaunch(gexec, stream));
+        }
+        setd_status st = run_steps(left, tune.split);
         if (st != SETD_OK) return st;
         step_host += n;
         return SETD_OK;
@@ -961,6 +1002,7 @@ setd_status setd_plan_info(const setd_plan* plan, setd_plan_info_t* info)
     info->variants[1] = p.tune.ax0;
     info->variants[2] = p.tune.ax1;
     info->streams = (p.tune.split == 2 && p.aux) ? 2 : 1;
+    info->graph_steps = p.graph_chunk;
     setd::axis_shape(p.d.precision, p.g.n[0], p.tune.ax0, &info->axis_tile[0], &info->axis_tile[1]);
     return SETD_OK;
 }

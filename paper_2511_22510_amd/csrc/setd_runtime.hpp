@@ -60,6 +60,12 @@ struct Plan {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool split_ok = true;         // whether bind may create the auxiliary stream
+    // setd_step replays a captured graph of graph_chunk steps (0: eager
+    // launches only), captured on a stream of the plan at the first use
+    int graph_chunk = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     bool bound = false;
     bool have_snap = false;
     // SETD2 storage: the carry Y_n = E phi_n + w_b F_{n-1} + G eta_n in the
@@ -87,7 +93,9 @@ struct Plan {
     setd_status step(int64_t n);
     // n steps of every realization without per-pass events, split over two
     // streams when `split` is 2
-    setd_status run_steps(int64_t n, int split);
+    setd_status run_steps(int64_t n, int split) { return run_steps_on(n, split, stream); }
+    setd_status run_steps_on(int64_t n, int split, hipStream_t s);
+    setd_status build_graph();
     void release();
     // time every variant of every pass on the bound buffers and keep the fastest
     setd_status autotune();

@@ -53,7 +53,7 @@ class setd_plan_info_t(ctypes.Structure):
         ("kept_modes", ctypes.c_size_t), ("nbins", ctypes.c_int), ("passes_per_step", ctypes.c_int),
         ("alg_bytes_per_step", ctypes.c_double), ("site_updates_per_step", ctypes.c_double),
         ("pass_bytes", ctypes.c_double * 4), ("variants", ctypes.c_int * 3),
-        ("axis_tile", ctypes.c_int * 2), ("streams", ctypes.c_int),
+        ("axis_tile", ctypes.c_int * 2), ("streams", ctypes.c_int), ("graph_steps", ctypes.c_int),
     ]
 
 

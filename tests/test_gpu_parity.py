@@ -246,6 +246,31 @@ def test_split_streams_match_one_stream(p, monkeypatch):
     two.close()
 
 
+@pytest.mark.parametrize("split", ["1", "2"])
+@pytest.mark.parametrize("p", [W.model_b([64, 64], precision=32, realizations=5),
+                               W.cgl([32, 32, 32], precision=64, realizations=3)])
+def test_graph_replays_match_eager_launches(p, split, monkeypatch):
+    """setd_step replays a captured graph of 4 steps: every replay, with eager
+    steps, field reads and observables between replays, gives bitwise the
+    trajectory of kernel launches alone (one stream or two)."""
+    S = _setd()
+    monkeypatch.setenv("SETD_VARIANT", "1,4,1")
+    monkeypatch.setenv("SETD_SPLIT", split)
+    monkeypatch.setenv("SETD_GRAPH", "0")
+    eager = S.Plan(p)
+    monkeypatch.setenv("SETD_GRAPH", "4")
+    graph = S.Plan(p)
+    assert int(eager.info.graph_steps) == 0 and int(graph.info.graph_steps) == 4
+    for n in [8, 3, 4, 13, 1]:   # replays, eager remainders, both
+        eager.step(n)
+        graph.step(n)
+        for r in range(p["realizations"]):
+            assert np.array_equal(eager.get(r), graph.get(r)), (n, r)
+        assert np.allclose(eager.observe(S.OBS_SK), graph.observe(S.OBS_SK), rtol=1e-12, atol=0)
+    eager.close()
+    graph.close()
+
+
 def test_observables_match_oracle():
     S = _setd()
     for p in [W.model_a([64, 64], precision=64, realizations=3, order=2),

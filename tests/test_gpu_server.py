@@ -43,9 +43,14 @@ MIX = [
 ]
 
 
-def test_mix_equals_solo_and_oracle():
+@pytest.mark.parametrize("lanes", [4, 0])
+def test_mix_equals_solo_and_oracle(lanes, monkeypatch):
+    """Each served job equals the same job run alone, bitwise, and the oracle
+    within the bars; with the launch classes of a tick on four streams of the
+    server and with everything on one stream."""
+    monkeypatch.setenv("SETD_SERVER_LANES", str(lanes))
     S = _setd()
-    say("server mix of", len(MIX), "jobs")
+    say("server mix of", len(MIX), "jobs, lanes", lanes)
     srv = S.Server(256 << 20)
     ids = []
     for k, (p, n) in enumerate(MIX):
