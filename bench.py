@@ -77,7 +77,7 @@ def measured_valu():
     vals = {}
     for line in open(VALU_FILE):
         if "=" in line and not line.lstrip().startswith("#"):
-            k, v = line.split("=", 1)
+            k, v = line.rsplit("=", 1)   # kernel labels hold "=" themselves
             vals[k.strip()] = v.strip()
     if vals.pop("source_hash", None) != kernel_source_hash():
         return {}

@@ -1,0 +1,44 @@
+"""Host logic of bench.py: the committed counter summaries it reads are gated
+by the kernel source hash and keyed by kernel labels (which contain '=')."""
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def _write(path, text):
+    with open(path, "w") as f:
+        f.write(text)
+
+
+def test_valu_summary_is_read_by_label_and_gated_by_hash(tmp_path, monkeypatch):
+    f = tmp_path / "valu.txt"
+    monkeypatch.setattr(bench, "VALU_FILE", str(f))
+    h = bench.kernel_source_hash()
+    _write(f, "# a comment = with equals\nsource_hash = %s\n"
+              "valu_insts_per_launch k_axis0r<float,512,tile=8> = 1234\n"
+              "valu_insts_per_launch k_row_real<float,512,pad=3,block=64,pair_groups=1> = 99\n" % h)
+    got = bench.measured_valu()
+    assert got == {"k_axis0r<float,512,tile=8>": 1234.0,
+                   "k_row_real<float,512,pad=3,block=64,pair_groups=1>": 99.0}
+    _write(f, "source_hash = 0000000000000000\nvalu_insts_per_launch k_axis0r<float,512,tile=8> = 1234\n")
+    assert bench.measured_valu() == {}
+
+
+def test_traffic_summary_is_gated_by_kernel_and_hash(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.txt"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    h = bench.kernel_source_hash()
+    _write(f, "kernel = k_axis0r<float,512,tile=8>\nsource_hash = %s\nhbm_bytes_per_launch = 5.5e8\n" % h)
+    assert bench.measured_traffic("k_axis0r<float,512,tile=8>") == 5.5e8
+    assert bench.measured_traffic("k_axis0r<float,512,tile=16>") is None
+    _write(f, "kernel = k_axis0r<float,512,tile=8>\nsource_hash = x\nhbm_bytes_per_launch = 5.5e8\n")
+    assert bench.measured_traffic("k_axis0r<float,512,tile=8>") is None
+
+
+def test_valu_roofline_uses_the_issue_peak():
+    names = ["a", "b"]
+    r = bench.valu_roofline(names, [1e-5, 2e-5], 1)
+    assert r["bound"] == "alu" and r["peak"] == 256 * 2.4e9
+    assert r["kernel"] == "b"
