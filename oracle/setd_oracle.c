@@ -347,6 +347,7 @@ typedef struct {
     cplx* pref;                /* prefactor of the transformed nonlinearity */
     /* observables */
     cplx* snap; int64_t snap_step; int have_snap;
+    int64_t kick_step; int have_kick;   /* reference step of the response estimator */
     double* acc; double acc_count; int nbins;
     /* scratch */
     cplx* work; cplx* work2; double* rwork; double* rwork2; cplx* F;
@@ -845,6 +846,47 @@ int orc_observe(orc_sim* s, int kind, double* out, size_t cap, size_t* len)
         if (cap < 1) return -1;
         out[0] = (double)s->step;
         *len = 1;
+        return 0;
+    }
+    if (kind == 7) {
+        /* the noise of the next step, xi_a(n') = G_a eta_a(n'), is the kick */
+        s->kick_step = s->step; s->have_kick = 1;
+        if (cap >= 1) { out[0] = (double)s->step; *len = 1; } else *len = 0;
+        return 0;
+    }
+    if (kind == 8) {
+        /* Linear response by the noise correlation (the Onsager-Machlup
+           estimator of the susceptibility of App. C), in
+           discrete time: for the Gaussian kick xi_a(n') of the step taken from
+           n', Stein's lemma gives <phi_a(n) conj xi_a(n')> / G_a^2 = the mean
+           response of phi_a(n) to an additive kick in that step.  Per shell:
+           mean over realizations and modes with G_a > 0 of
+           phi_a(n) conj eta_a(n') / G_a, interior modes of a real field as 2 Re. */
+        if (!s->have_kick || cap < (size_t)3 * nb) return -1;
+        double* re = (double*)calloc((size_t)nb, sizeof(double));
+        double* im = (double*)calloc((size_t)nb, sizeof(double));
+        double* cnt = (double*)calloc((size_t)nb, sizeof(double));
+        for (size_t e = 0; e < s->nspec; e++) {
+            if (!s->mask[e] || !(s->G[e] > 0)) continue;
+            double w = mode_weight(s, e);
+            int b = shell_of(s, e);
+            cplx acc = 0;
+            for (int rr = 0; rr < s->R; rr++) {
+                cplx eta = noise_eta(s, e, s->kick_step, (uint32_t)(s->r_first + rr));
+                acc += s->phi[(size_t)rr * s->nspec + e] * conj(eta);
+            }
+            acc /= s->G[e] * s->R;
+            if (w == 2.0) { re[b] += 2.0 * creal(acc); }
+            else { re[b] += creal(acc); im[b] += cimag(acc); }
+            cnt[b] += w;
+        }
+        for (int b = 0; b < nb; b++) {
+            out[b] = cnt[b] > 0 ? re[b] / cnt[b] : 0;
+            out[nb + b] = cnt[b] > 0 ? im[b] / cnt[b] : 0;
+            out[2 * nb + b] = cnt[b];
+        }
+        *len = (size_t)3 * nb;
+        free(re); free(im); free(cnt);
         return 0;
     }
     return -1;
