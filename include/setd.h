@@ -78,8 +78,19 @@ typedef enum {
     SETD_OBS_STEP = 4,        /* out: [step index n, non-finite flag]               */
     SETD_OBS_SK_ACCUM = 5,    /* add the current shell S(k) to a running FP64 sum.
                                  out: [number of samples accumulated]               */
-    SETD_OBS_SK_MEAN = 6      /* time mean of the accumulated S(k).
+    SETD_OBS_SK_MEAN = 6,     /* time mean of the accumulated S(k).
                                  out: [mean_j (nbins), count_j (nbins)]             */
+    SETD_OBS_KICK = 7,        /* mark the noise of the next step, xi_a(n') =
+                                 G_a eta_a(n'), as the kick of the response
+                                 estimator.  out: [n']                              */
+    SETD_OBS_RESPONSE = 8     /* linear response by the noise correlation (App. C
+                                 susceptibility, Onsager-Machlup): per shell the
+                                 mean over realizations and modes with G_a > 0 of
+                                 phi_a(n) conj eta_a(n') / G_a, i.e. (Stein) the
+                                 mean response of phi_a(n) to an additive kick
+                                 in the step taken from n'; interior modes of a
+                                 real field as 2 Re.  Needs SETD_OBS_KICK first.
+                                 out: [Re (nbins), Im (nbins), count (nbins)]      */
 } setd_obs_kind;
 
 /*
@@ -198,7 +209,8 @@ setd_status setd_step(setd_plan* plan, int64_t nsteps);
  * Synchronises the stream.  Returns SETD_E_NONFINITE (after writing the
  * output) if any realization has produced a non-finite value.
  * Errors: SETD_E_INVAL (cap too small, unknown kind, SETD_OBS_TWOTIME before
- * a snapshot, shells on unequal n[i]), SETD_E_STATE, SETD_E_DEVICE.
+ * a snapshot, SETD_OBS_RESPONSE before a kick, shells on unequal n[i]),
+ * SETD_E_STATE, SETD_E_DEVICE.
  */
 setd_status setd_observe(setd_plan* plan, int kind, double* host_out, size_t cap, size_t* len);
 

@@ -1304,11 +1304,12 @@ struct ObsArgs {
     Geo g;
     const Item* items;
     int nitems;
-    int kind;       // RED_SK / RED_WIDTH / RED_TWOTIME
+    int kind;       // RED_SK / RED_WIDTH / RED_TWOTIME / RED_RESPONSE
     int nbins;
     int total;      // stored elements per realization
     double vol;     // prod L_i / N_i^2
     double* acc;    // [3 * nbins] sums (re, im, weight)
+    int64_t kick;   // RED_RESPONSE: the step whose noise is the kick
 };
 
 // Per stored mode: weight w = 2 for interior modes of a real field (a and -a),
@@ -1346,6 +1347,31 @@ __global__ void __launch_bounds__(256) k_observe(ObsArgs a)
             continue;
         }
         const int b = ceil_isqrt(a0 * a0 + a1 * a1 + al * al);
+        if (a.kind == RED_RESPONSE) {
+            // linear response by the noise correlation (App. C): phi_a(n)
+            // conj eta_a(n') / G_a with the step's own unit noise, regenerated
+            // in the state precision, and G_a of the coefficient table
+            const int ew = it.coef_cplx ? 8 : 4;   // table words per entry
+            const int entry = (it.coef_mode == COEF_PER_MODE) ? i0 * g.pitch + col
+                              : ((g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0));
+            const double G = (double)reinterpret_cast<const T*>(it.coef)[(size_t)entry * ew + (it.coef_cplx ? 6 : 3)];
+            if (!(G > 0.0)) continue;
+            const int j0 = fft_pos(i0, g.n[0], g.kept[0], g.kp[0]);
+            const int j1 = (g.ndim == 3) ? fft_pos(i1, g.n[1], g.kept[1], g.kp[1]) : 0;
+            const int jl = g.cplx ? fft_pos(col, g.n[last], g.kept[last], g.kp[last]) : col;
+            const cx<T> e = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)a.kick);
+            const double ex = (double)e.x, ey = (double)e.y;
+            const double re = (px * ex + py * ey) / G * invR;
+            const double im = (py * ex - px * ey) / G * invR;
+            if (w == 2.0) {
+                atomicAdd(&sb[b], 2.0 * re);
+            } else {
+                atomicAdd(&sb[b], re);
+                atomicAdd(&sb[nb + b], im);
+            }
+            if (blockIdx.y == 0) atomicAdd(&sb[2 * nb + b], w);
+            continue;
+        }
         if (a.kind == RED_SK) {
             atomicAdd(&sb[b], w * a.vol * (px * px + py * py) * invR);
         } else {

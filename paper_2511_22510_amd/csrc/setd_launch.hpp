@@ -42,7 +42,7 @@ hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, i
                          hipStream_t s);
 template <typename T>
 hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind, int nbins, double vol,
-                          double* acc, hipStream_t s);
+                          double* acc, int64_t kick, hipStream_t s);
 
 // (tile width, columns per thread) of axis-pass variant `var` for line length n
 void axis_shape(int precision, int n, int var, int* tile, int* lpt);

@@ -251,7 +251,7 @@ hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, i
 
 template <typename T>
 hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind, int nbins, double vol,
-                          double* acc, hipStream_t s)
+                          double* acc, int64_t kick, hipStream_t s)
 {
     ObsArgs a;
     a.g = g;
@@ -262,6 +262,7 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
     a.total = g.kept[0] * (g.ndim == 3 ? g.kept[1] : 1) * g.pitch;
     a.vol = vol;
     a.acc = acc;
+    a.kick = kick;
     int blocks = (a.total + 255) / 256;
     if (blocks > 128) blocks = 128;
     dim3 grid(blocks, nitems);
@@ -275,7 +276,7 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
     template hipError_t launch_axis0<T>(const Geo&, const Item*, int, int, int, int, int, int, hipStream_t);    \
     template hipError_t launch_axis1<T>(const Geo&, const Item*, int, int, int, int, hipStream_t);              \
     template hipError_t launch_linear<T>(const Geo&, const Item*, int, int, int, int64_t, hipStream_t);         \
-    template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, hipStream_t); \
+    template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, int64_t, hipStream_t); \
     template hipError_t launch_hermitian<T>(const Geo&, const Item*, int, int, hipStream_t);
 
 }  // namespace setd

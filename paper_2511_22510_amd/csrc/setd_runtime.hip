@@ -758,14 +758,14 @@ setd_status Plan::observe(int kind, double* out, size_t cap, size_t* len)
     double* dout = reinterpret_cast<double*>(ws + lay.out);
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
     size_t n_out = 0;
-    if (kind != SETD_OBS_STEP && kind != SETD_OBS_SK_MEAN) {
+    if (kind != SETD_OBS_STEP && kind != SETD_OBS_SK_MEAN && kind != SETD_OBS_KICK) {
         const setd_status st0 = ensure_phi();
         if (st0 != SETD_OK) return st0;
     }
     auto reduce = [&](int red) -> setd_status {
         SETD_HIP(launch_fill64(acc, 3 * nb, 0.0, stream));
-        if (d.precision == 32) SETD_HIP((launch_observe<float>(g, items_dev, R, red, nb, vol, acc, stream)));
-        else SETD_HIP((launch_observe<double>(g, items_dev, R, red, nb, vol, acc, stream)));
+        if (d.precision == 32) SETD_HIP((launch_observe<float>(g, items_dev, R, red, nb, vol, acc, kick_step, stream)));
+        else SETD_HIP((launch_observe<double>(g, items_dev, R, red, nb, vol, acc, kick_step, stream)));
         return SETD_OK;
     };
     setd_status st;
@@ -799,6 +799,28 @@ setd_status Plan::observe(int kind, double* out, size_t cap, size_t* len)
         SETD_HIP(launch_obs_final(3, nb, acc, dout, skacc, 0.0, stream));
         n_out = (size_t)3 * nb;
         break;
+    case SETD_OBS_RESPONSE:
+        if (!iso) return fail(SETD_E_INVAL, "shell averages need equal n[i]");
+        if (!have_kick) return fail(SETD_E_INVAL, "no kick marked");
+        if (cap < (size_t)3 * nb) return fail(SETD_E_INVAL, "output needs %d doubles", 3 * nb);
+        if ((st = reduce(RED_RESPONSE)) != SETD_OK) return st;
+        SETD_HIP(launch_obs_final(3, nb, acc, dout, skacc, 0.0, stream));
+        n_out = (size_t)3 * nb;
+        break;
+    case SETD_OBS_KICK: {
+        Ctrl c0;
+        SETD_HIP(hipMemcpyAsync(&c0, ws + lay.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+        SETD_HIP(hipStreamSynchronize(stream));
+        kick_step = c0.step;
+        have_kick = true;
+        if (cap >= 1) {
+            out[0] = (double)c0.step;
+            *len = 1;
+        } else {
+            *len = 0;
+        }
+        return SETD_OK;
+    }
     case SETD_OBS_SNAPSHOT: {
         SETD_HIP(launch_copy(ws + lay.snap, ws + lay.phi, (size_t)R * Sb, stream));
         have_snap = true;

@@ -68,6 +68,8 @@ struct Plan {
     hipGraphExec_t gexec = nullptr;
     bool bound = false;
     bool have_snap = false;
+    bool have_kick = false;       // SETD_OBS_KICK taken: the response's reference step
+    int64_t kick_step = 0;
     // SETD2 storage: the carry Y_n = E phi_n + w_b F_{n-1} + G eta_n in the
     // F_{n-1} array, phi recovered from pre when read (phi_valid tracks it)
     bool lean = false;

@@ -81,6 +81,6 @@ enum { MODE_STEP = 0, MODE_IC = 1, MODE_SYNC = 2, MODE_RECOVER = 3 };
 enum { LIN_STEP = 0, LIN_CARRY = 1, LIN_RENOISE = 2 };
 
 // observable reductions
-enum { RED_SK = 0, RED_WIDTH = 1, RED_TWOTIME = 2 };
+enum { RED_SK = 0, RED_WIDTH = 1, RED_TWOTIME = 2, RED_RESPONSE = 3 };
 
 }  // namespace setd

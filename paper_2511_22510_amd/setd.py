@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "SETD_OK", -1: "SETD_E_INVAL", -2: "SETD_E_NOMEM", -3: "SETD_
 
 NL = {"phi3": 0, "phi3_cons": 1, "kpz": 2, "cgl": 3, "none": 4}
 
-OBS_SK, OBS_WIDTH, OBS_SNAPSHOT, OBS_TWOTIME, OBS_STEP, OBS_SK_ACCUM, OBS_SK_MEAN = range(7)
+OBS_SK, OBS_WIDTH, OBS_SNAPSHOT, OBS_TWOTIME, OBS_STEP, OBS_SK_ACCUM, OBS_SK_MEAN, OBS_KICK, OBS_RESPONSE = range(9)
 
 
 class setd_desc(ctypes.Structure):

@@ -271,6 +271,36 @@ def test_graph_replays_match_eager_launches(p, split, monkeypatch):
     graph.close()
 
 
+@pytest.mark.parametrize("p", [W.model_a([64, 64], precision=64, realizations=3, order=2),
+                               W.model_b([64, 64], precision=32, realizations=4),
+                               W.kpz([64, 64], precision=32, realizations=2, ic_kind=1, ic_sigma=0.2),
+                               W.cgl([32, 32], precision=32, realizations=2),
+                               W.cgl([32, 32, 32], precision=64, realizations=2),
+                               W.model_a([16, 16, 16], precision=32, realizations=2, order=2)])
+def test_response_matches_oracle(p):
+    """Linear response by the noise correlation (App. C): the device regenerates
+    the kick's noise with the step's own generator and precision, divides by the
+    table's G, and reduces in FP64; the oracle does the same from its own parts."""
+    S = _setd()
+    g = S.Plan(p)
+    o = O.Sim(p)
+    g.step(5)
+    o.step(5)
+    assert g.observe(S.OBS_KICK)[0] == o.observe(O.OBS_KICK)[0] == 5
+    for m, then in ((0, 1), (1, 2), (3, 0)):   # steps since the kick, steps to the next look
+        a, b = g.observe(S.OBS_RESPONSE), o.observe(O.OBS_RESPONSE)
+        nb = g.nbins
+        assert np.array_equal(a[2 * nb:], b[2 * nb:])
+        tol = 1e-10 if p["precision"] == 64 else 2e-4
+        scale = max(1.0, float(np.max(np.abs(b[:2 * nb]))))
+        err = float(np.max(np.abs(a[:2 * nb] - b[:2 * nb]))) / scale
+        say("response", p["nl"], p["n"], "f%d" % p["precision"], "m", m, "err", err)
+        assert err <= tol
+        g.step(then)
+        o.step(then)
+    g.close()
+
+
 def test_observables_match_oracle():
     S = _setd()
     for p in [W.model_a([64, 64], precision=64, realizations=3, order=2),
