@@ -58,6 +58,7 @@ def lib():
                                         ctypes.c_uint32, ctypes.c_int, dp, dp]
         L.orc_noise_normals.restype = None
         L.orc_noise_slot.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint32), ip, ip]
+        L.orc_sde_run.argtypes = [ctypes.POINTER(_SdeDesc), dp, dp]
         L.orc_phi12.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         L.orc_phi12.restype = None
         L.orc_create_subset.argtypes = [ctypes.POINTER(_Desc), ctypes.c_int, ctypes.c_int]
@@ -146,6 +147,27 @@ def noise_normals(seed, P, n, r, half):
     z2 = ctypes.c_double()
     lib().orc_noise_normals(ctypes.c_uint64(seed), P, n, r, int(half), ctypes.byref(z1), ctypes.byref(z2))
     return z1.value, z2.value
+
+
+class _SdeDesc(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int), ("c", ctypes.c_double), ("f1", ctypes.c_double),
+                ("f3", ctypes.c_double), ("g0", ctypes.c_double), ("g1", ctypes.c_double),
+                ("h", ctypes.c_double), ("u0", ctypes.c_double), ("nsteps", ctypes.c_int64),
+                ("npaths", ctypes.c_int), ("seed", ctypes.c_uint64)]
+
+
+SDE_EM, SDE_MILSTEIN, SDE_SETD1 = 0, 1, 2
+
+
+def sde_run(scheme, c, h, nsteps, npaths, seed, u0=1.0, f1=0.0, f3=0.0, g0=0.0, g1=0.0):
+    """Scalar SETD schemes (Sec. 2) for du = (c u + f1 u + f3 u^3) dt +
+    (g0 + g1 u) dW: (u after nsteps, sum of the dW) per path."""
+    d = _SdeDesc(scheme, c, f1, f3, g0, g1, h, u0, nsteps, npaths, seed)
+    u = np.zeros(max(npaths, 1))
+    w = np.zeros(max(npaths, 1))
+    if lib().orc_sde_run(ctypes.byref(d), _dptr(u), _dptr(w)) != 0:
+        raise RuntimeError("oracle sde_run failed")
+    return u[:npaths], w[:npaths]
 
 
 def phi12(x):

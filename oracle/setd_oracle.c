@@ -891,3 +891,54 @@ int orc_observe(orc_sim* s, int kind, double* out, size_t cap, size_t* len)
     }
     return -1;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Scalar SDE schemes (Sec. 2, Eqs. SETD-EM, SETD-Milstein, SETD1)          */
+/* ------------------------------------------------------------------------ */
+/* du = [c u + F(u)] dt + G(u) dW with F(u) = f1 u + f3 u^3 and
+   G(u) = g0 + g1 u: the SAO of Sec. 3 (c = -Gamma, f3 = -Gamma b,
+   g0 = sqrt(2 Gamma T)) and GBM (c = lambda - delta, f1 = delta, g1 = mu).
+   With x = c h the factors of the schemes are e^x, (e^x - 1)/c = h phi1(x),
+   e^{x/2} and sqrt((e^{2x} - 1)/(2c)) = sqrt(h phi1(2x)).  Path p, step n
+   draws z = z1 of the Philox block (p, n, 0, 2) (two 53-bit uniforms,
+   Box-Muller); dW = sqrt(h) z, and SETD1 takes z as its N(0, 1).
+   u_out[p] = u after nsteps steps; w_out[p] (if not NULL) = sum of the dW. */
+typedef struct {
+    int scheme;           /* 0: SETD-EM, 1: SETD-Milstein, 2: SETD1 */
+    double c, f1, f3, g0, g1, h, u0;
+    int64_t nsteps;
+    int npaths;
+    uint64_t seed;
+} orc_sde_desc;
+
+int orc_sde_run(const orc_sde_desc* d, double* u_out, double* w_out)
+{
+    if (!d || d->scheme < 0 || d->scheme > 2 || !(d->h > 0) || d->nsteps < 0 || d->npaths < 0) return -1;
+    cplx p1, p2, q1, q2;
+    phi12(d->c * d->h, &p1, &p2);
+    phi12(2.0 * d->c * d->h, &q1, &q2);
+    const double E = exp(d->c * d->h);
+    const double fF = d->h * creal(p1);            /* (e^{ch} - 1)/c */
+    const double fmid = exp(0.5 * d->c * d->h);    /* e^{ch/2}       */
+    const double f4 = sqrt(d->h * creal(q1));      /* sqrt((e^{2ch} - 1)/(2c)) */
+    const double sh = sqrt(d->h);
+    for (int p = 0; p < d->npaths; p++) {
+        double u = d->u0, w = 0.0;
+        for (int64_t n = 0; n < d->nsteps; n++) {
+            double z1, z2;
+            orc_normal_pair(d->seed, (uint32_t)p, (uint32_t)n, 0u, 2u, &z1, &z2);
+            const double dW = sh * z1;
+            const double F = d->f1 * u + d->f3 * u * u * u;
+            const double G = d->g0 + d->g1 * u;
+            double noise;
+            if (d->scheme == 0) noise = fmid * G * dW;
+            else if (d->scheme == 1) noise = fmid * G * (dW + 0.5 * d->g1 * (dW * dW - d->h));
+            else noise = f4 * G * z1;
+            u = E * u + fF * F + noise;
+            w += dW;
+        }
+        u_out[p] = u;
+        if (w_out) w_out[p] = w;
+    }
+    return 0;
+}
