@@ -205,6 +205,27 @@ def other_workloads(setd, W, steps):
     return res
 
 
+def sde_rate(setd, npaths=1 << 20, nsteps=1000):
+    """Scalar SETD-Milstein (Sec. 2) on GBM (lambda 2, mu 1, delta 0, h 2^-10):
+    path-steps per second of the batched FP64 kernel, outputs in HBM."""
+    import ctypes
+    import torch
+    lib = setd.load()
+    u = torch.empty(npaths, dtype=torch.float64, device="cuda")
+    w = torch.empty(npaths, dtype=torch.float64, device="cuda")
+    d = setd.setd_sde_desc(setd.SDE_MILSTEIN, 2.0, 0.0, 0.0, 0.0, 1.0, 2.0 ** -10, 1.0, nsteps, npaths, 3)
+    stream = torch.cuda.current_stream().cuda_stream
+    st = lib.setd_sde_run(ctypes.byref(d), u.data_ptr(), w.data_ptr(), stream)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st |= lib.setd_sde_run(ctypes.byref(d), u.data_ptr(), w.data_ptr(), stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = st == 0 and bool(torch.isfinite(u).all())
+    return {"workload": "GBM SETD-Milstein FP64, %d paths x %d steps" % (npaths, nsteps),
+            "path_steps_per_s": npaths * nsteps / dt, "seconds": dt, "ok": ok}
+
+
 def valu_roofline(names, avg_s, dom):
     """The ALU view of each pass: VALU wave-instructions per launch (committed
     counter summary) over the measured launch time, against PEAK_VALU_WINST.
@@ -309,6 +330,7 @@ def main():
 
     if not args.no_other:
         line["other_workloads"] = other_workloads(setd, W, 50)
+        line["sde"] = sde_rate(setd)
 
     if args.serving_jobs > 0 and hasattr(setd, "Server"):
         line["serving"] = serving_run(setd, W, args.serving_jobs, seed=2024, audit=not args.no_cpu)

@@ -285,6 +285,36 @@ setd_status setd_job_times(setd_server* server, setd_job job, double* out4);
    dropped; the arena itself is the caller's). */
 setd_status setd_server_destroy(setd_server* server);
 
+/*
+ * Scalar SDEs (Sec. 2, Eqs. SETD-EM, SETD-Milstein and SETD1; the examples of
+ * Sec. 3): npaths independent paths of
+ *   du = [c u + F(u)] dt + G(u) dW,  F(u) = f1 u + f3 u^3,  G(u) = g0 + g1 u,
+ * in FP64 (the SAO: c = -Gamma, f3 = -Gamma b, g0 = sqrt(2 Gamma T); GBM:
+ * c = lambda - delta, f1 = delta, g1 = mu).  With x = c h the schemes use
+ * e^x, (e^x - 1)/c and either e^{x/2} G dW (SETD-EM),
+ * e^{x/2} G [dW + g1 (dW^2 - h)/2] (SETD-Milstein) or
+ * sqrt((e^{2x} - 1)/(2c)) G z (SETD1).  Step n of path p draws z, the first
+ * Box-Muller normal of the Philox4x32-10 block with counter (p, n, 0, 2) keyed
+ * by seed (two 53-bit uniforms), and dW = sqrt(h) z.
+ */
+typedef enum { SETD_SDE_EM = 0, SETD_SDE_MILSTEIN = 1, SETD_SDE_SETD1 = 2 } setd_sde_scheme;
+
+typedef struct {
+    int scheme;               /* setd_sde_scheme                                  */
+    double c, f1, f3, g0, g1; /* the SDE above                                    */
+    double h, u0;             /* step, initial value of every path                */
+    int64_t nsteps;           /* steps, < 2^32                                    */
+    int npaths;               /* paths (0: nothing to do)                         */
+    uint64_t seed;
+} setd_sde_desc;
+
+/* Queue nsteps steps of every path on hip_stream (asynchronous; NULL is the
+   default stream).  dev_u[p] receives u after nsteps steps from u0, dev_w[p]
+   (may be NULL) the sum of the path's dW: npaths doubles each, device memory
+   of the caller.  Errors: SETD_E_INVAL (unknown scheme, h <= 0, negative or
+   too large counts, null dev_u with npaths > 0), SETD_E_DEVICE. */
+setd_status setd_sde_run(const setd_sde_desc* desc, double* dev_u, double* dev_w, void* hip_stream);
+
 /* Seconds on the clock used by setd_job_times. */
 double setd_clock(void);
 

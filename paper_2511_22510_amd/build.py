@@ -14,7 +14,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libsetd.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["setd_k32.hip", "setd_k64.hip", "setd_kmisc.hip", "setd_runtime.hip", "setd_server.hip"]
+SOURCES = ["setd_k32.hip", "setd_k64.hip", "setd_kmisc.hip", "setd_runtime.hip", "setd_server.hip", "setd_sde.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

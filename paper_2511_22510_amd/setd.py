@@ -57,6 +57,17 @@ class setd_plan_info_t(ctypes.Structure):
     ]
 
 
+class setd_sde_desc(ctypes.Structure):
+    _fields_ = [
+        ("scheme", ctypes.c_int), ("c", ctypes.c_double), ("f1", ctypes.c_double), ("f3", ctypes.c_double),
+        ("g0", ctypes.c_double), ("g1", ctypes.c_double), ("h", ctypes.c_double), ("u0", ctypes.c_double),
+        ("nsteps", ctypes.c_int64), ("npaths", ctypes.c_int), ("seed", ctypes.c_uint64),
+    ]
+
+
+SDE_EM, SDE_MILSTEIN, SDE_SETD1 = 0, 1, 2
+
+
 class SetdError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
@@ -90,6 +101,7 @@ SIGNATURES = {
     "setd_job_get_field": (ctypes.c_int, [_P, _I64, ctypes.c_int, _D, _SZ]),
     "setd_job_times": (ctypes.c_int, [_P, _I64, _D]),
     "setd_server_destroy": (ctypes.c_int, [_P]),
+    "setd_sde_run": (ctypes.c_int, [ctypes.POINTER(setd_sde_desc), _P, _P, _P]),
     "setd_clock": (ctypes.c_double, []),
     "setd_last_error": (ctypes.c_char_p, []),
 }
@@ -434,3 +446,18 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def sde_run(scheme, c, h, nsteps, npaths, seed, u0=1.0, f1=0.0, f3=0.0, g0=0.0, g1=0.0, lib=None):
+    """Scalar SETD schemes (Sec. 2) on the GPU for du = (c u + f1 u + f3 u^3) dt
+    + (g0 + g1 u) dW: returns (u after nsteps, sum of the dW) per path as host
+    arrays; the paths run in device memory on torch's current stream."""
+    import torch
+    lib = lib or load()
+    u = torch.empty(max(npaths, 1), dtype=torch.float64, device="cuda")
+    w = torch.empty(max(npaths, 1), dtype=torch.float64, device="cuda")
+    d = setd_sde_desc(scheme, c, f1, f3, g0, g1, h, u0, nsteps, npaths, seed)
+    _check(lib, lib.setd_sde_run(ctypes.byref(d), u.data_ptr(), w.data_ptr(),
+                                 torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    return u[:npaths].cpu().numpy(), w[:npaths].cpu().numpy()

@@ -56,3 +56,23 @@ def test_descriptor_layout_matches_header():
     assert out[0] == ctypes.sizeof(setd.setd_desc)
     assert out[1:1 + len(fields)] == [getattr(setd.setd_desc, f).offset for f in fields]
     assert out[-1] == ctypes.sizeof(setd.setd_plan_info_t)
+
+
+def test_sde_descriptor_layout_matches_header():
+    import subprocess
+    import tempfile
+    from paper_2511_22510_amd import setd
+    fields = [f[0] for f in setd.setd_sde_desc._fields_]
+    src = '#include <stdio.h>\n#include <stddef.h>\n#include "setd.h"\nint main(void){\n'
+    src += 'printf("%zu\\n", sizeof(setd_sde_desc));\n'
+    for f in fields:
+        src += 'printf("%%zu\\n", offsetof(setd_sde_desc, %s));\n' % f
+    src += '}\n'
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = [int(v) for v in subprocess.check_output([exe]).split()]
+    assert out[0] == ctypes.sizeof(setd.setd_sde_desc)
+    assert out[1:] == [getattr(setd.setd_sde_desc, f).offset for f in fields]
