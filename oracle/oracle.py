@@ -59,6 +59,8 @@ def lib():
         L.orc_noise_normals.restype = None
         L.orc_noise_slot.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint32), ip, ip]
         L.orc_sde_run.argtypes = [ctypes.POINTER(_SdeDesc), dp, dp]
+        L.orc_series_start.argtypes = [vp, ctypes.c_int]
+        L.orc_spectrum.argtypes = [vp, dp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
         L.orc_phi12.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         L.orc_phi12.restype = None
         L.orc_create_subset.argtypes = [ctypes.POINTER(_Desc), ctypes.c_int, ctypes.c_int]
@@ -272,6 +274,22 @@ class Sim:
         kind = ctypes.c_int()
         lib().orc_noise_slot(self._h, int(e), ctypes.byref(P), ctypes.byref(half), ctypes.byref(kind))
         return P.value, half.value, kind.value
+
+    def series_start(self, M):
+        """Record phi_a(m), m = 0 (now) .. M - 1, over the next M - 1 steps."""
+        assert lib().orc_series_start(self._h, int(M)) == 0
+        self.series_len = int(M)
+
+    def spectrum(self):
+        """(C, Re chi, Im chi) as [nbins, M] arrays and the shell counts, from
+        the recorded series (App. C dynamic correlations and susceptibility)."""
+        nb, M = self.nbins, self.series_len
+        out = np.zeros(3 * nb * M + nb)
+        ln = ctypes.c_size_t(0)
+        if lib().orc_spectrum(self._h, _dptr(out), out.size, ctypes.byref(ln)) != 0:
+            raise RuntimeError("oracle spectrum failed")
+        return (out[:nb * M].reshape(nb, M), out[nb * M:2 * nb * M].reshape(nb, M),
+                out[2 * nb * M:3 * nb * M].reshape(nb, M), out[3 * nb * M:])
 
     def step_xi(self, xi):
         a = np.ascontiguousarray(xi, dtype=np.complex128).reshape((self.R,) + self.spec_shape)

@@ -348,6 +348,7 @@ typedef struct {
     /* observables */
     cplx* snap; int64_t snap_step; int have_snap;
     int64_t kick_step; int have_kick;   /* reference step of the response estimator */
+    cplx* series; int series_len, series_pos; int64_t series_step0;   /* recorded phi_a(m) */
     double* acc; double acc_count; int nbins;
     /* scratch */
     cplx* work; cplx* work2; double* rwork; double* rwork2; cplx* F;
@@ -534,7 +535,7 @@ void orc_destroy(orc_sim* s)
     free(s->phi); free(s->fprev); free(s->k2); free(s->kidx); free(s->mask);
     free(s->E); free(s->wa); free(s->wb); free(s->G); free(s->pref);
     free(s->work); free(s->work2); free(s->rwork); free(s->rwork2); free(s->F);
-    free(s->snap); free(s->acc); free(s->have_prev);
+    free(s->snap); free(s->acc); free(s->have_prev); free(s->series);
     free(s);
 }
 
@@ -678,9 +679,113 @@ static int step_once(orc_sim* s, const cplx* xi_all)
     return 0;
 }
 
+static int shell_of(const orc_sim* s, size_t e);
+static double mode_weight(const orc_sim* s, size_t e);
+
+static void series_record(orc_sim* s)
+{
+    if (!s->series || s->series_pos >= s->series_len) return;
+    memcpy(s->series + (size_t)s->series_pos * s->R * s->nspec, s->phi, sizeof(cplx) * (size_t)s->R * s->nspec);
+    s->series_pos++;
+}
+
 int orc_step(orc_sim* s, int64_t nsteps)
 {
-    for (int64_t i = 0; i < nsteps; i++) step_once(s, NULL);
+    for (int64_t i = 0; i < nsteps; i++) {
+        step_once(s, NULL);
+        series_record(s);
+    }
+    return 0;
+}
+
+/* Start a time series of M samples (App. C, dynamic correlations): phi_a(m)
+   for m = 0 (now) .. M - 1 (after M - 1 further steps). */
+int orc_series_start(orc_sim* s, int M)
+{
+    if (M < 2) return -1;
+    free(s->series);
+    s->series = (cplx*)malloc(sizeof(cplx) * (size_t)M * s->R * s->nspec);
+    if (!s->series) return -1;
+    s->series_len = M;
+    s->series_pos = 0;
+    s->series_step0 = s->step;
+    series_record(s);
+    return 0;
+}
+
+/* Time-frequency observables of App. C from the recorded series, with
+   phi_{a,b} = sum_m e^{2 pi i b m / M} phi_a(m) and the same transform xi_{a,b}
+   of the kicks xi_a(m) = G_a eta_a(n0 + m) of the steps taken from the samples:
+     C(k, w_b)   = (L/N^2)^d (T/M^2) <|phi_{a,b}|^2>,                T = M h,
+     chi(k, w_b) = (L/N^2)^d (T/M^2) (1/2D_a) <phi_{a,b} conj[xi_{a,b}/h]>,
+   the paper's estimators with the sum over the ensemble taken as its mean
+   and [d_t phi - K] over a step taken as the step's kick over h.  Means over
+   realizations and over the modes of each shell with G_a > 0 and D_a > 0; an
+   interior mode a of a real field also stands for -a, whose transforms at
+   w_b are the conjugates of a's at -w_b.  out: C [nbins][M], Re chi
+   [nbins][M], Im chi [nbins][M], mode count [nbins]. */
+int orc_spectrum(orc_sim* s, double* out, size_t cap, size_t* len)
+{
+    const orc_desc* d = &s->d;
+    const int nb = s->nbins, M = s->series_len;
+    if (!s->series || s->series_pos < M || cap < (size_t)3 * nb * M + nb) return -1;
+    double vol = 1.0;
+    for (int i = 0; i < d->ndim; i++) vol *= (d->n[i] * d->dx) / ((double)d->n[i] * (double)d->n[i]);
+    memset(out, 0, sizeof(double) * ((size_t)3 * nb * M + nb));
+    double* C = out;
+    double* Xr = out + (size_t)nb * M;
+    double* Xi = out + (size_t)2 * nb * M;
+    double* cnt = out + (size_t)3 * nb * M;
+    cplx* ph = (cplx*)malloc(sizeof(cplx) * M);
+    cplx* xi = (cplx*)malloc(sizeof(cplx) * M);
+    cplx* pbs = (cplx*)malloc(sizeof(cplx) * M);
+    cplx* xbs = (cplx*)malloc(sizeof(cplx) * M);
+    for (size_t e = 0; e < s->nspec; e++) {
+        if (!s->mask[e] || !(s->G[e] > 0)) continue;
+        const double Da = d->noise_D * (d->noise_kpow == 2 ? s->k2[e] : 1.0);
+        if (!(Da > 0)) continue;
+        const int j = shell_of(s, e);
+        const double w = mode_weight(s, e);
+        cnt[j] += w;
+        for (int rr = 0; rr < s->R; rr++) {
+            for (int m = 0; m < M; m++) {
+                ph[m] = s->series[((size_t)m * s->R + rr) * s->nspec + e];
+                xi[m] = s->G[e] * noise_eta(s, e, s->series_step0 + m, (uint32_t)(s->r_first + rr));
+            }
+            for (int b = 0; b < M; b++) {
+                cplx pb = 0, xb = 0;
+                for (int m = 0; m < M; m++) {
+                    const cplx z = cexp(I * 2.0 * M_PI * (double)(((int64_t)b * m) % M) / (double)M);
+                    pb += z * ph[m];
+                    xb += z * xi[m];
+                }
+                pbs[b] = pb;
+                xbs[b] = xb;
+            }
+            for (int b = 0; b < M; b++) {
+                const int nbq = (M - b) % M;   /* -b */
+                double c2 = creal(pbs[b]) * creal(pbs[b]) + cimag(pbs[b]) * cimag(pbs[b]);
+                cplx x = pbs[b] * conj(xbs[b]);
+                if (w == 2.0) {
+                    c2 += creal(pbs[nbq]) * creal(pbs[nbq]) + cimag(pbs[nbq]) * cimag(pbs[nbq]);
+                    x += conj(pbs[nbq] * conj(xbs[nbq]));
+                }
+                C[(size_t)j * M + b] += vol * d->h / M * c2 / s->R;
+                Xr[(size_t)j * M + b] += vol / (2.0 * Da * M) * creal(x) / s->R;
+                Xi[(size_t)j * M + b] += vol / (2.0 * Da * M) * cimag(x) / s->R;
+            }
+        }
+    }
+    for (int j = 0; j < nb; j++) {
+        if (cnt[j] <= 0) continue;
+        for (int b = 0; b < M; b++) {
+            C[(size_t)j * M + b] /= cnt[j];
+            Xr[(size_t)j * M + b] /= cnt[j];
+            Xi[(size_t)j * M + b] /= cnt[j];
+        }
+    }
+    free(ph); free(xi); free(pbs); free(xbs);
+    *len = (size_t)3 * nb * M + nb;
     return 0;
 }
 
