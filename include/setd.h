@@ -83,7 +83,7 @@ typedef enum {
     SETD_OBS_KICK = 7,        /* mark the noise of the next step, xi_a(n') =
                                  G_a eta_a(n'), as the kick of the response
                                  estimator.  out: [n']                              */
-    SETD_OBS_RESPONSE = 8     /* linear response by the noise correlation (App. C
+    SETD_OBS_RESPONSE = 8,    /* linear response by the noise correlation (App. C
                                  susceptibility, Onsager-Machlup): per shell the
                                  mean over realizations and modes with G_a > 0 of
                                  phi_a(n) conj eta_a(n') / G_a, i.e. (Stein) the
@@ -91,6 +91,24 @@ typedef enum {
                                  in the step taken from n'; interior modes of a
                                  real field as 2 Re.  Needs SETD_OBS_KICK first.
                                  out: [Re (nbins), Im (nbins), count (nbins)]      */
+    SETD_OBS_SERIES_START = 9,/* start a window of series_len samples: phi_a now
+                                 (m = 0) and after each of the next M - 1 steps.
+                                 out: [n0]                                         */
+    SETD_OBS_SPECTRUM = 10    /* App. C dynamic correlation and susceptibility
+                                 of the completed window, with
+                                 phi_{a,b} = sum_m e^{2 pi i b m/M} phi_a(m) and
+                                 xi_{a,b} the same of the kicks of the steps
+                                 taken from the samples (T = M h):
+                                   C(k, w_b)   = (L/N^2)^d (T/M^2) <|phi_{a,b}|^2>
+                                   chi(k, w_b) = (L/N^2)^d (T/M^2) (1/2D_a)
+                                                 <phi_{a,b} conj xi_{a,b}> / h,
+                                 means over realizations and over the modes of
+                                 each shell with G_a, D_a > 0 (an interior mode
+                                 of a real field stands for -a too; its
+                                 transforms at w_b are the conjugates of a's at
+                                 -w_b); b in FFT order, w_b = 2 pi b / T.
+                                 out: [C (nbins x M), Re chi (nbins x M),
+                                 Im chi (nbins x M), count (nbins)]              */
 } setd_obs_kind;
 
 /*
@@ -134,6 +152,10 @@ typedef struct {
                                  rule, SETD1 plans, and plans whose per-
                                  realization arrays reach 2 GiB always use the
                                  separate storage.                                 */
+    int series_len;           /* 0 (default), or M, a power of two in [8, 1024]:
+                                 the workspace holds a window of M samples of
+                                 the stored spectrum per realization for
+                                 SETD_OBS_SERIES_START / SETD_OBS_SPECTRUM      */
 } setd_desc;
 
 /* Derived sizes of a plan (filled by setd_plan_info). */
@@ -209,7 +231,8 @@ setd_status setd_step(setd_plan* plan, int64_t nsteps);
  * Synchronises the stream.  Returns SETD_E_NONFINITE (after writing the
  * output) if any realization has produced a non-finite value.
  * Errors: SETD_E_INVAL (cap too small, unknown kind, SETD_OBS_TWOTIME before
- * a snapshot, SETD_OBS_RESPONSE before a kick, shells on unequal n[i]),
+ * a snapshot, SETD_OBS_RESPONSE before a kick, SETD_OBS_SPECTRUM before a full
+ * window or without series_len, shells on unequal n[i]),
  * SETD_E_STATE, SETD_E_DEVICE.
  */
 setd_status setd_observe(setd_plan* plan, int kind, double* host_out, size_t cap, size_t* len);

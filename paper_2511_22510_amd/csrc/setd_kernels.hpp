@@ -1394,4 +1394,107 @@ __global__ void __launch_bounds__(256) k_observe(ObsArgs a)
         if (sb[i] != 0.0) atomicAdd(&a.acc[i], sb[i]);
 }
 
+// ---------------------------------------------------------------- time-frequency observables (App. C)
+
+// One line per (stored mode, realization): the window phi_a(m) and the kicks
+// xi_a(m) = G_a eta_a(n0 + m) of the steps taken from the samples go through
+// the unscaled transform with e^{+2 pi i b m / M} together; an interior mode
+// of a real field adds its mirror -a (the conjugate transforms at -w_b, read
+// back through LDS); FP64 sums per shell and frequency.
+template <typename T, int M, int PAD>
+__global__ void __launch_bounds__(256) k_spectrum(SpecArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    constexpr int TPL = M / 8;
+    constexpr int LL = lds_len<M, PAD>();
+    const int tid = threadIdx.x;
+    const int lpb = (int)blockDim.x / TPL;
+    const int l = tid / TPL, t = tid - l * TPL;
+    const int idx = blockIdx.x * lpb + l;     // stored element of the realization
+    const Item& it = a.items[blockIdx.y];
+    const Geo& g = a.g;
+    const int last = g.ndim - 1;
+    cx<T>* L = lds + l * 2 * LL;
+    // the mode of this line, its shell, weight, G and D(k); lanes of lines
+    // without a mode compute on zeros (they share the block's barriers)
+    bool use = idx < a.total;
+    int col = 0, i0 = 0, i1 = 0;
+    if (use) {
+        col = idx % g.pitch;
+        const int rest = idx / g.pitch;
+        i1 = (g.ndim == 3) ? rest % g.kept[1] : 0;
+        i0 = (g.ndim == 3) ? rest / g.kept[1] : rest;
+        use = col < g.kept[last];
+    }
+    const int j0 = fft_pos(i0, g.n[0], g.kept[0], g.kp[0]);
+    const int j1 = (g.ndim == 3) ? fft_pos(i1, g.n[1], g.kept[1], g.kp[1]) : 0;
+    const int jl = g.cplx ? fft_pos(col, g.n[last], g.kept[last], g.kp[last]) : col;
+    const int a0 = sgn_idx(j0, g.n[0]);
+    const int a1 = (g.ndim == 3) ? sgn_idx(j1, g.n[1]) : 0;
+    const int al = g.cplx ? sgn_idx(jl, g.n[last]) : col;
+    double G = 0.0, Da = 0.0;
+    if (use) {
+        const int ew = it.coef_cplx ? 8 : 4;
+        const int entry = (it.coef_mode == COEF_PER_MODE) ? i0 * g.pitch + col
+                          : ((g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0));
+        G = (double)reinterpret_cast<const T*>(it.coef)[(size_t)entry * ew + (it.coef_cplx ? 6 : 3)];
+        const double k0 = it.dk[0] * a0;
+        const double k1 = (g.ndim == 3) ? it.dk[1] * a1 : 0.0;
+        const double kl = it.dk[last] * al;
+        Da = a.D * (a.kpow == 2 ? k0 * k0 + k1 * k1 + kl * kl : 1.0);
+        use = G > 0.0 && Da > 0.0;
+    }
+    const double w = (!g.cplx && col > 0 && 2 * col < g.n[last]) ? 2.0 : 1.0;
+    const int shell = ceil_isqrt(a0 * a0 + a1 * a1 + al * al);
+
+    cx<T> v[2][8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const int m = t + q * TPL;
+        v[0][q] = czero<T>();
+        v[1][q] = czero<T>();
+        if (use) {
+            v[0][q] = *reinterpret_cast<const cx<T>*>(a.series + (size_t)m * a.slot + (size_t)blockIdx.y * a.rstride +
+                                                      (size_t)idx * sizeof(cx<T>));
+            const cx<T> e = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)(a.step0 + m));
+            v[1][q] = {(T)G * e.x, (T)G * e.y};
+        }
+    }
+    LineTw<T, M> tw;
+    line_tw_load(tw, t, reinterpret_cast<const cx<T>*>(a.tw));
+    fft_lines<T, M, +1, PAD, 2>(v, t, L, 1, LL, tw);
+    // the transforms at -w_b for the mirror of an interior real mode
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        L[lds_slot<PAD>(t + q * TPL)] = v[0][q];
+        L[LL + lds_slot<PAD>(t + q * TPL)] = v[1][q];
+    }
+    __syncthreads();
+    if (!use) return;   // no barrier follows
+    const int nb = a.nbins;
+    const double invR = 1.0 / (double)a.nitems;
+    const double cC = a.vol * a.h / M * invR, cX = a.vol / (2.0 * Da * M) * invR;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const int b = t + q * TPL;
+        const double px = v[0][q].x, py = v[0][q].y, xx = v[1][q].x, xy = v[1][q].y;
+        double c2 = px * px + py * py;
+        double xr = px * xx + py * xy, xi = py * xx - px * xy;   // phi conj(xi)
+        if (w == 2.0) {
+            const int bm = (M - b) & (M - 1);
+            const cx<T> pm = L[lds_slot<PAD>(bm)], km = L[LL + lds_slot<PAD>(bm)];
+            const double qx = pm.x, qy = pm.y, yx = km.x, yy = km.y;
+            c2 += qx * qx + qy * qy;
+            xr += qx * yx + qy * yy;         // conj(phi(-b) conj xi(-b))
+            xi -= qy * yx - qx * yy;
+        }
+        atomicAdd(&a.acc[(size_t)shell * M + b], cC * c2);
+        atomicAdd(&a.acc[((size_t)nb + shell) * M + b], cX * xr);
+        atomicAdd(&a.acc[((size_t)2 * nb + shell) * M + b], cX * xi);
+    }
+    if (blockIdx.y == 0 && t == 0) atomicAdd(&a.acc[(size_t)3 * nb * M + shell], w);
+}
+
 }  // namespace setd

@@ -43,6 +43,9 @@ hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, i
 template <typename T>
 hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind, int nbins, double vol,
                           double* acc, int64_t kick, hipStream_t s);
+// time-frequency observables of a recorded window (M a power of two in [8, 1024])
+template <typename T>
+hipError_t launch_spectrum(const SpecArgs& a, int M, hipStream_t s);
 
 // (tile width, columns per thread) of axis-pass variant `var` for line length n
 void axis_shape(int precision, int n, int var, int* tile, int* lpt);

@@ -249,6 +249,26 @@ hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, i
     return hipGetLastError();
 }
 
+template <typename T, int M>
+static hipError_t launch_spectrum_m(const SpecArgs& a0, hipStream_t s)
+{
+    SpecArgs a = a0;
+    constexpr int PAD = 3;
+    constexpr int tpl = M / 8;
+    const int lpb = tpl >= 256 ? 1 : 256 / tpl;
+    dim3 grid((a.total + lpb - 1) / lpb, a.nitems);
+    const size_t lds = (size_t)lpb * 2 * lds_len<M, PAD>() * 2 * sizeof(T);
+    hipLaunchKernelGGL((k_spectrum<T, M, PAD>), grid, dim3(lpb * tpl), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spectrum(const SpecArgs& a, int M, hipStream_t s)
+{
+    SETD_DISPATCH_N(M, return (launch_spectrum_m<T, NN>(a, s)));
+    return hipSuccess;
+}
+
 template <typename T>
 hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind, int nbins, double vol,
                           double* acc, int64_t kick, hipStream_t s)
@@ -277,6 +297,7 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
     template hipError_t launch_axis1<T>(const Geo&, const Item*, int, int, int, int, hipStream_t);              \
     template hipError_t launch_linear<T>(const Geo&, const Item*, int, int, int, int64_t, hipStream_t);         \
     template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, int64_t, hipStream_t); \
+    template hipError_t launch_spectrum<T>(const SpecArgs&, int, hipStream_t);                                    \
     template hipError_t launch_hermitian<T>(const Geo&, const Item*, int, int, hipStream_t);
 
 }  // namespace setd

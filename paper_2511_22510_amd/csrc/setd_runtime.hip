@@ -58,6 +58,8 @@ setd_status validate(const setd_desc& d)
     if (d.precision != 32 && d.precision != 64) return fail(SETD_E_INVAL, "precision must be 32 or 64");
     if (d.realizations < 1) return fail(SETD_E_INVAL, "realizations must be >= 1");
     if (d.dealias != 0 && d.dealias != 1) return fail(SETD_E_INVAL, "dealias must be 0 or 1");
+    if (d.series_len != 0 && !pow2_in(d.series_len, 8, 1024))
+        return fail(SETD_E_INVAL, "series_len must be 0 or a power of two in [8, 1024]");
     if (d.ic_kind != 0 && d.ic_kind != 1) return fail(SETD_E_INVAL, "ic_kind must be 0 or 1");
     if (d.complex_field != 0 && d.complex_field != 1) return fail(SETD_E_INVAL, "complex_field must be 0 or 1");
     const bool cimag = d.c0[1] != 0.0 || d.c2[1] != 0.0 || d.c4[1] != 0.0;
@@ -196,6 +198,11 @@ setd_status Plan::init(const setd_desc& desc)
         lay.tw64[i] = take((size_t)d.n[i] * 16);
         lay.tw32[i] = take((size_t)d.n[i] * 8);
     }
+    // tables sit below phi: binding clears everything from phi on
+    if (d.series_len > 0) {
+        lay.twm64 = take((size_t)d.series_len * 16);
+        lay.twm32 = take((size_t)d.series_len * 8);
+    }
     lay.acc = take((size_t)3 * nbins * 8);
     lay.skacc = take((size_t)(2 * nbins + 1) * 8);
     lay.out = take((size_t)3 * nbins * 8);
@@ -205,6 +212,10 @@ setd_status Plan::init(const setd_desc& desc)
     lay.pre1 = (d.nl == NL_KPZ) ? take((size_t)R * Pb) : 0;
     lay.big = B ? take((size_t)R * Bb) : 0;
     lay.snap = take((size_t)R * Sb);
+    if (d.series_len > 0) {
+        lay.specacc = take(((size_t)3 * nbins * d.series_len + nbins) * 8);
+        lay.series = take((size_t)d.series_len * R * Sb);
+    }
     lay.total = off;
     return SETD_OK;
 }
@@ -387,6 +398,9 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
     for (int i = 0; i < d.ndim; i++)
         SETD_HIP(launch_twiddle(d.n[i], reinterpret_cast<double*>(ws + lay.tw64[i]),
                                 reinterpret_cast<float*>(ws + lay.tw32[i]), s));
+    if (d.series_len > 0)
+        SETD_HIP(launch_twiddle(d.series_len, reinterpret_cast<double*>(ws + lay.twm64),
+                                reinterpret_cast<float*>(ws + lay.twm32), s));
     CoefArgs ca{};
     ca.nkeys = nkeys;
     ca.mode = coef_mode;
@@ -672,12 +686,33 @@ void Plan::release()
     cap = nullptr;
 }
 
+// Sample series_pos of the window: the stored spectrum of every realization
+// (recovered first when the plan keeps the SETD2 carry).
+setd_status Plan::series_sample()
+{
+    const setd_status st = ensure_phi();
+    if (st != SETD_OK) return st;
+    SETD_HIP(launch_copy(ws + lay.series + (size_t)series_pos * R * Sb, ws + lay.phi, (size_t)R * Sb, stream));
+    series_pos++;
+    return SETD_OK;
+}
+
 setd_status Plan::step(int64_t n)
 {
     if (!bound) return fail(SETD_E_STATE, "plan not bound");
     if (n < 0) return fail(SETD_E_INVAL, "negative step count");
     if (step_host + n >= (int64_t)1 << 32) return fail(SETD_E_INVAL, "step index would exceed 2^32");
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
+    if (n > 0) phi_valid = !lean;
+    // an open time-series window takes a sample after every step
+    while (n > 0 && series_pos >= 0 && series_pos < d.series_len) {
+        setd_status st = run_steps(1, profiling ? 1 : tune.split);
+        if (st != SETD_OK) return st;
+        phi_valid = !lean;
+        step_host += 1;
+        n -= 1;
+        if ((st = series_sample()) != SETD_OK) return st;
+    }
     if (n > 0) phi_valid = !lean;
     if (!profiling) {
         int64_t left = n;
@@ -807,6 +842,62 @@ setd_status Plan::observe(int kind, double* out, size_t cap, size_t* len)
         SETD_HIP(launch_obs_final(3, nb, acc, dout, skacc, 0.0, stream));
         n_out = (size_t)3 * nb;
         break;
+    case SETD_OBS_SERIES_START: {
+        if (d.series_len <= 0) return fail(SETD_E_INVAL, "the plan has no time series (series_len 0)");
+        Ctrl c0;
+        SETD_HIP(hipMemcpyAsync(&c0, ws + lay.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+        SETD_HIP(hipStreamSynchronize(stream));
+        series_step0 = c0.step;
+        series_pos = 0;
+        if ((st = series_sample()) != SETD_OK) return st;
+        if (cap >= 1) {
+            out[0] = (double)c0.step;
+            *len = 1;
+        } else {
+            *len = 0;
+        }
+        return SETD_OK;
+    }
+    case SETD_OBS_SPECTRUM: {
+        const int M = d.series_len;
+        if (!iso) return fail(SETD_E_INVAL, "shell averages need equal n[i]");
+        if (M <= 0 || series_pos < M) return fail(SETD_E_INVAL, "no complete time series window");
+        const size_t nsum = (size_t)3 * nb * M + nb;
+        if (cap < nsum) return fail(SETD_E_INVAL, "output needs %zu doubles", nsum);
+        double* sacc = reinterpret_cast<double*>(ws + lay.specacc);
+        SETD_HIP(launch_fill64(sacc, (int64_t)nsum, 0.0, stream));
+        SpecArgs sa{};
+        sa.g = g;
+        sa.items = items_dev;
+        sa.nitems = R;
+        sa.nbins = nb;
+        sa.total = (int)(S);
+        sa.series = ws + lay.series;
+        sa.slot = (size_t)R * Sb;
+        sa.rstride = Sb;
+        sa.tw = ws + ((d.precision == 32) ? lay.twm32 : lay.twm64);
+        sa.step0 = series_step0;
+        sa.vol = vol;
+        sa.h = d.h;
+        sa.D = d.noise_D;
+        sa.kpow = d.noise_kpow;
+        sa.acc = sacc;
+        if (d.precision == 32) SETD_HIP((launch_spectrum<float>(sa, M, stream)));
+        else SETD_HIP((launch_spectrum<double>(sa, M, stream)));
+        SETD_HIP(hipMemcpyAsync(out, sacc, nsum * sizeof(double), hipMemcpyDeviceToHost, stream));
+        SETD_HIP(hipStreamSynchronize(stream));
+        // sums to means over each shell's modes
+        for (int j = 0; j < nb; j++) {
+            const double c = out[(size_t)3 * nb * M + j];
+            if (!(c > 0)) continue;
+            for (int part = 0; part < 3; part++)
+                for (int b = 0; b < M; b++) out[((size_t)part * nb + j) * M + b] /= c;
+        }
+        *len = nsum;
+        int f = 0;
+        if ((st = nonfinite_any(&f)) != SETD_OK) return st;
+        return f ? fail(SETD_E_NONFINITE, "a realization produced a non-finite value") : SETD_OK;
+    }
     case SETD_OBS_KICK: {
         Ctrl c0;
         SETD_HIP(hipMemcpyAsync(&c0, ws + lay.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));

@@ -27,6 +27,7 @@ struct Layout {
     size_t tw64[3] = {0, 0, 0}, tw32[3] = {0, 0, 0};
     size_t acc = 0, skacc = 0, out = 0;
     size_t phi = 0, prev = 0, pre0 = 0, pre1 = 0, big = 0, snap = 0;
+    size_t twm64 = 0, twm32 = 0, specacc = 0, series = 0;   // time series (series_len > 0)
     size_t total = 0;
 };
 
@@ -70,6 +71,11 @@ struct Plan {
     bool have_snap = false;
     bool have_kick = false;       // SETD_OBS_KICK taken: the response's reference step
     int64_t kick_step = 0;
+    // time series window: samples taken so far (series_len when complete, -1
+    // before SETD_OBS_SERIES_START) and the step of sample 0
+    int series_pos = -1;
+    int64_t series_step0 = 0;
+    setd_status series_sample();
     // SETD2 storage: the carry Y_n = E phi_n + w_b F_{n-1} + G eta_n in the
     // F_{n-1} array, phi recovered from pre when read (phi_valid tracks it)
     bool lean = false;

@@ -1,6 +1,7 @@
 // setd_types.hpp -- plain structs shared by the host runtime and the kernels.
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 namespace setd {
@@ -79,6 +80,20 @@ enum { MODE_STEP = 0, MODE_IC = 1, MODE_SYNC = 2, MODE_RECOVER = 3 };
 // k_linear: a step of F = 0 in place; the SETD2 carry Y = E phi + G eta_n;
 // re-drawing the carry's noise for another step index
 enum { LIN_STEP = 0, LIN_CARRY = 1, LIN_RENOISE = 2 };
+
+// arguments of the time-frequency observables of a recorded window (App. C)
+struct SpecArgs {
+    Geo g;
+    const Item* items;
+    int nitems, nbins, total;     // total: stored elements per realization
+    const char* series;           // sample m of realization r at series + m * slot + r * rstride
+    size_t slot, rstride;
+    const void* tw;               // exp(-2 pi i k / M), state precision
+    int64_t step0;                // step of sample 0 (the kick of the step taken from it)
+    double vol, h, D;             // prod L_i / N_i^2, step, D of D(k) = D k^kpow
+    int kpow;
+    double* acc;                  // [3][nbins][M] sums, then [nbins] mode counts
+};
 
 // observable reductions
 enum { RED_SK = 0, RED_WIDTH = 1, RED_TWOTIME = 2, RED_RESPONSE = 3 };

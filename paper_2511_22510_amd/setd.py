@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "SETD_OK", -1: "SETD_E_INVAL", -2: "SETD_E_NOMEM", -3: "SETD_
 
 NL = {"phi3": 0, "phi3_cons": 1, "kpz": 2, "cgl": 3, "none": 4}
 
-OBS_SK, OBS_WIDTH, OBS_SNAPSHOT, OBS_TWOTIME, OBS_STEP, OBS_SK_ACCUM, OBS_SK_MEAN, OBS_KICK, OBS_RESPONSE = range(9)
+OBS_SK, OBS_WIDTH, OBS_SNAPSHOT, OBS_TWOTIME, OBS_STEP, OBS_SK_ACCUM, OBS_SK_MEAN, OBS_KICK, OBS_RESPONSE, \
+    OBS_SERIES_START, OBS_SPECTRUM = range(11)
 
 
 class setd_desc(ctypes.Structure):
@@ -43,7 +44,7 @@ class setd_desc(ctypes.Structure):
         ("h", ctypes.c_double), ("order", ctypes.c_int), ("precision", ctypes.c_int),
         ("realizations", ctypes.c_int), ("seed", ctypes.c_uint64), ("dealias", ctypes.c_int),
         ("ic_kind", ctypes.c_int), ("ic_sigma", ctypes.c_double),
-        ("history_readback", ctypes.c_int),
+        ("history_readback", ctypes.c_int), ("series_len", ctypes.c_int),
     ]
 
 
@@ -167,6 +168,7 @@ def make_desc(p):
     d.ic_kind = int(p.get("ic_kind", 0))
     d.ic_sigma = float(p.get("ic_sigma", 0.0))
     d.history_readback = int(p.get("history_readback", 0))
+    d.series_len = int(p.get("series_len", 0))
     return d
 
 
@@ -413,9 +415,18 @@ class Plan:
         setd_step(self.h, n, self.lib)
 
     def observe(self, kind, allow_nonfinite=False):
-        cap = 3 * self.nbins + 8
+        M = int(self.p.get("series_len", 0)) if isinstance(getattr(self, "p", None), dict) else 0
+        cap = 3 * self.nbins * max(M, 1) + self.nbins + 8
         out, _ = setd_observe(self.h, kind, cap, self.lib, allow_nonfinite)
         return out
+
+    def spectrum(self):
+        """(C, Re chi, Im chi) as [nbins, M] arrays and the shell counts of the
+        completed window (SETD_OBS_SPECTRUM)."""
+        nb, M = self.nbins, int(self.p["series_len"])
+        out = self.observe(OBS_SPECTRUM)
+        return (out[:nb * M].reshape(nb, M), out[nb * M:2 * nb * M].reshape(nb, M),
+                out[2 * nb * M:3 * nb * M].reshape(nb, M), out[3 * nb * M:3 * nb * M + nb])
 
     def status_observe(self, kind):
         cap = 3 * self.nbins + 8

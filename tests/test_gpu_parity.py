@@ -301,6 +301,42 @@ def test_response_matches_oracle(p):
     g.close()
 
 
+@pytest.mark.parametrize("p,M", [(W.model_a([32, 32], precision=64, realizations=3, order=2), 16),
+                                 (W.model_b([32, 32], precision=32, realizations=2), 32),
+                                 (W.kpz([32, 32], precision=32, realizations=2, ic_kind=1, ic_sigma=0.2), 16),
+                                 (W.cgl([16, 16, 16], precision=64, realizations=2), 8)])
+def test_spectrum_matches_oracle(p, M):
+    """App. C time-frequency observables of a window of M steps: the device
+    records the stored spectrum after every step, transforms each mode's
+    window and the regenerated kicks along time and reduces per shell and
+    frequency in FP64; the oracle transforms by direct sums."""
+    S = _setd()
+    g = S.Plan(dict(p, series_len=M))
+    o = O.Sim(p)
+    g.step(5)
+    o.step(5)
+    assert g.observe(S.OBS_SERIES_START)[0] == 5
+    o.series_start(M)
+    g.step(M - 2)
+    o.step(M - 2)
+    with pytest.raises(S.SetdError):
+        g.spectrum()   # one sample short
+    g.step(1)
+    o.step(1)
+    a, b = g.spectrum(), o.spectrum()
+    assert np.array_equal(a[3], b[3])
+    tol = 1e-10 if p["precision"] == 64 else 2e-4
+    for x, y, name in zip(a[:3], b[:3], ["C", "Re chi", "Im chi"]):
+        err = float(np.max(np.abs(x - y))) / max(float(np.max(np.abs(y))), 1e-300)
+        say("spectrum", p["nl"], p["n"], "f%d" % p["precision"], name, "err", err)
+        assert err <= tol
+    # the window leaves the trajectory alone
+    g.step(2)
+    o.step(2)
+    assert relerr(g.get(0), o.get(0)) <= (1e-10 if p["precision"] == 64 else 2e-4)
+    g.close()
+
+
 def test_observables_match_oracle():
     S = _setd()
     for p in [W.model_a([64, 64], precision=64, realizations=3, order=2),
