@@ -19,7 +19,8 @@ from . import build as _build
 
 NL_CODES = {"phi3": 0, "phi3_cons": 1, "kpz": 2, "cgl": 3, "none": 4}
 
-OBS_SK, OBS_WIDTH, OBS_SNAPSHOT, OBS_TWOTIME, OBS_STEP, OBS_SK_ACCUM, OBS_SK_MEAN, OBS_KICK, OBS_RESPONSE = range(9)
+OBS_SK, OBS_WIDTH, OBS_SNAPSHOT, OBS_TWOTIME, OBS_STEP, OBS_SK_ACCUM, OBS_SK_MEAN, OBS_KICK, OBS_RESPONSE, \
+    OBS_SERIES_START, OBS_SPECTRUM, OBS_BOXWIDTH = range(12)
 
 
 class _Desc(ctypes.Structure):

@@ -953,6 +953,56 @@ int orc_observe(orc_sim* s, int kind, double* out, size_t cap, size_t* len)
         *len = 1;
         return 0;
     }
+    if (kind == 11) {
+        /* box-averaged width (Sec. 5 KPZ): w_l = sqrt of the mean over boxes of
+           l^d sites and realizations of [mean_box h^2 - (mean_box h)^2]
+           (a complex field: mean_box |A|^2 - |mean_box A|^2), from the
+           real-space field, for l = 2, 4, .., N (equal n[i]) */
+        int nl = 0;
+        for (int l = 2; l <= d->n[0]; l *= 2) nl++;
+        if (cap < (size_t)nl) return -1;
+        for (int i = 1; i < d->ndim; i++) if (d->n[i] != d->n[0]) return -1;
+        const int N = d->n[0], nd = d->ndim;
+        double* acc = (double*)calloc((size_t)nl, sizeof(double));
+        cplx* x = (cplx*)malloc(sizeof(cplx) * s->nreal);
+        for (int rr = 0; rr < s->R; rr++) {
+            cplx* src = s->phi + (size_t)rr * s->nspec;
+            if (d->complex_field) {
+                memcpy(x, src, sizeof(cplx) * s->nreal);
+                fftn(x, nd, d->n, +1);                 /* scaled by 1/N^d */
+            } else {
+                irfftn(src, s->rwork, nd, d->n, s->work);
+                for (size_t i = 0; i < s->nreal; i++) x[i] = s->rwork[i];
+            }
+            int li = 0;
+            for (int l = 2; l <= N; l *= 2, li++) {
+                const int P = N / l;
+                const size_t nbox = (size_t)P * P * (nd == 3 ? P : 1);
+                cplx* s1 = (cplx*)calloc(nbox, sizeof(cplx));
+                double* s2 = (double*)calloc(nbox, sizeof(double));
+                for (size_t i = 0; i < s->nreal; i++) {
+                    size_t rem = i, box = 0;
+                    int c[3] = { 0, 0, 0 };
+                    for (int dd = nd - 1; dd >= 0; dd--) { c[dd] = (int)(rem % (size_t)N); rem /= (size_t)N; }
+                    for (int dd = 0; dd < nd; dd++) box = box * (size_t)P + (size_t)(c[dd] / l);
+                    s1[box] += x[i];
+                    s2[box] += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+                }
+                const double per = pow((double)l, nd);
+                double v = 0;
+                for (size_t b = 0; b < nbox; b++) {
+                    const cplx m = s1[b] / per;
+                    v += s2[b] / per - (creal(m) * creal(m) + cimag(m) * cimag(m));
+                }
+                acc[li] += v / (double)nbox;
+                free(s1); free(s2);
+            }
+        }
+        for (int i = 0; i < nl; i++) out[i] = sqrt(acc[i] / s->R);
+        *len = (size_t)nl;
+        free(acc); free(x);
+        return 0;
+    }
     if (kind == 7) {
         /* the noise of the next step, xi_a(n') = G_a eta_a(n'), is the kick */
         s->kick_step = s->step; s->have_kick = 1;
