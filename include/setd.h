@@ -94,7 +94,7 @@ typedef enum {
     SETD_OBS_SERIES_START = 9,/* start a window of series_len samples: phi_a now
                                  (m = 0) and after each of the next M - 1 steps.
                                  out: [n0]                                         */
-    SETD_OBS_SPECTRUM = 10    /* App. C dynamic correlation and susceptibility
+    SETD_OBS_SPECTRUM = 10,   /* App. C dynamic correlation and susceptibility
                                  of the completed window, with
                                  phi_{a,b} = sum_m e^{2 pi i b m/M} phi_a(m) and
                                  xi_{a,b} the same of the kicks of the steps
@@ -109,6 +109,13 @@ typedef enum {
                                  -w_b); b in FFT order, w_b = 2 pi b / T.
                                  out: [C (nbins x M), Re chi (nbins x M),
                                  Im chi (nbins x M), count (nbins)]              */
+    SETD_OBS_BOXWIDTH = 11    /* box-averaged width (Sec. 5 KPZ): for l = 2, 4, ..,
+                                 N (equal n[i] = N) the sqrt of the ensemble mean,
+                                 over the N^d/l^d boxes of l^d sites, of the
+                                 variance of the field within the box (complex
+                                 field: of |phi - box mean|^2).  Computed from the
+                                 spectrum without a transform.
+                                 out: [w_2, w_4, .., w_N] (log2 N values)        */
 } setd_obs_kind;
 
 /*

@@ -1394,6 +1394,134 @@ __global__ void __launch_bounds__(256) k_observe(ObsArgs a)
         if (sb[i] != 0.0) atomicAdd(&a.acc[i], sb[i]);
 }
 
+// ---------------------------------------------------------------- box-averaged width (Sec. 5 KPZ)
+// With h(x) = N^-d sum_a h_a e^{2 pi i a.x/N}, the mean over boxes of l^d
+// sites of |box mean|^2 is N^-2d sum_c |A_c|^2 with A_c = sum_{a = c mod N/l}
+// h_a D_l(a), D_l(a) = prod_i (1/l) sum_{u < l} e^{2 pi i a_i u/N}, and the
+// mean of |h|^2 is N^-2d sum_a |h_a|^2 (Parseval): the box variance needs no
+// transform.  D_l vanishes on the multiples of N/l other than 0, so the mode
+// a = 0 is alone in its class and cancels; it is left out of both sums.  Per
+// stored mode of one realization the kernel adds to the class sums of every
+// level l = 2^j (an interior mode of a real field adds its mirror -a to the
+// class of -a with the conjugate value).  The coarse levels, whose few
+// classes every mode reaches, are summed in LDS first.
+__device__ __forceinline__ double2 box_dirichlet(int a, int l, int N)
+{
+    const int am = ((a % N) + N) % N;
+    if (am == 0) return make_double2(1.0, 0.0);
+    if ((am * l) % N == 0) return make_double2(0.0, 0.0);
+    const double num = sinpi((double)am * l / N), den = sinpi((double)am / N);
+    double s, c;
+    sincospi((double)am * (l - 1) / N, &s, &c);
+    const double m = num / (l * den);
+    return make_double2(m * c, m * s);
+}
+
+constexpr int BOX_LDS = 1024;   // complex class sums held in LDS per block
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_boxclass(BoxArgs a)
+{
+    __shared__ double lcls[2 * BOX_LDS];
+    __shared__ double red[256];
+    for (int i = threadIdx.x; i < 2 * a.nlds; i += blockDim.x) lcls[i] = 0.0;
+    __syncthreads();
+    const Geo& g = a.g;
+    const Item& it = a.items[a.r];
+    const int last = g.ndim - 1;
+    const cx<T>* phi = reinterpret_cast<const cx<T>*>(it.phi);
+    double s2 = 0.0;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < a.total; idx += gridDim.x * blockDim.x) {
+        const int col = idx % g.pitch;
+        if (col >= g.kept[last]) continue;
+        const int rest = idx / g.pitch;
+        const int i1 = (g.ndim == 3) ? rest % g.kept[1] : 0;
+        const int i0 = (g.ndim == 3) ? rest / g.kept[1] : rest;
+        int ai[3] = {sgn_idx(fft_pos(i0, g.n[0], g.kept[0], g.kp[0]), g.n[0]), 0, 0};
+        if (g.ndim == 3) ai[1] = sgn_idx(fft_pos(i1, g.n[1], g.kept[1], g.kp[1]), g.n[1]);
+        ai[last] = g.cplx ? sgn_idx(fft_pos(col, g.n[last], g.kept[last], g.kp[last]), g.n[last]) : col;
+        if (ai[0] == 0 && ai[1] == 0 && ai[last] == 0) continue;
+        const bool mirror = !g.cplx && col > 0 && 2 * col < g.n[last];
+        const cx<T> p = phi[idx];
+        const double hx = (double)p.x, hy = (double)p.y;
+        s2 += (mirror ? 2.0 : 1.0) * (hx * hx + hy * hy);
+        size_t off = 0;
+        for (int j = 1; j <= a.J; j++) {
+            const int l = 1 << j, P = a.N >> j;
+            size_t cls_size = 1;
+            for (int d = 0; d < g.ndim; d++) cls_size *= (size_t)P;
+            double2 D = make_double2(1.0, 0.0);
+            bool zero = false;
+            for (int d = 0; d < g.ndim; d++) {
+                const double2 e = box_dirichlet(ai[d], l, a.N);
+                if (e.x == 0.0 && e.y == 0.0) zero = true;
+                D = make_double2(D.x * e.x - D.y * e.y, D.x * e.y + D.y * e.x);
+            }
+            if (!zero) {
+                const double vx = hx * D.x - hy * D.y, vy = hx * D.y + hy * D.x;
+                size_t c = 0, cm = 0;
+                for (int d = 0; d < g.ndim; d++) {
+                    c = c * P + (size_t)(((ai[d] % P) + P) % P);
+                    cm = cm * P + (size_t)(((-ai[d] % P) + P) % P);
+                }
+                c += off;
+                cm += off;
+                if (c >= a.lds_base) {
+                    atomicAdd(&lcls[2 * (c - a.lds_base)], vx);
+                    atomicAdd(&lcls[2 * (c - a.lds_base) + 1], vy);
+                } else {
+                    atomicAdd(&a.cls[2 * c], vx);
+                    atomicAdd(&a.cls[2 * c + 1], vy);
+                }
+                if (mirror) {
+                    if (cm >= a.lds_base) {
+                        atomicAdd(&lcls[2 * (cm - a.lds_base)], vx);
+                        atomicAdd(&lcls[2 * (cm - a.lds_base) + 1], -vy);
+                    } else {
+                        atomicAdd(&a.cls[2 * cm], vx);
+                        atomicAdd(&a.cls[2 * cm + 1], -vy);
+                    }
+                }
+            }
+            off += cls_size;
+        }
+    }
+    red[threadIdx.x] = s2;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&a.sums[0], red[0]);
+    for (int i = threadIdx.x; i < 2 * a.nlds; i += blockDim.x)
+        if (lcls[i] != 0.0) atomicAdd(&a.cls[2 * a.lds_base + i], lcls[i]);
+}
+
+// sum_c |A_c|^2 per level, one atomic per block and level
+static __global__ void __launch_bounds__(256) k_boxfinal(BoxArgs a, size_t ncls)
+{
+    __shared__ double red[16];
+    for (int j = threadIdx.x; j < 16; j += blockDim.x) red[j] = 0.0;
+    __syncthreads();
+    const int nd = a.g.ndim;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncls; c += (size_t)gridDim.x * blockDim.x) {
+        size_t off = 0;
+        int j = 1;
+        for (; j < a.J; j++) {
+            size_t sz = 1;
+            for (int d = 0; d < nd; d++) sz *= (size_t)(a.N >> j);
+            if (c < off + sz) break;
+            off += sz;
+        }
+        const double x = a.cls[2 * c], y = a.cls[2 * c + 1];
+        const double v = x * x + y * y;
+        if (v != 0.0) atomicAdd(&red[j], v);
+    }
+    __syncthreads();
+    for (int j = 1 + (int)threadIdx.x; j <= a.J; j += blockDim.x)
+        if (red[j] != 0.0) atomicAdd(&a.sums[j], red[j]);
+}
+
 // ---------------------------------------------------------------- time-frequency observables (App. C)
 
 // One line per (stored mode, realization): the window phi_a(m) and the kicks

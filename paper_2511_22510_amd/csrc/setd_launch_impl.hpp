@@ -249,6 +249,20 @@ hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, i
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_boxwidth(const BoxArgs& a, size_t ncls, hipStream_t s)
+{
+    int blocks = (a.total + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL((k_boxclass<T>), dim3(blocks), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t fb = (ncls + 255) / 256;
+    if (fb > 1024) fb = 1024;
+    hipLaunchKernelGGL(k_boxfinal, dim3((unsigned)fb), dim3(256), 0, s, a, ncls);
+    return hipGetLastError();
+}
+
 template <typename T, int M>
 static hipError_t launch_spectrum_m(const SpecArgs& a0, hipStream_t s)
 {
@@ -298,6 +312,7 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
     template hipError_t launch_linear<T>(const Geo&, const Item*, int, int, int, int64_t, hipStream_t);         \
     template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, int64_t, hipStream_t); \
     template hipError_t launch_spectrum<T>(const SpecArgs&, int, hipStream_t);                                    \
+    template hipError_t launch_boxwidth<T>(const BoxArgs&, size_t, hipStream_t);                                  \
     template hipError_t launch_hermitian<T>(const Geo&, const Item*, int, int, hipStream_t);
 
 }  // namespace setd

@@ -212,6 +212,15 @@ setd_status Plan::init(const setd_desc& desc)
     lay.pre1 = (d.nl == NL_KPZ) ? take((size_t)R * Pb) : 0;
     lay.big = B ? take((size_t)R * Bb) : 0;
     lay.snap = take((size_t)R * Sb);
+    if (iso) {
+        lay.boxn = 0;
+        for (int l = 2; l <= d.n[0]; l *= 2) {
+            size_t c = 1;
+            for (int i = 0; i < d.ndim; i++) c *= (size_t)(d.n[0] / l);
+            lay.boxn += c;
+        }
+        lay.boxcls = take(lay.boxn * 16);
+    }
     if (d.series_len > 0) {
         lay.specacc = take(((size_t)3 * nbins * d.series_len + nbins) * 8);
         lay.series = take((size_t)d.series_len * R * Sb);
@@ -894,6 +903,51 @@ setd_status Plan::observe(int kind, double* out, size_t cap, size_t* len)
                 for (int b = 0; b < M; b++) out[((size_t)part * nb + j) * M + b] /= c;
         }
         *len = nsum;
+        int f = 0;
+        if ((st = nonfinite_any(&f)) != SETD_OK) return st;
+        return f ? fail(SETD_E_NONFINITE, "a realization produced a non-finite value") : SETD_OK;
+    }
+    case SETD_OBS_BOXWIDTH: {
+        if (!iso) return fail(SETD_E_INVAL, "box widths need equal n[i]");
+        const int N = d.n[0];
+        int J = 0;
+        while ((1 << J) < N) J++;
+        if (cap < (size_t)J) return fail(SETD_E_INVAL, "output needs %d doubles", J);
+        BoxArgs ba{};
+        ba.g = g;
+        ba.items = items_dev;
+        ba.total = (int)S;
+        ba.N = N;
+        ba.J = J;
+        ba.cls = reinterpret_cast<double*>(ws + lay.boxcls);
+        ba.sums = acc;
+        // whole coarse levels, from l = N down, while they fit the LDS table
+        size_t tail = 0;
+        for (int j = J; j >= 1; j--) {
+            size_t c = 1;
+            for (int i = 0; i < d.ndim; i++) c *= (size_t)(N >> j);
+            if (tail + c > 1024) break;
+            tail += c;
+        }
+        ba.lds_base = lay.boxn - tail;
+        ba.nlds = (int)tail;
+        SETD_HIP(launch_fill64(acc, J + 1, 0.0, stream));
+        for (int r = 0; r < R; r++) {
+            ba.r = r;
+            SETD_HIP(launch_fill64(ba.cls, (int64_t)(2 * lay.boxn), 0.0, stream));
+            if (d.precision == 32) SETD_HIP((launch_boxwidth<float>(ba, lay.boxn, stream)));
+            else SETD_HIP((launch_boxwidth<double>(ba, lay.boxn, stream)));
+        }
+        double sums[16];
+        SETD_HIP(hipMemcpyAsync(sums, acc, (size_t)(J + 1) * sizeof(double), hipMemcpyDeviceToHost, stream));
+        SETD_HIP(hipStreamSynchronize(stream));
+        // w_l^2 = (sum |h_a|^2 - sum_c |A_c|^2) / N^2d, averaged over realizations
+        const double norm = 1.0 / ((double)nreal * (double)nreal * R);
+        for (int j = 1; j <= J; j++) {
+            const double v = (sums[0] - sums[j]) * norm;
+            out[j - 1] = std::sqrt(v > 0.0 ? v : 0.0);
+        }
+        *len = (size_t)J;
         int f = 0;
         if ((st = nonfinite_any(&f)) != SETD_OK) return st;
         return f ? fail(SETD_E_NONFINITE, "a realization produced a non-finite value") : SETD_OK;

@@ -95,6 +95,19 @@ struct SpecArgs {
     double* acc;                  // [3][nbins][M] sums, then [nbins] mode counts
 };
 
+// arguments of the box-averaged width: class sums of one realization
+struct BoxArgs {
+    Geo g;
+    const Item* items;
+    int r;            // realization (item index)
+    int total;        // stored elements per realization
+    int N, J;         // lattice points per axis (equal axes), log2 N
+    double* cls;      // [sum_j (N >> j)^d][re, im] class sums, levels j = 1..J
+    double* sums;     // [J + 1]: sums[0] sum_a |h_a|^2, sums[j] sum_c |A_c|^2 of level j (a != 0)
+    size_t lds_base;  // first class summed in LDS (the coarse levels at the end)
+    int nlds;         // classes summed in LDS, at most 1024
+};
+
 // observable reductions
 enum { RED_SK = 0, RED_WIDTH = 1, RED_TWOTIME = 2, RED_RESPONSE = 3 };
 

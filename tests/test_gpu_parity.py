@@ -337,6 +337,58 @@ def test_spectrum_matches_oracle(p, M):
     g.close()
 
 
+@pytest.mark.parametrize("p", [W.model_a([64, 64], precision=64, realizations=3, order=2),
+                               W.kpz([32, 32], precision=32, realizations=2, dealias=0, ic_kind=1, ic_sigma=0.2),
+                               W.kpz([64, 64], precision=64, realizations=2, ic_kind=1, ic_sigma=0.3),
+                               W.model_a([16, 16, 16], precision=32, realizations=2),
+                               W.cgl([16, 16, 16], precision=64, realizations=2)])
+def test_box_width_matches_oracle(p):
+    """Box-averaged width w_l (Sec. 5 KPZ): the device sums the spectrum into
+    the alias classes of each box size (no transform); the oracle takes box
+    means of the real-space field."""
+    S = _setd()
+    g = S.Plan(p)
+    o = O.Sim(p)
+    tol = 1e-10 if p["precision"] == 64 else 2e-4
+    for steps in (0, 6):
+        g.step(steps)
+        o.step(steps)
+        a, b = g.box_width(), o.observe(O.OBS_BOXWIDTH)
+        assert len(a) == len(b) == int(p["n"][0]).bit_length() - 1
+        err = float(np.max(np.abs(a - b) / np.maximum(b, 1e-300)))
+        say("boxwidth", p["nl"], p["n"], "f%d" % p["precision"], "steps", steps, "err", err)
+        assert err <= tol
+    # the largest box is the whole lattice: the global width
+    assert a[-1] == pytest.approx(g.observe(S.OBS_WIDTH)[0], rel=1e-9)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_box_width_full_size_set_state(prec):
+    """512^2 Model B, the same seeded spectrum set on both sides."""
+    S = _setd()
+    p = W.model_b([512, 512], precision=prec, realizations=2, dealias=1)
+    g = S.Plan(p)
+    o = O.Sim(p)
+    for r in range(2):
+        x = W.random_spectrum(p, 40 + r, 0.05)
+        g.set(r, x)
+        o.set(r, x)
+    a, b = g.box_width(), o.observe(O.OBS_BOXWIDTH)
+    err = float(np.max(np.abs(a - b) / b))
+    say("boxwidth 512^2 f%d err" % prec, err)
+    assert err <= (1e-10 if prec == 64 else 1e-5)
+    g.close()
+
+
+def test_box_width_needs_equal_axes():
+    S = _setd()
+    g = S.Plan(W.model_a([32, 64], precision=64, realizations=1))
+    with pytest.raises(S.SetdError):
+        g.box_width()
+    g.close()
+
+
 def test_observables_match_oracle():
     S = _setd()
     for p in [W.model_a([64, 64], precision=64, realizations=3, order=2),
