@@ -607,6 +607,16 @@ int orc_noise_slot(const orc_sim* s, size_t e, uint32_t* P, int* half, int* kind
         if (ep == e) *kind = 1;
         else if (ep < e) { *kind = 2; ed = ep; }
     }
+    if (d->ndim == 1 && !d->complex_field) {
+        /* a real line stores a = 0..N/2: the block of a < N/2 serves a and
+           a + 2M (M = N/8, 1 for N < 8), the lower one taking half 0; the
+           Nyquist mode a = N/2 draws alone from block 2M */
+        size_t M1 = d->n[0] >= 8 ? (size_t)d->n[0] / 8 : 1;
+        size_t a = ed;
+        if (2 * a == (size_t)d->n[0]) { *P = (uint32_t)(2 * M1); *half = 0; }
+        else { size_t q = a / M1; *P = (uint32_t)(a % M1 + (q % 2) * M1); *half = (int)(q / 2); }
+        return 0;
+    }
     /* pair the drawing mode's axis-0 position j0 with (j0 mod M) + (7 - j0 div M) M */
     size_t S = s->nspec / (size_t)s->nh[0];   /* elements per axis-0 position */
     size_t j0 = ed / S, rest = ed % S;

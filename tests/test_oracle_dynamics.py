@@ -26,13 +26,13 @@ def test_noise_free_decay_is_exact():
     assert np.max(np.abs(s2.get(0) - expect)) <= 40 * 4e-16 * np.max(np.abs(phi0))
 
 
-@pytest.mark.parametrize("model", ["A", "B"])
-def test_linear_theory_variance_is_exact_for_any_h(model):
+@pytest.mark.parametrize("model,n", [("A", [16, 16]), ("B", [16, 16]), ("A", [64]), ("B", [64])])
+def test_linear_theory_variance_is_exact_for_any_h(model, n):
     """For u = 0 SETD1 samples the OU transition exactly, so from phi = 0 the
     mode variance after t = n h is (N^2/L)^d D_a (e^{2 c t} - 1)/c for every h;
-    at large t this is the steady state D/(r + k^2) times (N^2/L)^d."""
+    at large t this is the steady state D/(r + k^2) times (N^2/L)^d (2D
+    lattices and the 1D lines of Sec. 5's Model A/B figures)."""
     r, T, h = 0.7, 0.3, 0.25
-    n = [16, 16]
     mk = W.model_a if model == "A" else W.model_b
     p = mk(n, r=r, u=0.0, T=T, nl="none", h=h, order=1, ic_kind=0, realizations=200,
            dealias=0, seed=11, dx=1.3)
@@ -43,8 +43,8 @@ def test_linear_theory_variance_is_exact_for_any_h(model):
     k2 = s.coef(4)
     c = -(r + k2) if model == "A" else -k2 * (r + k2)
     D = T if model == "A" else T * k2
-    L = 16 * 1.3
-    lat = (16**2 / L) ** 2
+    L = n[0] * 1.3
+    lat = (n[0]**2 / L) ** len(n)
     t = nsteps * h
     with np.errstate(divide="ignore", invalid="ignore"):
         var = lat * np.where(c != 0, D * np.expm1(2 * c * t) / c, 2 * D * t)
@@ -122,6 +122,27 @@ def test_homogeneous_model_a_logistic_ode(order, expect):
     assert all(abs(r_ - expect) < 0.25 * expect for r_ in ratios), (errs, ratios)
 
 
+@pytest.mark.parametrize("order,expect", [(1, 2.0), (2, 4.0)])
+def test_homogeneous_model_a_logistic_ode_on_a_line(order, expect):
+    """The same ODE on a 1D line: phi(t)^2 = 1 / (1 + (1/phi0^2 - 1) e^{-2t})."""
+    N, phi0, T = 16, 0.3, 1.0
+    errs = []
+    for h in (0.1, 0.05, 0.025):
+        p = W.model_a([N], r=-1.0, u=1.0, T=0.0, h=h, order=order, ic_kind=0, dealias=1)
+        s = O.Sim(p)
+        st = np.zeros(W.spectral_shape(p), dtype=complex)
+        st[0] = phi0 * N
+        s.set(0, st)
+        nsteps = int(round(T / h))
+        s.step(nsteps)
+        got = s.get(0)[0].real / N
+        exact = 1.0 / np.sqrt(1 + (1 / phi0**2 - 1) * np.exp(-2 * nsteps * h))
+        errs.append(abs(got - exact))
+        assert np.max(np.abs(s.get(0)[1:])) < 1e-12
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(abs(r_ - expect) < 0.25 * expect for r_ in ratios), (errs, ratios)
+
+
 def _first_F(p, state):
     """F_0 of the first SETD2 step: the stored previous nonlinear term."""
     s = O.Sim(dict(p, order=2, T=0.0, noise_D=0.0, ic_kind=0))
@@ -171,6 +192,34 @@ def test_kpz_gradient_squared_spectrum():
     expect[0, 0] = lam / 2 * A**2 * k2 / 2 * N * N
     expect[2 * m1, 2 * m2] = -lam / 2 * A**2 * k2 / 4 * N * N
     assert np.max(np.abs(F - expect)) < 1e-11 * N * N
+
+
+def test_kpz_gradient_squared_spectrum_on_a_line():
+    """1D KPZ (the line of Sec. 5's scaling figure): (lambda/2) (h')^2 for
+    h = A cos(k x) is (lambda/2) A^2 k^2 (1 - cos 2kx)/2; the Nyquist mode's
+    derivative is dropped, so a Nyquist wave has no nonlinear term."""
+    N, m, A, lam, dx = 64, 3, 0.8, 50.0, 0.5
+    p = W.kpz([N], lam=lam, dealias=0, dx=dx)
+    x = np.arange(N)
+    F = _first_F(p, np.fft.rfft(A * np.cos(2 * np.pi * m * x / N)))
+    k2 = (2 * np.pi * m / (N * dx)) ** 2
+    expect = np.zeros_like(F)
+    expect[0] = lam / 2 * A**2 * k2 / 2 * N
+    expect[2 * m] = -lam / 2 * A**2 * k2 / 4 * N
+    assert np.max(np.abs(F - expect)) < 1e-11 * N * lam
+    F = _first_F(p, np.fft.rfft(A * np.cos(np.pi * x)))
+    assert np.max(np.abs(F)) < 1e-11 * N * lam
+
+
+def test_phi_cubed_spectrum_on_a_line():
+    N, m, A, u = 32, 3, 0.7, 1.3
+    p = W.model_a([N], u=u, dealias=1)
+    x = np.arange(N)
+    F = _first_F(p, np.fft.rfft(A * np.cos(2 * np.pi * m * x / N)))
+    expect = np.zeros_like(F)
+    expect[m] = -u * 3 * A**3 / 4 * N / 2
+    expect[3 * m] = -u * A**3 / 4 * N / 2
+    assert np.max(np.abs(F - expect)) < 1e-12 * N
 
 
 def test_cgl_two_mode_cubic_spectrum():

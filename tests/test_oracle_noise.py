@@ -86,6 +86,55 @@ def test_noise_slots(kind, shape):
             assert ra == rb and jb == ja % M + (7 - ja // M) * M
 
 
+@pytest.mark.parametrize("N,dealias", [(64, 0), (64, 1), (8, 0), (4, 0), (1024, 1)])
+def test_noise_slots_real_line(N, dealias):
+    """A real 1D line (App. B, noise in one dimension): eta_0 and eta_{N/2} are
+    real N(0, 1), the interior modes complex; every mode has a slot of its
+    own; the block of a < N/2 serves a and a + 2M (M = N/8), the lower one
+    taking half 0, and the Nyquist mode draws from block 2M."""
+    p = W.model_a([N], dealias=dealias, ic_kind=0, T=1.0, r=1.0, seed=7)
+    s = O.Sim(p)
+    G = s.coef(3)
+    n = 9
+    eta = s.noise_xi(n)[0] / np.where(G > 0, G, 1)
+    M = N // 8 if N >= 8 else 1
+    K = (N - 1) // 3 if dealias else N // 2
+    owners = set()
+    for a in range(N // 2 + 1):
+        if a > K:
+            assert eta[a] == 0
+            continue
+        P, half, kd = s.noise_slot(a)
+        assert kd == (1 if a in (0, N // 2) else 0)
+        assert (P, half) not in owners
+        owners.add((P, half))
+        if 2 * a == N:
+            assert (P, half) == (2 * M, 0)
+        else:
+            assert half == (a // M) // 2 and P == a % M + ((a // M) % 2) * M
+            assert a == P % M + M * (P // M + 2 * half)
+        z1, z2 = O.noise_normals(7, P, n, 0, half)
+        want = z1 if kd == 1 else (z1 + 1j * z2) / np.sqrt(2)
+        assert eta[a] == pytest.approx(want, abs=1e-15)
+        if kd == 1:
+            assert eta[a].imag == 0.0
+
+
+def test_noise_of_a_real_line_is_white_in_real_space():
+    """App. A sanity check in 1D: the inverse transform of eta is real white
+    noise of per-site variance 1/N, uncorrelated between neighbours."""
+    N = 64
+    p = W.model_a([N], dealias=0, ic_kind=0, T=1.0, r=1.0)
+    s = O.Sim(p)
+    G = s.coef(3)
+    x = np.stack([np.fft.irfft(s.noise_xi(n)[0] / G, N) for n in range(400)]) * np.sqrt(N)
+    v = x.reshape(-1)
+    assert abs(v.mean()) < 5 / np.sqrt(v.size)
+    assert abs(v.var() - 1.0) < 5 * np.sqrt(2.0 / v.size)
+    c = np.mean(x * np.roll(x, 1, axis=1))
+    assert abs(c) < 5 / np.sqrt(v.size)
+
+
 def test_noise_is_real_white_noise_in_real_space():
     """App. A sanity check: a unit-variance Hermitian eta_a is, after the inverse
     transform, real noise with per-site variance N^-d."""
