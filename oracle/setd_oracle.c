@@ -987,7 +987,8 @@ int orc_observe(orc_sim* s, int kind, double* out, size_t cap, size_t* len)
             int li = 0;
             for (int l = 2; l <= N; l *= 2, li++) {
                 const int P = N / l;
-                const size_t nbox = (size_t)P * P * (nd == 3 ? P : 1);
+                size_t nbox = 1;
+                for (int dd = 0; dd < nd; dd++) nbox *= (size_t)P;
                 cplx* s1 = (cplx*)calloc(nbox, sizeof(cplx));
                 double* s2 = (double*)calloc(nbox, sizeof(double));
                 for (size_t i = 0; i < s->nreal; i++) {

@@ -63,3 +63,28 @@ def test_white_noise_box_variance():
         want = sig * sig * (1 - 1.0 / l ** 2)
         # relative SE of a sample variance over R 32^2 sites: ~ sqrt(2 / (R 32^2))
         assert abs(wl ** 2 - want) < 6 * want * np.sqrt(2.0 / (R * 1024)) + 1e-15
+
+
+def test_white_noise_box_variance_on_a_line():
+    """1D (the line of the KPZ scaling figure): i.i.d. sites give
+    E w_l^2 = s^2 (1 - 1/l), and a plane wave's box variances equal the brute
+    force over the grid."""
+    sig, R, N = 0.3, 64, 256
+    p = W.kpz([N], dealias=0, realizations=R, precision=64, ic_kind=1, ic_sigma=sig, seed=4)
+    s = O.Sim(p)
+    w = s.observe(O.OBS_BOXWIDTH)
+    assert len(w) == 8
+    for wl, l in zip(w, [2 ** j for j in range(1, 9)]):
+        want = sig * sig * (1 - 1.0 / l)
+        assert abs(wl ** 2 - want) < 6 * want * np.sqrt(2.0 / (R * N)) + 1e-15
+    p = W.kpz([16], dealias=0, realizations=1, precision=64, ic_kind=0)
+    s = O.Sim(p)
+    A, m = 0.7, 3
+    spec = np.zeros(s.spec_shape, dtype=complex)
+    spec[m] = 16 * A / 2
+    s.set(0, spec)
+    h = A * np.cos(2 * np.pi * m * np.arange(16) / 16)
+    for wl, l in zip(s.observe(O.OBS_BOXWIDTH), [2, 4, 8, 16]):
+        b = h.reshape(16 // l, l)
+        brute = np.mean(np.mean(b ** 2, axis=1) - np.mean(b, axis=1) ** 2)
+        assert wl ** 2 == pytest.approx(brute, rel=1e-12, abs=1e-15)
