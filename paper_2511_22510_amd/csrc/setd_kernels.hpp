@@ -16,6 +16,8 @@
 // `pitch` so that every line segment starts on a 128-byte boundary.
 #pragma once
 
+#include <type_traits>
+
 #include "setd_device.hpp"
 
 namespace setd {
@@ -135,6 +137,25 @@ struct NoiseSlot {
 
 __device__ __forceinline__ NoiseSlot noise_slot(const Geo& g, int j0, int j1, int jl)
 {
+    if (g.ndim == 1) {
+        // one axis, position jl, M = N/8: a real line pairs a with a + 2M (the
+        // Nyquist mode draws alone from block 2M, a = 0 and N/2 take z1); a
+        // complex line pairs j with (j mod M) + (7 - j div M) M
+        const int N = g.n[0], sh = __ffs(N) - 4, M = 1 << sh;
+        NoiseSlot s;
+        if (!g.cplx) {
+            const int q = jl >> sh;
+            s.kind = (jl == 0 || 2 * jl == N) ? 1 : 0;
+            s.P = (2 * jl == N) ? (uint32_t)(2 * M) : (uint32_t)((jl & (M - 1)) + (q & 1) * M);
+            s.half = (2 * jl == N) ? 0u : (uint32_t)(q >> 1);
+        } else {
+            const int q = jl >> sh;
+            s.kind = 0;
+            s.P = (uint32_t)((jl & (M - 1)) + ((q < 4 ? q : 7 - q) << sh));
+            s.half = q >= 4 ? 1u : 0u;
+        }
+        return s;
+    }
     const int last = g.ndim - 1;
     int d0 = j0, d1 = j1, kind = 0;
     if (!g.cplx && !(jl > 0 && 2 * jl < g.n[last])) {
@@ -1392,6 +1413,436 @@ __global__ void __launch_bounds__(256) k_observe(ObsArgs a)
     __syncthreads();
     for (int i = threadIdx.x; i < 3 * nb; i += blockDim.x)
         if (sb[i] != 0.0) atomicAdd(&a.acc[i], sb[i]);
+}
+
+// ---------------------------------------------------------------- 1D lattices
+// A line of N sites is a whole lattice: one group of N/8 threads holds a
+// line's transform (thread t: bins t + q N/8), and the state stays in
+// registers for all steps of a launch, so HBM sees the state once per launch.
+// Real fields pair two realizations in one complex line (z = h1 + i h2, as
+// the row pass of the other lattices does); complex fields take a line each.
+struct Line1dArgs {
+    Geo g;
+    const Item* items;
+    int nitems;
+    int nlines;   // realization pairs (real fields) or realizations (complex)
+    int mode;     // MODE_STEP or MODE_IC
+    int sub;      // sub-step of the scheduler tick
+    int nsteps;   // MODE_STEP: steps of this launch
+};
+
+template <typename T, int N>
+using Line1dTw = typename std::conditional<sizeof(T) == 4, LineTwP<T, N>, LineTw<T, N>>::type;
+
+template <typename T, int N>
+__device__ __forceinline__ void line1d_tw(Line1dTw<T, N>& tw, int t, const cx<T>* tab)
+{
+    LineTw<T, N> base;
+    line_tw_load(base, t, tab);
+    if constexpr (sizeof(T) == 4) line_tw_expand(tw, base);
+    else tw = base;
+}
+
+// Real field, realizations 2l and 2l + 1 of line l.  Thread t keeps the stored
+// modes a = t + q N/8 (q < 4, and a = N/2 in slot 4 of thread 0) of both
+// realizations.  A step: pack z = A + i B from the two half spectra (the bins
+// above N/2 are conj(A_{N-k}) + i conj(B_{N-k}), read back through LDS),
+// inverse transform, the nonlinearity of each real part, forward transform,
+// split W into the two spectra through LDS, and the update of Eq. SETD1/SETD2
+// per realization with its own noise, table and step.  KIND 0: phi^3 (Model A,
+// and Model B with its k^2 in the prefactor), 1: KPZ ((lambda/2) h'^2 from the
+// line of h + i h' per realization pair), 2: no nonlinearity.
+template <typename T, int N, int PAD, bool DA, int KIND>
+__global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int TPL = N / 8, M = N / 8;
+    constexpr int LPB = 256 / TPL;
+    constexpr int LL = lds_len<N, PAD>();
+    constexpr int QS = DA ? 3 : 5;    // register slots of stored modes
+    const Geo& g = a.g;
+    const int tid = threadIdx.x;
+    const int l = tid / TPL, t = tid - l * TPL;
+    const int line = blockIdx.x * LPB + l;
+    cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw) + (size_t)l * 2 * LL;
+    const int ra = 2 * line, rb = 2 * line + 1;
+    const bool va = line < a.nlines && ra < a.nitems, vb = line < a.nlines && rb < a.nitems;
+    const Item& ia = a.items[va ? ra : 0];
+    const Item& ib = a.items[vb ? rb : (va ? ra : 0)];
+    const bool acta = va && a.sub < ia.steps, actb = vb && a.sub < ib.steps;
+    const int K = DA ? (N - 1) / 3 : N / 2;
+    Line1dTw<T, N> tw;
+    line1d_tw<T, N>(tw, t, twid<T>(ia.tw0));
+    const T inv = (T)ia.inv_vol;
+    // mode of slot q, and whether it is stored
+    auto mode_of = [&](int q) { return t + q * M; };
+    auto stored = [&](int q) { return q < 4 ? (t + q * M <= K) : (!DA && t == 0); };
+
+    cx<T> pa[QS], pb[QS];
+    if (a.mode == MODE_IC) {
+        // per site: h = sigma z1 of the Philox block (site, 0, r, 1)
+        cx<T> v[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            T z1a = T(0), z2a, z1b = T(0), z2b;
+            const uint32_t site = (uint32_t)(t + q * M);
+            if (va) normal_pair(ia.seed, site, 0u, ia.r, 1u, z1a, z2a);
+            if (vb) normal_pair(ib.seed, site, 0u, ib.r, 1u, z1b, z2b);
+            v[q] = {(T)ia.ic_sigma * z1a, (T)ib.ic_sigma * z1b};
+        }
+        fft_line<T, N, -1, PAD>(v, t, L, 1, tw);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; q++) L[lds_slot<PAD>(t + q * M)] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QS; q++) {
+            const int k = mode_of(q) & (N - 1);
+            const cx<T> Zk = L[lds_slot<PAD>(k)], Zm = L[lds_slot<PAD>((N - k) & (N - 1))];
+            pa[q] = {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y - Zm.y)};
+            pb[q] = {T(0.5) * (Zk.y + Zm.y), T(0.5) * (Zm.x - Zk.x)};
+            if (!stored(q)) pa[q] = pb[q] = czero<T>();
+        }
+        cx<T>* phia = reinterpret_cast<cx<T>*>(ia.phi);
+        cx<T>* phib = reinterpret_cast<cx<T>*>(ib.phi);
+#pragma unroll
+        for (int q = 0; q < QS; q++) {
+            if (!stored(q)) continue;
+            const int m = mode_of(q);
+            if (m == 0 || 2 * m == N) {
+                pa[q].y = T(0);
+                pb[q].y = T(0);
+            }
+            if (va) phia[m] = pa[q];
+            if (vb) phib[m] = pb[q];
+        }
+        return;
+    }
+
+    // state, F_{n-1}, coefficients and steps of both realizations
+    cx<T> fa[QS], fb[QS];
+    Coef<T> ca[QS], cb[QS];
+    const cx<T>* phia0 = reinterpret_cast<const cx<T>*>(ia.phi);
+    const cx<T>* phib0 = reinterpret_cast<const cx<T>*>(ib.phi);
+    const cx<T>* preva = reinterpret_cast<const cx<T>*>(ia.prev);
+    const cx<T>* prevb = reinterpret_cast<const cx<T>*>(ib.prev);
+    const int64_t stepa = va ? ia.ctrl->step : 0, stepb = vb ? ib.ctrl->step : 0;
+    const int hpa = va ? ia.ctrl->have_prev : 0, hpb = vb ? ib.ctrl->have_prev : 0;
+    const bool o2 = ia.order == 2;
+#pragma unroll
+    for (int q = 0; q < QS; q++) {
+        pa[q] = pb[q] = fa[q] = fb[q] = czero<T>();
+        ca[q] = cb[q] = Coef<T>{czero<T>(), czero<T>(), czero<T>(), T(0)};
+        if (!stored(q)) continue;
+        const int m = mode_of(q);
+        if (va) {
+            pa[q] = phia0[m];
+            if (o2 && hpa) fa[q] = preva[m];
+            ca[q] = load_coef_t<T, false>(ia.coef, coef_key(ia, m, 0, 0));   // real fields: real tables
+        }
+        if (vb) {
+            pb[q] = phib0[m];
+            if (o2 && hpb) fb[q] = prevb[m];
+            cb[q] = load_coef_t<T, false>(ib.coef, coef_key(ib, m, 0, 0));
+        }
+        if (m == 0 || 2 * m == N) {
+            pa[q].y = T(0);
+            pb[q].y = T(0);
+        }
+    }
+    const T dka = (T)ia.dk[0], dkb = (T)ib.dk[0];
+    const cx<T> pra = nl_pref<T>(ia, T(0)), prb = nl_pref<T>(ib, T(0));
+
+#pragma unroll 1
+    for (int s = 0; s < a.nsteps; s++) {
+        cx<T> F1[QS], F2[QS];
+        if constexpr (KIND != 2) {
+            // pack the two half spectra (KPZ: of h and h' per realization)
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < QS; q++) {
+                if (q == 4 && t != 0) continue;
+                const int m = mode_of(q);
+                cx<T> A = pa[q], B = pb[q];
+                if constexpr (KIND == 1) {
+                    // h' = i k h, the Nyquist derivative dropped
+                    const T kk = (2 * m == N) ? T(0) : (T)m;
+                    A = {-kk * dka * pa[q].y, kk * dka * pa[q].x};
+                    B = {-kk * dkb * pb[q].y, kk * dkb * pb[q].x};
+                }
+                L[lds_slot<PAD>(m)] = A;
+                L[LL + lds_slot<PAD>(m)] = B;
+            }
+            __syncthreads();
+            cx<T> z[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int k = t + q * M;
+                // bins whose mode (k or N - k) is not stored are zero
+                if ((DA && (q == 3 || q == 4)) || (k <= N / 2 ? k : N - k) > K) {
+                    z[q] = czero<T>();
+                } else if (k <= N / 2) {
+                    const cx<T> A = L[lds_slot<PAD>(k)], B = L[LL + lds_slot<PAD>(k)];
+                    z[q] = {A.x - B.y, A.y + B.x};
+                } else {
+                    const cx<T> A = L[lds_slot<PAD>(N - k)], B = L[LL + lds_slot<PAD>(N - k)];
+                    z[q] = {A.x + B.y, B.x - A.y};
+                }
+            }
+            fft_line<T, N, +1, PAD>(z, t, L, 1, tw);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const T x = z[q].x * inv, y = z[q].y * inv;
+                z[q] = (KIND == 1) ? cx<T>{x * x, y * y} : cx<T>{x * x * x, y * y * y};
+            }
+            fft_line<T, N, -1, PAD>(z, t, L, 1, tw);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                if (DA && (q == 3 || q == 4)) continue;
+                L[lds_slot<PAD>(t + q * M)] = z[q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < QS; q++) {
+                const int k = mode_of(q) & (N - 1);
+                const cx<T> Zk = L[lds_slot<PAD>(k)], Zm = L[lds_slot<PAD>((N - k) & (N - 1))];
+                const cx<T> wa = {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y - Zm.y)};
+                const cx<T> wb = {T(0.5) * (Zk.y + Zm.y), T(0.5) * (Zm.x - Zk.x)};
+                const T k2a = (dka * (T)k) * (dka * (T)k), k2b = (dkb * (T)k) * (dkb * (T)k);
+                // Model B: -u k^2; the others a constant
+                const T sa = (ia.nl == NL_PHI3_CONS) ? -(T)ia.par0 * k2a : pra.x;
+                const T sb = (ib.nl == NL_PHI3_CONS) ? -(T)ib.par0 * k2b : prb.x;
+                F1[q] = sa * wa;
+                F2[q] = sb * wb;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < QS; q++) F1[q] = F2[q] = czero<T>();
+        }
+        // noise: block t serves modes t and t + 2M, block t + M serves t + M
+        // and t + 3M, block 2M the Nyquist mode (thread 0)
+        cx<T> ea[QS], eb[QS];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            uint32_t xa[4], xb[4];
+            const uint32_t P = (uint32_t)(t + h * M);
+            if (acta) philox_block(ia.seed, P, (uint32_t)(stepa + s), ia.r, 0u, xa);
+            if (actb) philox_block(ib.seed, P, (uint32_t)(stepb + s), ib.r, 0u, xb);
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int q = h + 2 * u;
+                if (q >= QS) continue;
+                NoiseSlot ns;
+                ns.P = P;
+                ns.half = (uint32_t)u;
+                ns.kind = (q == 0 && t == 0) ? 1 : 0;
+                ea[q] = acta ? eta_of<T>(xa, ns) : czero<T>();
+                eb[q] = actb ? eta_of<T>(xb, ns) : czero<T>();
+            }
+        }
+        if constexpr (!DA) {
+            ea[4] = eb[4] = czero<T>();
+            if (t == 0) {
+                uint32_t xa[4], xb[4];
+                NoiseSlot ns;
+                ns.P = (uint32_t)(2 * M);
+                ns.half = 0u;
+                ns.kind = 1;
+                if (acta) {
+                    philox_block(ia.seed, ns.P, (uint32_t)(stepa + s), ia.r, 0u, xa);
+                    ea[4] = eta_of<T>(xa, ns);
+                }
+                if (actb) {
+                    philox_block(ib.seed, ns.P, (uint32_t)(stepb + s), ib.r, 0u, xb);
+                    eb[4] = eta_of<T>(xb, ns);
+                }
+            }
+        }
+        // Eq. SETD1 / SETD2 (the first step of a fresh state takes F_{n-1} = F_n)
+        const bool upa = o2 && (s > 0 || hpa), upb = o2 && (s > 0 || hpb);
+#pragma unroll
+        for (int q = 0; q < QS; q++) {
+            if (!stored(q)) continue;
+            const int m = mode_of(q);
+            cx<T> na = cmul(ca[q].E, pa[q]) + cmul(ca[q].wa, F1[q]) + ca[q].G * ea[q];
+            cx<T> nb = cmul(cb[q].E, pb[q]) + cmul(cb[q].wa, F2[q]) + cb[q].G * eb[q];
+            if (o2) {
+                na = na + cmul(ca[q].wb, upa ? fa[q] : F1[q]);
+                nb = nb + cmul(cb[q].wb, upb ? fb[q] : F2[q]);
+                fa[q] = F1[q];
+                fb[q] = F2[q];
+            }
+            if (m == 0 || 2 * m == N) {
+                na.y = T(0);
+                nb.y = T(0);
+            }
+            if (acta) pa[q] = na;
+            if (actb) pb[q] = nb;
+        }
+    }
+    cx<T>* phia = reinterpret_cast<cx<T>*>(ia.phi);
+    cx<T>* phib = reinterpret_cast<cx<T>*>(ib.phi);
+    cx<T>* pva = reinterpret_cast<cx<T>*>(ia.prev);
+    cx<T>* pvb = reinterpret_cast<cx<T>*>(ib.prev);
+    bool bada = false, badb = false;
+#pragma unroll
+    for (int q = 0; q < QS; q++) {
+        if (!stored(q)) continue;
+        const int m = mode_of(q);
+        if (acta) {
+            phia[m] = pa[q];
+            if (o2 && a.nsteps > 0) pva[m] = fa[q];
+            bada |= !(isfinite(pa[q].x) && isfinite(pa[q].y));
+        }
+        if (actb) {
+            phib[m] = pb[q];
+            if (o2 && a.nsteps > 0) pvb[m] = fb[q];
+            badb |= !(isfinite(pb[q].x) && isfinite(pb[q].y));
+        }
+    }
+    if (bada) atomicOr(&ia.ctrl->nonfinite, 1);
+    if (badb) atomicOr(&ib.ctrl->nonfinite, 1);
+    // every thread has read the step counters before thread 0 of the line
+    // advances them
+    __syncthreads();
+    if (t == 0) {
+        if (acta) {
+            ia.ctrl->step = stepa + a.nsteps;
+            if (a.nsteps > 0) ia.ctrl->have_prev = 1;
+        }
+        if (actb) {
+            ib.ctrl->step = stepb + a.nsteps;
+            if (a.nsteps > 0) ib.ctrl->have_prev = 1;
+        }
+    }
+}
+
+// Complex field, one realization per line: thread t keeps bins j = t + q N/8
+// of phi (FFT order).  KIND 0: CGL, F = -(1 + i beta) FFT[|phi|^2 phi];
+// 1: no nonlinearity.  The noise block t + qM (q < 4) serves bins q and 7 - q.
+template <typename T, int N, int PAD, bool DA, int KIND>
+__global__ void __launch_bounds__(256) k_line1d_cplx(Line1dArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int TPL = N / 8, M = N / 8;
+    constexpr int LPB = 256 / TPL;
+    constexpr int LL = lds_len<N, PAD>();
+    const Geo& g = a.g;
+    const int tid = threadIdx.x;
+    const int l = tid / TPL, t = tid - l * TPL;
+    const int line = blockIdx.x * LPB + l;
+    cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw) + (size_t)l * LL;
+    const bool valid = line < a.nlines;
+    const Item& it = a.items[valid ? line : 0];
+    const bool act = valid && a.sub < it.steps;
+    Line1dTw<T, N> tw;
+    line1d_tw<T, N>(tw, t, twid<T>(it.tw0));
+    const T inv = (T)it.inv_vol;
+    const int kept = g.kept[0], kp = g.kp[0];
+    int si[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) si[q] = (DA && (q == 3 || q == 4)) ? -1 : stored_idx(t + q * M, N, kept, kp);
+    cx<T>* phi = reinterpret_cast<cx<T>*>(it.phi);
+    cx<T> p[8];
+    if (a.mode == MODE_IC) {
+        // per site: phi = sigma (z1 + i z2) of the Philox block (site, 0, r, 1)
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            T z1 = T(0), z2 = T(0);
+            if (valid) normal_pair(it.seed, (uint32_t)(t + q * M), 0u, it.r, 1u, z1, z2);
+            p[q] = {(T)it.ic_sigma * z1, (T)it.ic_sigma * z2};
+        }
+        fft_line<T, N, -1, PAD>(p, t, L, 1, tw);
+        if (valid) {
+#pragma unroll
+            for (int q = 0; q < 8; q++)
+                if (si[q] >= 0) phi[si[q]] = p[q];
+        }
+        return;
+    }
+    cx<T> fp[8];
+    Coef<T> cf[8];
+    const int64_t step0 = valid ? it.ctrl->step : 0;
+    const int hp = valid ? it.ctrl->have_prev : 0;
+    const bool o2 = it.order == 2;
+    const cx<T>* prev0 = reinterpret_cast<const cx<T>*>(it.prev);
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        p[q] = fp[q] = czero<T>();
+        cf[q] = Coef<T>{czero<T>(), czero<T>(), czero<T>(), T(0)};
+        if (si[q] < 0 || !valid) continue;
+        p[q] = phi[si[q]];
+        if (o2 && hp) fp[q] = prev0[si[q]];
+        cf[q] = load_coef_t<T, true>(it.coef, coef_key(it, sgn_idx(t + q * M, N), 0, 0));   // complex tables
+    }
+    const cx<T> pref = nl_pref<T>(it, T(0));
+    bool bad = false;
+#pragma unroll 1
+    for (int s = 0; s < a.nsteps; s++) {
+        cx<T> F[8];
+        if constexpr (KIND == 0) {
+            cx<T> z[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) z[q] = p[q];
+            fft_line<T, N, +1, PAD>(z, t, L, 1, tw);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const T x = z[q].x * inv, y = z[q].y * inv;
+                const T m2 = x * x + y * y;
+                z[q] = {m2 * x, m2 * y};
+            }
+            fft_line<T, N, -1, PAD>(z, t, L, 1, tw);
+#pragma unroll
+            for (int q = 0; q < 8; q++) F[q] = (si[q] >= 0) ? cmul(pref, z[q]) : czero<T>();
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; q++) F[q] = czero<T>();
+        }
+        cx<T> eta[8];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            eta[q] = eta[7 - q] = czero<T>();
+            if (DA && q == 3) continue;
+            if (!act || (si[q] < 0 && si[7 - q] < 0)) continue;
+            uint32_t x[4];
+            philox_block(it.seed, (uint32_t)(t + q * M), (uint32_t)(step0 + s), it.r, 0u, x);
+            NoiseSlot ns;
+            ns.P = (uint32_t)(t + q * M);
+            ns.kind = 0;
+            ns.half = 0u;
+            eta[q] = eta_of<T>(x, ns);
+            ns.half = 1u;
+            eta[7 - q] = eta_of<T>(x, ns);
+        }
+        const bool up = o2 && (s > 0 || hp);
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            if (si[q] < 0) continue;
+            cx<T> nw = cmul(cf[q].E, p[q]) + cmul(cf[q].wa, F[q]) + cf[q].G * eta[q];
+            if (o2) {
+                nw = nw + cmul(cf[q].wb, up ? fp[q] : F[q]);
+                fp[q] = F[q];
+            }
+            if (act) p[q] = nw;
+        }
+    }
+    cx<T>* pv = reinterpret_cast<cx<T>*>(it.prev);
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            if (si[q] < 0) continue;
+            phi[si[q]] = p[q];
+            if (o2 && a.nsteps > 0) pv[si[q]] = fp[q];
+            bad |= !(isfinite(p[q].x) && isfinite(p[q].y));
+        }
+    }
+    if (bad) atomicOr(&it.ctrl->nonfinite, 1);
+    __syncthreads();
+    if (t == 0 && act) {
+        it.ctrl->step = step0 + a.nsteps;
+        if (a.nsteps > 0) it.ctrl->have_prev = 1;
+    }
 }
 
 // ---------------------------------------------------------------- box-averaged width (Sec. 5 KPZ)

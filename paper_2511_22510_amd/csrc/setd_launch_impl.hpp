@@ -133,7 +133,7 @@ static hipError_t launch_hermitian_t(const Geo& g, const Item* items, int nitems
     a.g = g;
     a.items = items;
     a.which = which;
-    a.nplane = g.kept[0] * (g.ndim == 3 ? g.kept[1] : 1);
+    a.nplane = geo_rows(g);
     a.ncol = (2 * g.kp[g.ndim - 1] == g.n[g.ndim - 1]) ? 2 : 1;
     a.sub = sub;
     dim3 grid((a.nplane * a.ncol + 255) / 256, nitems);
@@ -240,13 +240,58 @@ hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, i
     LinArgs a;
     a.g = g;
     a.items = items;
-    a.total = g.kept[0] * (g.ndim == 3 ? g.kept[1] : 1) * g.pitch;
+    a.total = geo_rows(g) * g.pitch;
     a.sub = sub;
     a.mode = mode;
     a.new_step = new_step;
     dim3 grid((a.total + 255) / 256, nitems);
     hipLaunchKernelGGL((k_linear<T>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+// 1D lattices: one launch takes nsteps steps (MODE_STEP) or draws the initial
+// condition (MODE_IC)
+template <typename T, int N, bool DA>
+static hipError_t launch_line1d_n(const Geo& g, const Item* items, int nitems, int mode, int sub, int nsteps,
+                                  int nl, hipStream_t s)
+{
+    constexpr int TPL = N / 8, LPB = 256 / TPL, PAD = 0;
+    constexpr int LL = lds_len<N, PAD>();
+    Line1dArgs a;
+    a.g = g;
+    a.items = items;
+    a.nitems = nitems;
+    a.mode = mode;
+    a.sub = sub;
+    a.nsteps = nsteps;
+    if (g.cplx) {
+        a.nlines = nitems;
+        const dim3 grid((unsigned)((a.nlines + LPB - 1) / LPB));
+        const size_t lds = (size_t)LPB * LL * sizeof(cx<T>);
+        if (nl == NL_NONE) hipLaunchKernelGGL((k_line1d_cplx<T, N, PAD, DA, 1>), grid, dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((k_line1d_cplx<T, N, PAD, DA, 0>), grid, dim3(256), lds, s, a);
+        return hipGetLastError();
+    }
+    a.nlines = (nitems + 1) / 2;
+    const dim3 grid((unsigned)((a.nlines + LPB - 1) / LPB));
+    const size_t lds = (size_t)LPB * 2 * LL * sizeof(cx<T>);
+    if (nl == NL_KPZ) hipLaunchKernelGGL((k_line1d_real<T, N, PAD, DA, 1>), grid, dim3(256), lds, s, a);
+    else if (nl == NL_NONE) hipLaunchKernelGGL((k_line1d_real<T, N, PAD, DA, 2>), grid, dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_line1d_real<T, N, PAD, DA, 0>), grid, dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_line1d(const Geo& g, const Item* items, int nitems, int mode, int sub, int nsteps, int nl,
+                         hipStream_t s)
+{
+    if (g.ndim != 1 || nitems <= 0) return hipErrorInvalidValue;
+    if (g.dealias) {
+        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, true>(g, items, nitems, mode, sub, nsteps, nl, s)));
+    } else {
+        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, false>(g, items, nitems, mode, sub, nsteps, nl, s)));
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -293,7 +338,7 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
     a.nitems = nitems;
     a.kind = kind;
     a.nbins = nbins;
-    a.total = g.kept[0] * (g.ndim == 3 ? g.kept[1] : 1) * g.pitch;
+    a.total = geo_rows(g) * g.pitch;
     a.vol = vol;
     a.acc = acc;
     a.kick = kick;
@@ -313,6 +358,7 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
     template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, int64_t, hipStream_t); \
     template hipError_t launch_spectrum<T>(const SpecArgs&, int, hipStream_t);                                    \
     template hipError_t launch_boxwidth<T>(const BoxArgs&, size_t, hipStream_t);                                  \
+    template hipError_t launch_line1d<T>(const Geo&, const Item*, int, int, int, int, int, hipStream_t);          \
     template hipError_t launch_hermitian<T>(const Geo&, const Item*, int, int, hipStream_t);
 
 }  // namespace setd

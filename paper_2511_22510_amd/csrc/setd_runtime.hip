@@ -46,8 +46,7 @@ static size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 setd_status validate(const setd_desc& d)
 {
-    if (d.ndim == 1) return fail(SETD_E_UNSUPPORTED, "1D lattices are not built");
-    if (d.ndim != 2 && d.ndim != 3) return fail(SETD_E_INVAL, "ndim must be 2 or 3");
+    if (d.ndim < 1 || d.ndim > 3) return fail(SETD_E_INVAL, "ndim must be 1, 2 or 3");
     for (int i = 0; i < d.ndim; i++)
         if (!pow2_in(d.n[i], 8, 1024)) return fail(SETD_E_INVAL, "n[%d] = %d is not a power of two in [8, 1024]", i, d.n[i]);
     if (!(d.dx > 0) || !std::isfinite(d.dx)) return fail(SETD_E_INVAL, "dx must be positive");
@@ -68,7 +67,7 @@ setd_status validate(const setd_desc& d)
     if (d.complex_field && (d.nl == NL_PHI3 || d.nl == NL_PHI3_CONS || d.nl == NL_KPZ))
         return fail(SETD_E_UNSUPPORTED, "complex fields take the CGL nonlinearity or none");
     if (!d.complex_field && d.nl == NL_CGL) return fail(SETD_E_UNSUPPORTED, "the CGL nonlinearity needs a complex field");
-    if (d.nl == NL_KPZ && d.ndim != 2) return fail(SETD_E_UNSUPPORTED, "KPZ is built for 2D lattices");
+    if (d.nl == NL_KPZ && d.ndim == 3) return fail(SETD_E_UNSUPPORTED, "KPZ is built for 1D and 2D lattices");
     const double cs[6] = {d.c0[0], d.c0[1], d.c2[0], d.c2[1], d.c4[0], d.c4[1]};
     for (double v : cs)
         if (!std::isfinite(v)) return fail(SETD_E_INVAL, "c(k) coefficients must be finite");
@@ -140,7 +139,12 @@ setd_status Plan::init(const setd_desc& desc)
         if (d.n[i] != d.n[0]) iso = 0;
     int kmax[3] = {0, 0, 0};
     for (int i = 0; i < d.ndim; i++) kmax[i] = d.dealias ? (d.n[i] - 1) / 3 : d.n[i] / 2;
-    if (d.ndim == 2) {
+    if (d.ndim == 1) {
+        coef_mode = COEF_SEPARABLE;  // one entry per |a| of the line
+        keydim[0] = kmax[0] + 1;
+        keydim[1] = keydim[2] = 1;
+        nkeys = keydim[0];
+    } else if (d.ndim == 2) {
         coef_mode = COEF_PER_MODE;   // the state layout: coalesced, shared by all realizations
         keydim[0] = keydim[1] = keydim[2] = 1;
     } else if (iso) {
@@ -164,8 +168,8 @@ setd_status Plan::init(const setd_desc& desc)
     // sizes
     if (coef_mode == COEF_PER_MODE) nkeys = g.kept[0] * g.pitch;
     const size_t k1 = (d.ndim == 3) ? (size_t)g.kept[1] : 1;
-    S = (size_t)g.kept[0] * k1 * g.pitch;
-    P = (size_t)g.n[0] * k1 * g.pitch;
+    S = (size_t)geo_rows(g) * g.pitch;
+    P = (d.ndim == 1) ? 0 : (size_t)g.n[0] * k1 * g.pitch;   // a line keeps no partial transform
     B = (d.ndim == 3) ? (size_t)g.n[0] * g.n[1] * g.pitch : 0;
     // Realizations of an array lie an odd multiple of 256 bytes apart: blocks
     // that work on the same columns of different realizations at the same
@@ -180,7 +184,7 @@ setd_status Plan::init(const setd_desc& desc)
     Pb = real_stride(P * elt);
     Bb = B ? real_stride(B * elt) : 0;
     // SETD2 keeps only the carry unless F_{n-1} must stay readable
-    lean = d.order == 2 && !d.history_readback && d.nl != NL_NONE && axis0_register_ok(g, elt / 2);
+    lean = d.ndim >= 2 && d.order == 2 && !d.history_readback && d.nl != NL_NONE && axis0_register_ok(g, elt / 2);
 
     // workspace layout, every buffer 256-byte aligned
     size_t off = 0;
@@ -231,7 +235,7 @@ setd_status Plan::init(const setd_desc& desc)
 
 int Plan::passes_per_step() const
 {
-    if (d.nl == NL_NONE) return 1;
+    if (d.nl == NL_NONE || d.ndim == 1) return 1;
     return d.ndim == 2 ? 2 : 4;
 }
 
@@ -245,6 +249,12 @@ void Plan::pass_bytes(double* out) const
     const double kl = (double)g.kept[g.ndim - 1];
     const double st = (double)kept_modes;                 // stored modes
     const double hist = (d.order == 2 && !lean) ? 2.0 : 0.0;   // read + write F_{n-1} (lean: one carry array)
+    if (d.ndim == 1) {
+        // a line: state (and F_{n-1}) in and out once per launch, given per step
+        // of a one-step launch
+        out[0] = (2.0 + hist) * st * e;
+        return;
+    }
     if (d.nl == NL_NONE) {
         out[0] = 2.0 * st * e;
         return;
@@ -275,6 +285,10 @@ template <typename T>
 static setd_status launch_pass_t(const Plan& p, int i, const Item* items_dev, int nitems, int sub, hipStream_t s)
 {
     const Geo& g = p.g;
+    if (g.ndim == 1) {
+        SETD_HIP((launch_line1d<T>(g, items_dev, nitems, MODE_STEP, sub, 1, p.d.nl, s)));
+        return SETD_OK;
+    }
     if (p.d.nl == NL_NONE) {
         SETD_HIP((launch_linear<T>(g, items_dev, nitems, sub, LIN_STEP, 0, s)));
         return SETD_OK;
@@ -312,6 +326,10 @@ template <typename T>
 static setd_status launch_ic_t(const Plan& p, const Item* items_dev, int nitems, hipStream_t s)
 {
     const Geo& g = p.g;
+    if (g.ndim == 1) {
+        SETD_HIP((launch_line1d<T>(g, items_dev, nitems, MODE_IC, 0, 0, p.d.nl, s)));
+        return SETD_OK;
+    }
     SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_IC, 0, p.tune.row, 0, s)));
     if (g.ndim == 3) SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -1, 0, p.tune.ax1, s)));
     SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_IC, 0, p.tune.ax0, p.d.nl == NL_KPZ, 0, s)));
@@ -321,6 +339,7 @@ static setd_status launch_ic_t(const Plan& p, const Item* items_dev, int nitems,
 template <typename T>
 static setd_status launch_sync_t(const Plan& p, const Item* items_dev, int nitems, hipStream_t s)
 {
+    if (p.g.ndim == 1) return SETD_OK;   // a line keeps no partial transform
     SETD_HIP((launch_axis0<T>(p.g, items_dev, nitems, MODE_SYNC, 0, p.tune.ax0, p.d.nl == NL_KPZ, 0, s)));
     return SETD_OK;
 }
@@ -531,7 +550,7 @@ setd_status Plan::autotune()
     }
     const char* env = std::getenv("SETD_AUTOTUNE");
     if (env && env[0] == '0') return SETD_OK;
-    if (d.nl == NL_NONE) return SETD_OK;
+    if (d.nl == NL_NONE || d.ndim == 1) return SETD_OK;   // a line has one kernel
     const std::string key = tune_key(*this);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -628,6 +647,16 @@ setd_status Plan::autotune()
 setd_status Plan::run_steps_on(int64_t n, int split, hipStream_t s)
 {
     const Item* items_dev = reinterpret_cast<const Item*>(ws + lay.items);
+    if (g.ndim == 1) {
+        // a line steps in registers: up to 256 steps per launch
+        for (int64_t left = n; left > 0;) {
+            const int c = (int)std::min<int64_t>(left, 256);
+            if (d.precision == 32) SETD_HIP((launch_line1d<float>(g, items_dev, R, MODE_STEP, 0, c, d.nl, s)));
+            else SETD_HIP((launch_line1d<double>(g, items_dev, R, MODE_STEP, 0, c, d.nl, s)));
+            left -= c;
+        }
+        return SETD_OK;
+    }
     if (split != 2 || !aux || R < 2 || n <= 0) {
         for (int64_t i = 0; i < n; i++) {
             setd_status st = launch_step(items_dev, R, 0, s);
@@ -1025,7 +1054,7 @@ void Plan::scatter(const char* raw, double* out) const
     std::memset(out, 0, 2 * nspec * sizeof(double));
     const int last = d.ndim - 1;
     const int k1 = (d.ndim == 3) ? g.kept[1] : 1;
-    for (int i0 = 0; i0 < g.kept[0]; i0++) {
+    for (int i0 = 0; i0 < (d.ndim == 1 ? 1 : g.kept[0]); i0++) {
         const int j0 = (i0 <= g.kp[0]) ? i0 : i0 + g.n[0] - g.kept[0];
         for (int i1 = 0; i1 < k1; i1++) {
             const int j1 = (d.ndim == 3) ? ((i1 <= g.kp[1]) ? i1 : i1 + g.n[1] - g.kept[1]) : 0;
@@ -1059,7 +1088,7 @@ setd_status Plan::set_field(int r, const double* in, size_t len)
     std::vector<char> host(S * elt, 0);
     const int last = d.ndim - 1;
     const int k1 = (d.ndim == 3) ? g.kept[1] : 1;
-    for (int i0 = 0; i0 < g.kept[0]; i0++) {
+    for (int i0 = 0; i0 < (d.ndim == 1 ? 1 : g.kept[0]); i0++) {
         const int j0 = (i0 <= g.kp[0]) ? i0 : i0 + g.n[0] - g.kept[0];
         for (int i1 = 0; i1 < k1; i1++) {
             const int j1 = (d.ndim == 3) ? ((i1 <= g.kp[1]) ? i1 : i1 + g.n[1] - g.kept[1]) : 0;

@@ -1,6 +1,7 @@
 // setd_types.hpp -- plain structs shared by the host runtime and the kernels.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -19,6 +20,13 @@ struct Geo {
     int pitch;        // padded length of the stored last axis (elements)
     int nh_last;      // unpruned spectral length of the last axis (n/2+1 or n)
 };
+
+// stored rows of a realization: [kept0][kept1] lines of the last axis (3D),
+// kept0 (2D), one (a 1D line)
+inline __host__ __device__ int geo_rows(const Geo& g)
+{
+    return g.ndim == 1 ? 1 : g.kept[0] * (g.ndim == 3 ? g.kept[1] : 1);
+}
 
 // Per-realization control block in device memory.
 struct Ctrl {

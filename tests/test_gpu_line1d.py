@@ -1,0 +1,196 @@
+"""GPU parity on 1D lattices (the lines of Sec. 5's Model A/B correlation and
+KPZ scaling figures): the HIP line kernels, which keep the state in registers
+for all steps of a launch, against the FP64 oracle on the same seeded inputs.
+Bars as for the other lattices: relative L2 error 1e-10 in FP64, 2e-4 in FP32."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2511_22510_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: 1e-10, 32: 2e-4}
+
+
+def _setd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_22510_amd import setd
+    return setd
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run_pair(p, steps, every):
+    S = _setd()
+    say("line case", p["nl"], p["n"], "prec", p["precision"], "R", p["realizations"], "order", p["order"],
+        "dealias", p["dealias"], "steps", steps)
+    g = S.Plan(p)
+    o = O.Sim(p)
+    R = p["realizations"]
+    worst, done = 0.0, 0
+    while True:
+        num = sum(np.linalg.norm(g.get(r) - o.get(r)) ** 2 for r in range(R))
+        den = sum(np.linalg.norm(o.get(r)) ** 2 for r in range(R))
+        worst = max(worst, float(np.sqrt(num / max(den, 1e-300))))
+        if done >= steps:
+            break
+        k = min(every, steps - done)
+        g.step(k)
+        o.step(k)
+        done += k
+    g.close()
+    return worst
+
+
+CASES = [
+    W.model_a([256], precision=64, order=1, realizations=3, dx=0.25),
+    W.model_a([256], precision=32, order=2, realizations=4, dx=0.25),
+    W.model_a([64], precision=64, order=2, realizations=5, dealias=0),
+    W.model_b([256], precision=64, order=2, realizations=2, dx=0.25, ic_sigma=0.3),
+    W.model_b([128], precision=32, order=1, realizations=3, dealias=0),
+    W.kpz([1024], precision=64, order=2, realizations=3, dx=0.5, lam=50.0, D=0.01, h=2e-3, ic_kind=1, ic_sigma=0.2),
+    W.kpz([1024], precision=32, order=2, realizations=2, dx=0.5, lam=50.0, D=0.01, h=2e-3),
+    W.kpz([32], precision=64, order=1, realizations=1, dealias=0, ic_kind=1, ic_sigma=0.3),
+    W.cgl([64], precision=64, order=2, realizations=3),
+    W.cgl([512], precision=32, order=1, realizations=2, dealias=0),
+    W.model_a([8], precision=64, order=2, realizations=3),
+    W.model_a([8], precision=32, order=1, realizations=2, dealias=0),
+    W.cgl([8], precision=64, order=2, realizations=1, dealias=0),
+    W.model_a([128], precision=64, nl="none", u=0.0, r=0.5, realizations=3),
+    W.cgl([128], precision=64, nl="none", realizations=2),
+]
+
+
+@pytest.mark.parametrize("p", CASES, ids=lambda p: "%s-%d-f%d-o%d-d%d-R%d" % (
+    p["nl"], p["n"][0], p["precision"], p["order"], p["dealias"], p["realizations"]))
+def test_line_trajectory_parity(p):
+    err = run_pair(p, steps=120, every=40)
+    say("max rel err", err)
+    assert err <= TOL[p["precision"]]
+
+
+@pytest.mark.parametrize("p", [W.model_a([256], precision=32, order=2, realizations=3),
+                               W.kpz([1024], precision=64, order=2, realizations=2, ic_kind=1, ic_sigma=0.2),
+                               W.cgl([64], precision=32, order=2, realizations=2)])
+def test_fused_launches_equal_single_steps(p):
+    """Many steps in one launch give the same bits as one launch per step."""
+    S = _setd()
+    a, b = S.Plan(p), S.Plan(p)
+    a.step(300)
+    for _ in range(300):
+        b.step(1)
+    for r in range(p["realizations"]):
+        assert np.array_equal(a.get(r), b.get(r))
+        assert np.array_equal(a.history(r), b.history(r))
+    a.close()
+    b.close()
+
+
+def test_line_history_set_field_and_restart():
+    """F_{n-1} read back, a state set mid-run (fresh history) and the step
+    index moved, against the oracle."""
+    S = _setd()
+    p = W.model_a([128], precision=64, order=2, realizations=3, ic_kind=1, ic_sigma=0.2, history_readback=1)
+    g = S.Plan(p)
+    o = O.Sim(p)
+    g.step(7)
+    o.step(7)
+    for r in range(3):
+        assert relerr(g.history(r), o.get(r, which=1)) <= 1e-10
+    x = W.random_spectrum(p, 5, 3.0)
+    g.set(1, x)
+    o.set(1, x)
+    g.step(9)
+    o.step(9)
+    for r in range(3):
+        assert relerr(g.get(r), o.get(r)) <= 1e-10
+    g.close()
+
+
+@pytest.mark.parametrize("p", [W.model_a([256], precision=64, order=2, realizations=4, dx=0.25),
+                               W.kpz([256], precision=32, order=2, realizations=3, ic_kind=1, ic_sigma=0.3),
+                               W.cgl([128], precision=64, order=1, realizations=2)])
+def test_line_observables_match_oracle(p):
+    """S(k), the width, the box widths, the two-time correlation and the linear
+    response on a line."""
+    S = _setd()
+    g = S.Plan(p)
+    o = O.Sim(p)
+    tol = 1e-10 if p["precision"] == 64 else 2e-4
+    g.step(20)
+    o.step(20)
+    nb = g.nbins
+    a, b = g.observe(S.OBS_SK), o.observe(O.OBS_SK)
+    assert np.array_equal(a[nb:2 * nb], b[nb:2 * nb])
+    assert relerr(a[:nb], b[:nb]) <= tol
+    assert abs(g.observe(S.OBS_WIDTH)[0] - o.observe(O.OBS_WIDTH)[0]) <= tol * o.observe(O.OBS_WIDTH)[0]
+    wa, wb = g.box_width(), o.observe(O.OBS_BOXWIDTH)
+    assert float(np.max(np.abs(wa - wb) / wb)) <= tol
+    g.observe(S.OBS_SNAPSHOT)
+    o.observe(O.OBS_SNAPSHOT)
+    assert g.observe(S.OBS_KICK)[0] == o.observe(O.OBS_KICK)[0] == 20
+    g.step(5)
+    o.step(5)
+    a, b = g.observe(S.OBS_TWOTIME), o.observe(O.OBS_TWOTIME)
+    assert np.array_equal(a[2 * nb:], b[2 * nb:])
+    assert float(np.max(np.abs(a[:2 * nb] - b[:2 * nb]))) <= tol * max(1.0, float(np.max(np.abs(b[:2 * nb]))))
+    a, b = g.observe(S.OBS_RESPONSE), o.observe(O.OBS_RESPONSE)
+    assert np.array_equal(a[2 * nb:], b[2 * nb:])
+    assert float(np.max(np.abs(a[:2 * nb] - b[:2 * nb]))) <= tol * max(1.0, float(np.max(np.abs(b[:2 * nb]))))
+    g.close()
+
+
+def test_line_spectrum_window_matches_oracle():
+    S = _setd()
+    p = W.model_a([128], precision=64, order=2, realizations=3)
+    M = 16
+    g = S.Plan(dict(p, series_len=M))
+    o = O.Sim(p)
+    g.step(4)
+    o.step(4)
+    assert g.observe(S.OBS_SERIES_START)[0] == 4
+    o.series_start(M)
+    g.step(M - 1)
+    o.step(M - 1)
+    a, b = g.spectrum(), o.spectrum()
+    assert np.array_equal(a[3], b[3])
+    for x, y in zip(a[:3], b[:3]):
+        assert float(np.max(np.abs(x - y))) <= 1e-10 * max(float(np.max(np.abs(y))), 1e-300)
+    g.close()
+
+
+def test_line_stationary_spectrum_of_the_paper_figure():
+    """Sec. 5, Model A/B on a line (u = 0, N = 256, L = 64, D = 0.1, h = 0.01):
+    the equal-time correlation relaxes to D/(r + k^2); from phi = 0 after
+    t = n h the exact mode variance is (N^2/L) D (1 - e^{2ct})/(-c)."""
+    S = _setd()
+    r, D, h, R = 1.0, 0.1, 0.01, 512
+    p = W.model_a([256], r=r, u=0.0, T=D, h=h, dx=0.25, order=1, ic_kind=0, realizations=R,
+                  precision=32, seed=3)
+    g = S.Plan(p)
+    nsteps = 400
+    g.step(nsteps)
+    nb = g.nbins
+    sk = g.observe(S.OBS_SK)[:nb]
+    L, N = 64.0, 256
+    k = 2 * np.pi / L * np.arange(nb)
+    c = -(r + k**2)
+    K = (N - 1) // 3
+    want = D * (1 - np.exp(2 * c * nsteps * h)) / (-c)
+    # shells 1..K hold the modes +-a: 2 R samples of |phi_a|^2 each
+    z = (sk[1:K + 1] / want[1:K + 1] - 1) / np.sqrt(1.0 / R)
+    say("line S(k) z max", float(np.max(np.abs(z))))
+    assert np.max(np.abs(z)) < 5.0
+    g.close()
