@@ -191,8 +191,12 @@ def serving_run(setd, W, n_jobs, seed, audit=True):
     return out
 
 
+LINE_STEPS_PER_LAUNCH = 256
+
+
 def other_workloads(setd, W, steps):
-    """Step rate of the KPZ (1024^2 x 16) and CGL (256^3 x 4) workloads."""
+    """Step rate of the KPZ (1024^2 x 16) and CGL (256^3 x 4) workloads and of
+    the 1D lines of the paper's Model A and KPZ figures."""
     res = []
     for name, cfg in (("KPZ 1024x1024, SETD2, FP32, 16 realizations", W.CONFIG_KPZ),
                       ("CGL 256x256x256, SETD2, complex64, 4 realizations", W.CONFIG_CGL)):
@@ -202,6 +206,17 @@ def other_workloads(setd, W, steps):
         res.append({"workload": name, "site_updates_per_s": float(info.site_updates_per_step) / sec,
                     "ms_per_step": 1e3 * sec, "alg_bytes_per_step": float(info.alg_bytes_per_step),
                     "step_frac": float(info.alg_bytes_per_step / sec / 1e9 / PEAK_HBM_GBS), "ok": bool(ok)})
+    # 1D lines: up to 256 steps per launch with the state in registers, so the
+    # state crosses HBM once per launch and the transforms and noise bound it
+    for name, cfg in (("Model A line N=256 (L=64), SETD1, FP32, 16384 realizations", W.LINE_MODEL_A),
+                      ("KPZ line N=1024 (L=512), SETD2, FP32, 4096 realizations", W.LINE_KPZ)):
+        p = W.problem(cfg)
+        k = 8 * LINE_STEPS_PER_LAUNCH
+        el, _, info, ok, _ = time_plan(setd, p, k, LINE_STEPS_PER_LAUNCH, profile=False)
+        sec = el / k
+        res.append({"workload": name, "site_updates_per_s": float(info.site_updates_per_step) / sec,
+                    "ms_per_step": 1e3 * sec, "steps_per_launch": LINE_STEPS_PER_LAUNCH,
+                    "hbm_bytes_per_launch": float(info.alg_bytes_per_step), "ok": bool(ok)})
     return res
 
 

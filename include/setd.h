@@ -56,7 +56,7 @@ typedef enum {
     SETD_NL_PHI3 = 0,         /* Model A, Eq. modelA:   F = -u FFT[phi^3]             */
     SETD_NL_PHI3_CONS = 1,    /* Model B, Eq. modelB:   F = -u k^2 FFT[phi^3]         */
     SETD_NL_KPZ = 2,          /* KPZ, Eq. kpz_fourier:  F = lambda/2 FFT[|grad h|^2],
-                                 gradient taken spectrally (2D real fields only)     */
+                                 gradient taken spectrally (1D and 2D real fields)   */
     SETD_NL_CGL = 3,          /* CGL, Eq. cgle:         F = -(1 + i beta) FFT[|A|^2 A] */
     SETD_NL_NONE = 4          /* linear theory, F = 0                                */
 } setd_nonlin;
@@ -128,7 +128,8 @@ typedef enum {
  * CGL:     c0 = 1, c2 = -(1 + i alpha), complex_field 1, nl CGL, nl_par[0] = beta.
  */
 typedef struct {
-    int ndim;                 /* 2 or 3                                            */
+    int ndim;                 /* 1, 2 or 3 (a 1D line steps up to 256 steps per
+                                 kernel launch with its state in registers)       */
     int n[3];                 /* points per axis, powers of two in [8, 1024]       */
     double dx;                /* lattice spacing (> 0)                             */
     int complex_field;        /* 0: real order parameter (R2C); 1: complex (C2C)   */
@@ -199,11 +200,11 @@ typedef int64_t setd_job;
 
 /*
  * Validate *desc and prepare a plan (host work only, no device memory).
- * Errors: SETD_E_INVAL for ndim not in {2,3}, n[i] not a power of two in
+ * Errors: SETD_E_INVAL for ndim not in {1,2,3}, n[i] not a power of two in
  * [8, 1024], order not in {1,2}, h <= 0, dx <= 0, noise_D < 0, noise_kpow not
  * in {0,2}, precision not in {32,64}, realizations < 1, a complex c(k) on a
- * real field, ic_kind not in {0,1}; SETD_E_UNSUPPORTED for KPZ outside 2D real
- * fields, PHI3/PHI3_CONS on complex fields or CGL on real fields.
+ * real field, ic_kind not in {0,1}; SETD_E_UNSUPPORTED for KPZ outside 1D/2D
+ * real fields, PHI3/PHI3_CONS on complex fields or CGL on real fields.
  * *out is owned by the caller and released with setd_plan_destroy.
  */
 setd_status setd_plan_create(const setd_desc* desc, setd_plan** out);

@@ -67,6 +67,13 @@ CONFIG_A = dict(model_a([64, 64], order=1, precision=64, realizations=1, seed=0)
 CONFIG_B = dict(model_b([512, 512], order=2, precision=32, realizations=64, seed=1), steps=10000)
 CONFIG_KPZ = dict(kpz([1024, 1024], order=2, precision=32, realizations=16, seed=2), steps=50000)
 CONFIG_CGL = dict(cgl([256, 256, 256], order=2, precision=32, realizations=4, seed=3), steps=20000)
+# the lines of Sec. 5's 1D figures, batched over realizations: Model A
+# (u = 0, N = 256, L = 64, D = 0.1, h = 0.01, r = 1) and KPZ (N = 1024, L = 512,
+# lambda = 50, nu = 1, D = 0.01, h = 2e-3)
+LINE_MODEL_A = dict(model_a([256], r=1.0, u=0.0, T=0.1, dx=0.25, h=0.01, order=1, precision=32,
+                            realizations=16384, ic_kind=0, seed=4), steps=100000)
+LINE_KPZ = dict(kpz([1024], nu=1.0, lam=50.0, D=0.01, dx=0.5, h=2e-3, order=2, precision=32,
+                    realizations=4096, ic_kind=0, seed=5), steps=100000)
 
 
 def problem(cfg, **over):
