@@ -1448,7 +1448,9 @@ __device__ __forceinline__ void line1d_tw(Line1dTw<T, N, KIND>& tw, int t, const
     else tw = base;
 }
 
-// Real field, realizations 2l and 2l + 1 of line l.  Thread t keeps the stored
+// Real field, realizations 2l and 2l + 1 of line l.  Rounding in the packed
+// transforms couples the two channels, so a realization's bits depend on its
+// partner: the server keeps every job's realizations on lines of their own.  Thread t keeps the stored
 // modes a = t + q N/8 (q < 4, and a = N/2 in slot 4 of thread 0) of both
 // realizations.  A step: pack z = A + i B from the two half spectra (the bins
 // above N/2 are conj(A_{N-k}) + i conj(B_{N-k}), read back through LDS),
@@ -1538,11 +1540,13 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
         pa[q] = pb[q] = fa[q] = fb[q] = czero<T>();
         if (!stored(q)) continue;
         const int m = mode_of(q);
-        if (va) {
+        // a realization that does not step in this launch is no partner: its
+        // channel stays zero, as for the missing partner of an odd count
+        if (acta) {
             pa[q] = phia0[m];
             if (o2 && hpa) fa[q] = preva[m];
         }
-        if (vb) {
+        if (actb) {
             pb[q] = phib0[m];
             if (o2 && hpb) fb[q] = prevb[m];
         }

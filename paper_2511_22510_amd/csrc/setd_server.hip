@@ -238,10 +238,18 @@ setd_status setd_server::tick(std::vector<Job*>& act, int* steps_taken)
         maxk = std::max(maxk, j->steps_tick);
         classes[class_key(*j->plan)].push_back(j);
     }
-    // item tables, one contiguous run per class
+    // item tables, one contiguous run per class.  A real 1D line pairs
+    // realizations 2l and 2l + 1 in one transform, whose rounding couples
+    // them: a job with an odd count gets a partner that never steps (a copy
+    // of its last item with no steps), so that every job's realizations pair
+    // as in a solo run.
+    auto padded = [](const Job* j) {
+        const Plan& p = *j->plan;
+        return p.g.ndim == 1 && !p.g.cplx && (p.R % 2) == 1;
+    };
     size_t nitems = 0;
     for (auto& c : classes)
-        for (Job* j : c.second) nitems += (size_t)j->plan->R;
+        for (Job* j : c.second) nitems += (size_t)j->plan->R + (padded(j) ? 1 : 0);
     if (nitems > items_cap) return fail(SETD_E_NOMEM, "item table overflow");
     size_t pos = 0;
     struct Launch { Plan* rep; size_t first; int n; };
@@ -252,6 +260,11 @@ setd_status setd_server::tick(std::vector<Job*>& act, int* steps_taken)
             for (int r = 0; r < j->plan->R; r++) {
                 Item it = j->plan->items[r];
                 it.steps = j->steps_tick;
+                items_host[pos++] = it;
+            }
+            if (padded(j)) {
+                Item it = j->plan->items[j->plan->R - 1];
+                it.steps = 0;
                 items_host[pos++] = it;
             }
         }

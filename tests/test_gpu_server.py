@@ -40,6 +40,12 @@ MIX = [
     (W.model_a([64, 32], precision=64, order=1, realizations=1, seed=106), 33),
     (W.model_b([64, 64], precision=32, realizations=2, seed=107), 50),
     (W.cgl([32, 32], precision=32, realizations=1, seed=108), 18),
+    # 1D lines: two jobs of one launch class share a line pair across the job
+    # boundary (3 + 1 realizations)
+    (W.model_a([256], precision=32, realizations=3, seed=109, dx=0.25), 27),
+    (W.model_a([256], precision=32, realizations=1, seed=110, dx=0.25), 19),
+    (W.kpz([128], precision=32, order=2, realizations=2, seed=111, ic_kind=1, ic_sigma=0.2), 21),
+    (W.cgl([64], precision=64, realizations=1, seed=112), 15),
 ]
 
 
