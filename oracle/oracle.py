@@ -32,7 +32,7 @@ class _Desc(ctypes.Structure):
         ("noise_D", ctypes.c_double), ("noise_kpow", ctypes.c_int),
         ("h", ctypes.c_double), ("order", ctypes.c_int),
         ("realizations", ctypes.c_int), ("seed", ctypes.c_uint64), ("dealias", ctypes.c_int),
-        ("ic_kind", ctypes.c_int), ("ic_sigma", ctypes.c_double),
+        ("ic_kind", ctypes.c_int), ("ic_sigma", ctypes.c_double), ("noise_space", ctypes.c_int),
     ]
 
 
@@ -77,6 +77,7 @@ def lib():
         L.orc_step.argtypes = [vp, ctypes.c_int64]
         L.orc_step_xi.argtypes = [vp, dp]
         L.orc_noise_xi.argtypes = [vp, ctypes.c_int64, dp]
+        L.orc_site_noise.argtypes = [vp, ctypes.c_int64, ctypes.c_uint32, dp]
         L.orc_get.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp]
         L.orc_set.argtypes = [vp, ctypes.c_int, dp]
         L.orc_set_step.argtypes = [vp, ctypes.c_int64]
@@ -209,6 +210,7 @@ def make_desc(p):
     d.dealias = int(p.get("dealias", 1))
     d.ic_kind = int(p.get("ic_kind", 0))
     d.ic_sigma = float(p.get("ic_sigma", 0.0))
+    d.noise_space = int(p.get("noise_space", 0))
     return d
 
 
@@ -266,6 +268,15 @@ class Sim:
         out = np.zeros((self.R,) + self.spec_shape, dtype=np.complex128)
         lib().orc_noise_xi(self._h, int(n), _dptr(out.view(np.float64)))
         return out
+
+    def site_noise(self, n, r):
+        """The real-space draws eta_x of step n, realization r (noise_space 1),
+        in lattice shape (complex for a complex field)."""
+        cplx = bool(self.p.get("complex_field", 0))
+        shape = tuple(int(v) for v in self.p["n"])
+        out = np.zeros(int(np.prod(shape)) * (2 if cplx else 1))
+        lib().orc_site_noise(self._h, int(n), int(r), _dptr(out))
+        return (out.view(np.complex128) if cplx else out).reshape(shape)
 
     def noise_slot(self, e):
         """(P, half, kind) of stored element e: the Philox slot its noise is

@@ -75,6 +75,7 @@ typedef struct {
     int dealias;           /* 0 none, 1 the 2/3 rule                        */
     int ic_kind;           /* 0 zero, 1 Gaussian per site                   */
     double ic_sigma;
+    int noise_space;       /* 0 Fourier-space draws (App. B), 1 real space  */
 } orc_desc;
 
 enum { NL_PHI3 = 0, NL_PHI3_CONS = 1, NL_KPZ = 2, NL_CGL = 3, NL_NONE = 4 };
@@ -350,6 +351,8 @@ typedef struct {
     int64_t kick_step; int have_kick;   /* reference step of the response estimator */
     cplx* series; int series_len, series_pos; int64_t series_step0;   /* recorded phi_a(m) */
     double* acc; double acc_count; int nbins;
+    /* real-space noise: eta_a of step rs_n, realization rs_r */
+    cplx* rs_eta; int64_t rs_n; int64_t rs_r;
     /* scratch */
     cplx* work; cplx* work2; double* rwork; double* rwork2; cplx* F;
 } orc_sim;
@@ -535,7 +538,7 @@ void orc_destroy(orc_sim* s)
     free(s->phi); free(s->fprev); free(s->k2); free(s->kidx); free(s->mask);
     free(s->E); free(s->wa); free(s->wb); free(s->G); free(s->pref);
     free(s->work); free(s->work2); free(s->rwork); free(s->rwork2); free(s->F);
-    free(s->snap); free(s->acc); free(s->have_prev); free(s->series);
+    free(s->snap); free(s->acc); free(s->have_prev); free(s->series); free(s->rs_eta);
     free(s);
 }
 
@@ -643,13 +646,88 @@ static cplx noise_eta(const orc_sim* s, size_t e, int64_t n, uint32_t r)
     return (z1 + I * z2) * rs2;
 }
 
+/* The alternative of Sec. 4 step 2: eta drawn in real space and transformed
+   (one more FFT per step; App. B counts one real deviate per site).  Site x
+   (linear index over the lattice) takes Box-Muller normals of Philox blocks
+   with counter (P, n, r, 3), 32-bit words as for the Fourier noise.  A real
+   field: Q = nreal/4 blocks, site x takes normal (x div Q) mod 2 of half
+   (x div Q) div 2 of block x mod Q, so eta_x ~ N(0, 1).  A complex field:
+   nreal/2 blocks, site x takes (z1 + i z2)/sqrt2 of half x div (nreal/2) of
+   block x mod (nreal/2).  Then eta_a = DFT[eta_x]_a / sqrt(nreal), which has
+   the statistics of App. B (unit variance, Hermitian for a real field). */
+static void noise_block_normals(uint64_t seed, uint32_t P, uint32_t n, uint32_t r, uint32_t tag, int half,
+                                double* z1, double* z2)
+{
+    uint32_t ctr[4] = { P, n, r, tag };
+    uint32_t key[2] = { (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
+    uint32_t x[4];
+    orc_philox(ctr, key, x);
+    double u1 = ((double)x[half ? 2 : 0] + 0.5) * 0x1p-32;
+    double u2 = ((double)x[half ? 3 : 1] + 0.5) * 0x1p-32;
+    double rad = sqrt(-2.0 * log(u1));
+    *z1 = rad * cos(2.0 * M_PI * u2);
+    *z2 = rad * sin(2.0 * M_PI * u2);
+}
+
+int orc_site_noise(const orc_sim* s, int64_t n, uint32_t r, double* out)
+{
+    const orc_desc* d = &s->d;
+    const size_t nr = s->nreal;
+    for (size_t x = 0; x < nr; x++) {
+        double z1, z2;
+        if (d->complex_field) {
+            const size_t Q = nr / 2;
+            noise_block_normals(d->seed, (uint32_t)(x % Q), (uint32_t)n, r, 3u, (int)(x / Q), &z1, &z2);
+            out[2 * x] = z1 * 0.70710678118654752440;
+            out[2 * x + 1] = z2 * 0.70710678118654752440;
+        } else {
+            const size_t Q = nr / 4, slot = x / Q;
+            noise_block_normals(d->seed, (uint32_t)(x % Q), (uint32_t)n, r, 3u, (int)(slot / 2), &z1, &z2);
+            out[x] = (slot % 2) ? z2 : z1;
+        }
+    }
+    return 0;
+}
+
+static cplx noise_eta_rs(orc_sim* s, size_t e, int64_t n, uint32_t r)
+{
+    if (!s->mask[e]) return 0;
+    if (!s->rs_eta || s->rs_n != n || s->rs_r != (int64_t)r) {
+        const orc_desc* d = &s->d;
+        const size_t nr = s->nreal;
+        if (!s->rs_eta) s->rs_eta = (cplx*)malloc(sizeof(cplx) * s->nspec);
+        double* site = (double*)malloc(sizeof(double) * 2 * nr);
+        orc_site_noise(s, n, r, site);
+        const double sc = 1.0 / sqrt((double)nr);
+        if (d->complex_field) {
+            for (size_t x = 0; x < nr; x++) s->work2[x] = site[2 * x] + I * site[2 * x + 1];
+            fftn(s->work2, d->ndim, d->n, -1);
+            for (size_t e2 = 0; e2 < s->nspec; e2++) s->rs_eta[e2] = sc * s->work2[e2];
+        } else {
+            for (size_t x = 0; x < nr; x++) s->rwork[x] = site[x];
+            rfftn(s->rwork, s->rs_eta, d->ndim, d->n, s->work);
+            for (size_t e2 = 0; e2 < s->nspec; e2++) s->rs_eta[e2] *= sc;
+            hermitian_planes(s, s->rs_eta);
+        }
+        free(site);
+        s->rs_n = n;
+        s->rs_r = (int64_t)r;
+    }
+    return s->rs_eta[e];
+}
+
+static cplx step_eta(orc_sim* s, size_t e, int64_t n, uint32_t r)
+{
+    return s->d.noise_space ? noise_eta_rs(s, e, n, r) : noise_eta(s, e, n, r);
+}
+
 /* the additive noise term G_a eta_a of step n for all realizations */
 int orc_noise_xi(orc_sim* s, int64_t n, double* xi_out)
 {
     cplx* xi = (cplx*)xi_out;
     for (int rr = 0; rr < s->R; rr++)
         for (size_t e = 0; e < s->nspec; e++)
-            xi[(size_t)rr * s->nspec + e] = s->G[e] * noise_eta(s, e, n, (uint32_t)(s->r_first + rr));
+            xi[(size_t)rr * s->nspec + e] = s->G[e] * step_eta(s, e, n, (uint32_t)(s->r_first + rr));
     return 0;
 }
 
@@ -680,7 +758,7 @@ static int step_once(orc_sim* s, const cplx* xi_all)
         if (xi_all) memcpy(xi, xi_all + (size_t)rr * s->nspec, sizeof(cplx) * s->nspec);
         else
             for (size_t e = 0; e < s->nspec; e++)
-                xi[e] = s->G[e] * noise_eta(s, e, s->step, (uint32_t)(s->r_first + rr));
+                xi[e] = s->G[e] * step_eta(s, e, s->step, (uint32_t)(s->r_first + rr));
         update(s, rr, xi);
         s->have_prev[rr] = 1;
     }
@@ -738,7 +816,8 @@ int orc_spectrum(orc_sim* s, double* out, size_t cap, size_t* len)
 {
     const orc_desc* d = &s->d;
     const int nb = s->nbins, M = s->series_len;
-    if (!s->series || s->series_pos < M || cap < (size_t)3 * nb * M + nb) return -1;
+    /* chi regenerates the kicks' Fourier-space draws */
+    if (!s->series || s->series_pos < M || s->d.noise_space || cap < (size_t)3 * nb * M + nb) return -1;
     double vol = 1.0;
     for (int i = 0; i < d->ndim; i++) vol *= (d->n[i] * d->dx) / ((double)d->n[i] * (double)d->n[i]);
     memset(out, 0, sizeof(double) * ((size_t)3 * nb * M + nb));
@@ -1028,7 +1107,8 @@ int orc_observe(orc_sim* s, int kind, double* out, size_t cap, size_t* len)
            response of phi_a(n) to an additive kick in that step.  Per shell:
            mean over realizations and modes with G_a > 0 of
            phi_a(n) conj eta_a(n') / G_a, interior modes of a real field as 2 Re. */
-        if (!s->have_kick || cap < (size_t)3 * nb) return -1;
+        /* the estimator regenerates the kick's Fourier-space draws */
+        if (!s->have_kick || s->d.noise_space || cap < (size_t)3 * nb) return -1;
         double* re = (double*)calloc((size_t)nb, sizeof(double));
         double* im = (double*)calloc((size_t)nb, sizeof(double));
         double* cnt = (double*)calloc((size_t)nb, sizeof(double));

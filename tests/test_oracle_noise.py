@@ -199,3 +199,96 @@ def test_initial_condition_is_per_site_philox():
     A = O.fftn(sc.get(0), inverse=True).reshape(-1)
     z1, z2 = O.normal_pair(9, 13, 0, 0, 1)
     assert A[13] == pytest.approx(0.01 * complex(z1, z2), abs=1e-16)
+
+
+def _bm32(words, half):
+    """Box-Muller of 32-bit words (x0, x1) or (x2, x3) of a Philox block."""
+    a, b = (words[2], words[3]) if half else (words[0], words[1])
+    u1, u2 = (a + 0.5) * 2.0 ** -32, (b + 0.5) * 2.0 ** -32
+    rad = np.sqrt(-2 * np.log(u1))
+    return rad * np.cos(2 * np.pi * u2), rad * np.sin(2 * np.pi * u2)
+
+
+@pytest.mark.parametrize("kind,shape", [("real", (64,)), ("real", (16, 8)), ("cplx", (32,)), ("cplx", (8, 16)),
+                                        ("real", (8, 4, 8))])
+def test_real_space_noise_is_the_transform_of_site_draws(kind, shape):
+    """Sec. 4 step 2, the real-space alternative: site x draws from the Philox
+    block (x mod Q, n, r, 3) (real: Q = nreal/4, normal (x div Q) mod 2 of half
+    (x div Q) div 2; complex: Q = nreal/2, (z1 + i z2)/sqrt2 of half x div Q),
+    and eta_a is the DFT of the draws over sqrt(nreal) (numpy's FFT here)."""
+    seed, n, r = 13, 6, 2
+    if kind == "real":
+        p = W.model_a(list(shape), dealias=0, ic_kind=0, T=1.0, r=1.0, seed=seed, realizations=3, noise_space=1)
+    else:
+        p = W.cgl(list(shape), dealias=0, ic_kind=0, T=1.0, seed=seed, realizations=3, noise_space=1)
+    s = O.Sim(p)
+    site = s.site_noise(n, r)
+    nr = int(np.prod(shape))
+    flat = site.reshape(-1)
+    for x in list(range(0, nr, max(1, nr // 13))) + [nr - 1]:
+        if kind == "real":
+            Q = nr // 4
+            z = _bm32(O.philox([x % Q, n, r, 3], [seed, 0]), (x // Q) // 2)
+            assert flat[x] == pytest.approx(z[(x // Q) % 2], abs=1e-13)
+        else:
+            Q = nr // 2
+            z1, z2 = _bm32(O.philox([x % Q, n, r, 3], [seed, 0]), x // Q)
+            assert flat[x] == pytest.approx((z1 + 1j * z2) / np.sqrt(2), abs=1e-13)
+    G = s.coef(3)
+    eta = s.noise_xi(n)[r] / G
+    want = (np.fft.rfftn(site) if kind == "real" else np.fft.fftn(site)) / np.sqrt(nr)
+    assert np.max(np.abs(eta - want)) < 1e-12
+    if kind == "real":
+        # exactly Hermitian on the a_last = 0 plane, real self-conjugate modes
+        for idx in np.ndindex(eta.shape):
+            if idx[-1] != 0:
+                continue
+            partner = tuple((-idx[i]) % shape[i] for i in range(len(shape) - 1)) + (0,)
+            assert eta[partner] == np.conj(eta[idx])
+
+
+def test_real_space_noise_moments():
+    N, R = 256, 4
+    p = W.model_a([N], dealias=0, ic_kind=0, T=1.0, r=1.0, seed=3, realizations=R, noise_space=1)
+    s = O.Sim(p)
+    x = np.concatenate([s.site_noise(n, r) for n in range(30) for r in range(R)])
+    assert abs(x.mean()) < 5 / np.sqrt(x.size)
+    assert abs(x.var() - 1) < 5 * np.sqrt(2.0 / x.size)
+    assert abs(np.mean(x[1:] * x[:-1])) < 5 / np.sqrt(x.size)
+    pc = W.cgl([64], dealias=0, ic_kind=0, T=1.0, seed=3, realizations=1, noise_space=1)
+    sc = O.Sim(pc)
+    z = np.concatenate([sc.site_noise(n, 0) for n in range(100)])
+    assert abs(np.mean(np.abs(z) ** 2) - 1) < 5 * np.sqrt(1.0 / z.size)
+    assert abs(np.mean(z ** 2)) < 5 * np.sqrt(1.0 / z.size)
+
+
+@pytest.mark.parametrize("model", ["A", "B"])
+def test_linear_theory_variance_with_real_space_noise(model):
+    """The exact OU variance (N^2/L)^d D_a (e^{2ct} - 1)/c of every mode holds
+    with noise drawn in real space, as with App. B's Fourier draws."""
+    r, T, h, N, dx, R = 0.7, 0.3, 0.25, 64, 1.3, 300
+    mk = W.model_a if model == "A" else W.model_b
+    p = mk([N], r=r, u=0.0, T=T, nl="none", h=h, order=1, ic_kind=0, realizations=R, dealias=0, seed=17,
+           dx=dx, noise_space=1)
+    s = O.Sim(p)
+    s.step(6)
+    phi = s.get_all()
+    k2 = s.coef(4)
+    c = -(r + k2) if model == "A" else -k2 * (r + k2)
+    D = T if model == "A" else T * k2
+    lat = N * N / (N * dx)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        var = lat * np.where(c != 0, D * np.expm1(2 * c * 6 * h) / c, 2 * D * 6 * h)
+    emp = np.mean(np.abs(phi) ** 2, axis=0)
+    sel = var > 0
+    z = (emp[sel] / var[sel] - 1) / np.sqrt(2.0 / R)
+    assert np.max(np.abs(z)) < 4.8, z
+
+
+def test_real_space_noise_has_no_kick_estimators():
+    p = W.model_a([32], dealias=0, ic_kind=0, realizations=2, noise_space=1)
+    s = O.Sim(p)
+    s.observe(O.OBS_KICK)
+    s.step(1)
+    with pytest.raises(Exception):
+        s.observe(O.OBS_RESPONSE)
