@@ -164,6 +164,13 @@ typedef struct {
                                  the workspace holds a window of M samples of
                                  the stored spectrum per realization for
                                  SETD_OBS_SERIES_START / SETD_OBS_SPECTRUM      */
+    int noise_space;          /* 0 (default): eta_a drawn in Fourier space (App. B);
+                                 1: eta drawn per site in real space and
+                                 transformed, eta_a = DFT[eta_x]_a / sqrt(prod n)
+                                 (Sec. 4 step 2's alternative, one more transform
+                                 per step; 1D lines only, SETD_E_UNSUPPORTED
+                                 otherwise).  The kick estimators
+                                 (SETD_OBS_KICK / RESPONSE / SPECTRUM) need 0.  */
 } setd_desc;
 
 /* Derived sizes of a plan (filled by setd_plan_info). */

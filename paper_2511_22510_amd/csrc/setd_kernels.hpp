@@ -1459,7 +1459,7 @@ __device__ __forceinline__ void line1d_tw(Line1dTw<T, N, KIND>& tw, int t, const
 // per realization with its own noise, table and step.  KIND 0: phi^3 (Model A,
 // and Model B with its k^2 in the prefactor), 1: KPZ ((lambda/2) h'^2 from the
 // line of h + i h' per realization pair), 2: no nonlinearity.
-template <typename T, int N, int PAD, bool DA, int KIND>
+template <typename T, int N, int PAD, bool DA, int KIND, bool RS>
 __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1557,6 +1557,39 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
     }
     const T dka = (T)ia.dk[0], dkb = (T)ib.dk[0];
     const cx<T> pra = nl_pref<T>(ia, T(0)), prb = nl_pref<T>(ib, T(0));
+    // real-space noise of step s: site x = t + qM of both realizations from
+    // Philox blocks (x mod N/4, n, r, 3): block t + hM gives sites q = h,
+    // h + 2 (half 0) and h + 4, h + 6 (half 1)
+    auto site_noise = [&](cx<T> (&e)[8], int s) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) e[q] = czero<T>();
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const uint32_t P = (uint32_t)(t + h * M);
+            uint32_t x[4];
+            T z1, z2, z3, z4;
+            if (acta) {
+                philox_block(ia.seed, P, (uint32_t)(stepa + s), ia.r, 3u, x);
+                box_muller32(x[0], x[1], z1, z2);
+                box_muller32(x[2], x[3], z3, z4);
+                e[h].x = z1;
+                e[h + 2].x = z2;
+                e[h + 4].x = z3;
+                e[h + 6].x = z4;
+            }
+            if (actb) {
+                philox_block(ib.seed, P, (uint32_t)(stepb + s), ib.r, 3u, x);
+                box_muller32(x[0], x[1], z1, z2);
+                box_muller32(x[2], x[3], z3, z4);
+                e[h].y = z1;
+                e[h + 2].y = z2;
+                e[h + 4].y = z3;
+                e[h + 6].y = z4;
+            }
+        }
+    };
+    (void)site_noise;
+    const T rsq = (T)(1.0 / sqrt((double)N));
 
 #pragma unroll 1
     for (int s = 0; s < a.nsteps; s++) {
@@ -1599,13 +1632,38 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
                 const T x = z[q].x * inv, y = z[q].y * inv;
                 z[q] = (KIND == 1) ? cx<T>{x * x, y * y} : cx<T>{x * x * x, y * y * y};
             }
-            fft_line<T, N, -1, PAD>(z, t, L, 1, tw);
+            if constexpr (RS) {
+                // the nonlinearity and the site noise of both realizations
+                // through the forward stages together (interleaved in LDS)
+                cx<T> w2[2][8];
+                site_noise(w2[1], s);
+#pragma unroll
+                for (int q = 0; q < 8; q++) w2[0][q] = z[q];
+                fft_lines<T, N, -1, PAD, 2>(w2, t, L, 2, 1, tw);
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    L[lds_slot<PAD>(t + q * M)] = w2[0][q];
+                    L[LL + lds_slot<PAD>(t + q * M)] = w2[1][q];
+                }
+                __syncthreads();
+            } else {
+                fft_line<T, N, -1, PAD>(z, t, L, 1, tw);
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    if (DA && (q == 3 || q == 4)) continue;
+                    L[lds_slot<PAD>(t + q * M)] = z[q];
+                }
+                __syncthreads();
+            }
+        } else if constexpr (RS) {
+            cx<T> e[8];
+            site_noise(e, s);
+            fft_line<T, N, -1, PAD>(e, t, L, 1, tw);
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < 8; q++) {
-                if (DA && (q == 3 || q == 4)) continue;
-                L[lds_slot<PAD>(t + q * M)] = z[q];
-            }
+            for (int q = 0; q < 8; q++) L[LL + lds_slot<PAD>(t + q * M)] = e[q];
             __syncthreads();
         }
         // per Philox block: split W into the two spectra, the model prefactor,
@@ -1618,6 +1676,20 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
         auto update = [&](int q, const uint32_t (&xa)[4], const uint32_t (&xb)[4], uint32_t P, uint32_t half, int kind) {
             if (!stored(q)) return;
             const int m = mode_of(q);
+            cx<T> eta_a, eta_b;
+            if constexpr (RS) {
+                // the transformed site noise of both realizations, split
+                const cx<T> Ek = L[LL + lds_slot<PAD>(m)], Em = L[LL + lds_slot<PAD>((N - m) & (N - 1))];
+                eta_a = {rsq * T(0.5) * (Ek.x + Em.x), rsq * T(0.5) * (Ek.y - Em.y)};
+                eta_b = {rsq * T(0.5) * (Ek.y + Em.y), rsq * T(0.5) * (Em.x - Ek.x)};
+            } else {
+                NoiseSlot ns;
+                ns.P = P;
+                ns.half = half;
+                ns.kind = kind;
+                eta_a = acta ? eta_of<T>(xa, ns) : czero<T>();
+                eta_b = actb ? eta_of<T>(xb, ns) : czero<T>();
+            }
             cx<T> F1 = czero<T>(), F2 = czero<T>();
             if constexpr (KIND != 2) {
                 const cx<T> Zk = L[lds_slot<PAD>(m)], Zm = L[lds_slot<PAD>((N - m) & (N - 1))];
@@ -1630,13 +1702,9 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
                 F1 = sa * wa;
                 F2 = sb * wb;
             }
-            NoiseSlot ns;
-            ns.P = P;
-            ns.half = half;
-            ns.kind = kind;
             if (acta) {
                 const Coef<T> c = load_coef_t<T, false>(ia.coef, m);
-                cx<T> nw = cmul(c.E, pa[q]) + cmul(c.wa, F1) + c.G * eta_of<T>(xa, ns);
+                cx<T> nw = cmul(c.E, pa[q]) + cmul(c.wa, F1) + c.G * eta_a;
                 if (o2) {
                     nw = nw + cmul(c.wb, upa ? fa[q] : F1);
                     fa[q] = F1;
@@ -1646,7 +1714,7 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
             }
             if (actb) {
                 const Coef<T> c = load_coef_t<T, false>(ib.coef, m);
-                cx<T> nw = cmul(c.E, pb[q]) + cmul(c.wa, F2) + c.G * eta_of<T>(xb, ns);
+                cx<T> nw = cmul(c.E, pb[q]) + cmul(c.wa, F2) + c.G * eta_b;
                 if (o2) {
                     nw = nw + cmul(c.wb, upb ? fb[q] : F2);
                     fb[q] = F2;
@@ -1659,8 +1727,8 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
         for (int h = 0; h < 2; h++) {
             uint32_t xa[4] = {0u, 0u, 0u, 0u}, xb[4] = {0u, 0u, 0u, 0u};
             const uint32_t P = (uint32_t)(t + h * M);
-            if (acta) philox_block(ia.seed, P, (uint32_t)(stepa + s), ia.r, 0u, xa);
-            if (actb) philox_block(ib.seed, P, (uint32_t)(stepb + s), ib.r, 0u, xb);
+            if (!RS && acta) philox_block(ia.seed, P, (uint32_t)(stepa + s), ia.r, 0u, xa);
+            if (!RS && actb) philox_block(ib.seed, P, (uint32_t)(stepb + s), ib.r, 0u, xb);
             update(h, xa, xb, P, 0u, (h == 0 && t == 0) ? 1 : 0);
             if (h + 2 < QS) update(h + 2, xa, xb, P, 1u, 0);
         }
@@ -1668,8 +1736,8 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
             if (t == 0) {
                 uint32_t xa[4] = {0u, 0u, 0u, 0u}, xb[4] = {0u, 0u, 0u, 0u};
                 const uint32_t P = (uint32_t)(2 * M);
-                if (acta) philox_block(ia.seed, P, (uint32_t)(stepa + s), ia.r, 0u, xa);
-                if (actb) philox_block(ib.seed, P, (uint32_t)(stepb + s), ib.r, 0u, xb);
+                if (!RS && acta) philox_block(ia.seed, P, (uint32_t)(stepa + s), ia.r, 0u, xa);
+                if (!RS && actb) philox_block(ib.seed, P, (uint32_t)(stepb + s), ib.r, 0u, xb);
                 update(4, xa, xb, P, 0u, 1);
             }
         }
@@ -1714,7 +1782,7 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
 // Complex field, one realization per line: thread t keeps bins j = t + q N/8
 // of phi (FFT order).  KIND 0: CGL, F = -(1 + i beta) FFT[|phi|^2 phi];
 // 1: no nonlinearity.  The noise block t + qM (q < 4) serves bins q and 7 - q.
-template <typename T, int N, int PAD, bool DA, int KIND>
+template <typename T, int N, int PAD, bool DA, int KIND, bool RS>
 __global__ void __launch_bounds__(256) k_line1d_cplx(Line1dArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1725,7 +1793,7 @@ __global__ void __launch_bounds__(256) k_line1d_cplx(Line1dArgs a)
     const int tid = threadIdx.x;
     const int l = tid / TPL, t = tid - l * TPL;
     const int line = blockIdx.x * LPB + l;
-    cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw) + (size_t)l * LL;
+    cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw) + (size_t)l * 2 * LL;
     const bool valid = line < a.nlines;
     const Item& it = a.items[valid ? line : 0];
     const bool act = valid && a.sub < it.steps;
@@ -1770,43 +1838,78 @@ __global__ void __launch_bounds__(256) k_line1d_cplx(Line1dArgs a)
         cf[q] = load_coef_t<T, true>(it.coef, coef_key(it, sgn_idx(t + q * M, N), 0, 0));   // complex tables
     }
     const cx<T> pref = nl_pref<T>(it, T(0));
+    const T rsq = (T)(1.0 / sqrt((double)N));
     bool bad = false;
 #pragma unroll 1
     for (int s = 0; s < a.nsteps; s++) {
-        cx<T> F[8];
-        if constexpr (KIND == 0) {
-            cx<T> z[8];
+        cx<T> F[8], eta[8];
+        // real-space noise: site x = t + qM takes (z1 + i z2)/sqrt2 of half
+        // q div 4 of the Philox block (t + (q mod 4) M, n, r, 3)
+        cx<T> e[8];
+        if constexpr (RS) {
+            const T rs2 = T(0.70710678118654752440084436210484903928);
 #pragma unroll
-            for (int q = 0; q < 8; q++) z[q] = p[q];
-            fft_line<T, N, +1, PAD>(z, t, L, 1, tw);
+            for (int q = 0; q < 4; q++) {
+                e[q] = e[q + 4] = czero<T>();
+                if (!act) continue;
+                uint32_t x[4];
+                T z1, z2, z3, z4;
+                philox_block(it.seed, (uint32_t)(t + q * M), (uint32_t)(step0 + s), it.r, 3u, x);
+                box_muller32(x[0], x[1], z1, z2);
+                box_muller32(x[2], x[3], z3, z4);
+                e[q] = {rs2 * z1, rs2 * z2};
+                e[q + 4] = {rs2 * z3, rs2 * z4};
+            }
+        }
+        if constexpr (KIND == 0) {
+            cx<T> z[2][8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) z[0][q] = p[q];
+            fft_line<T, N, +1, PAD>(z[0], t, L, 1, tw);
 #pragma unroll
             for (int q = 0; q < 8; q++) {
-                const T x = z[q].x * inv, y = z[q].y * inv;
+                const T x = z[0][q].x * inv, y = z[0][q].y * inv;
                 const T m2 = x * x + y * y;
-                z[q] = {m2 * x, m2 * y};
+                z[0][q] = {m2 * x, m2 * y};
             }
-            fft_line<T, N, -1, PAD>(z, t, L, 1, tw);
+            if constexpr (RS) {
+                // the nonlinearity and the site noise through the forward
+                // stages together
 #pragma unroll
-            for (int q = 0; q < 8; q++) F[q] = (si[q] >= 0) ? cmul(pref, z[q]) : czero<T>();
+                for (int q = 0; q < 8; q++) z[1][q] = e[q];
+                fft_lines<T, N, -1, PAD, 2>(z, t, L, 2, 1, tw);
+#pragma unroll
+                for (int q = 0; q < 8; q++) e[q] = z[1][q];
+            } else {
+                fft_line<T, N, -1, PAD>(z[0], t, L, 1, tw);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) F[q] = (si[q] >= 0) ? cmul(pref, z[0][q]) : czero<T>();
         } else {
 #pragma unroll
             for (int q = 0; q < 8; q++) F[q] = czero<T>();
+            if constexpr (RS) fft_line<T, N, -1, PAD>(e, t, L, 1, tw);
         }
-        cx<T> eta[8];
+        if constexpr (RS) {
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            eta[q] = eta[7 - q] = czero<T>();
-            if (DA && q == 3) continue;
-            if (!act || (si[q] < 0 && si[7 - q] < 0)) continue;
-            uint32_t x[4];
-            philox_block(it.seed, (uint32_t)(t + q * M), (uint32_t)(step0 + s), it.r, 0u, x);
-            NoiseSlot ns;
-            ns.P = (uint32_t)(t + q * M);
-            ns.kind = 0;
-            ns.half = 0u;
-            eta[q] = eta_of<T>(x, ns);
-            ns.half = 1u;
-            eta[7 - q] = eta_of<T>(x, ns);
+            for (int q = 0; q < 8; q++) eta[q] = rsq * e[q];
+        }
+        if constexpr (!RS) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                eta[q] = eta[7 - q] = czero<T>();
+                if (DA && q == 3) continue;
+                if (!act || (si[q] < 0 && si[7 - q] < 0)) continue;
+                uint32_t x[4];
+                philox_block(it.seed, (uint32_t)(t + q * M), (uint32_t)(step0 + s), it.r, 0u, x);
+                NoiseSlot ns;
+                ns.P = (uint32_t)(t + q * M);
+                ns.kind = 0;
+                ns.half = 0u;
+                eta[q] = eta_of<T>(x, ns);
+                ns.half = 1u;
+                eta[7 - q] = eta_of<T>(x, ns);
+            }
         }
         const bool up = o2 && (s > 0 || hp);
 #pragma unroll

@@ -61,6 +61,8 @@ setd_status validate(const setd_desc& d)
         return fail(SETD_E_INVAL, "series_len must be 0 or a power of two in [8, 1024]");
     if (d.ic_kind != 0 && d.ic_kind != 1) return fail(SETD_E_INVAL, "ic_kind must be 0 or 1");
     if (d.complex_field != 0 && d.complex_field != 1) return fail(SETD_E_INVAL, "complex_field must be 0 or 1");
+    if (d.noise_space != 0 && d.noise_space != 1) return fail(SETD_E_INVAL, "noise_space must be 0 or 1");
+    if (d.noise_space == 1 && d.ndim != 1) return fail(SETD_E_UNSUPPORTED, "real-space noise is built for 1D lines");
     const bool cimag = d.c0[1] != 0.0 || d.c2[1] != 0.0 || d.c4[1] != 0.0;
     if (cimag && !d.complex_field) return fail(SETD_E_INVAL, "complex c(k) needs a complex field");
     if (d.nl < 0 || d.nl > 4) return fail(SETD_E_INVAL, "unknown nonlinearity %d", d.nl);
@@ -89,6 +91,7 @@ setd_status Plan::init(const setd_desc& desc)
     g.cplx = d.complex_field;
     g.prec = d.precision;
     g.dealias = d.dealias;
+    g.rsn = d.noise_space;
     const int last = d.ndim - 1;
     for (int i = 0; i < 3; i++) {
         if (i >= d.ndim) {
@@ -898,6 +901,7 @@ setd_status Plan::observe(int kind, double* out, size_t cap, size_t* len)
     }
     case SETD_OBS_SPECTRUM: {
         const int M = d.series_len;
+        if (g.rsn) return fail(SETD_E_UNSUPPORTED, "the kick estimators regenerate Fourier-space noise");
         if (!iso) return fail(SETD_E_INVAL, "shell averages need equal n[i]");
         if (M <= 0 || series_pos < M) return fail(SETD_E_INVAL, "no complete time series window");
         const size_t nsum = (size_t)3 * nb * M + nb;
@@ -982,6 +986,7 @@ setd_status Plan::observe(int kind, double* out, size_t cap, size_t* len)
         return f ? fail(SETD_E_NONFINITE, "a realization produced a non-finite value") : SETD_OK;
     }
     case SETD_OBS_KICK: {
+        if (g.rsn) return fail(SETD_E_UNSUPPORTED, "the kick estimators regenerate Fourier-space noise");
         Ctrl c0;
         SETD_HIP(hipMemcpyAsync(&c0, ws + lay.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
         SETD_HIP(hipStreamSynchronize(stream));
@@ -1144,8 +1149,8 @@ std::string class_key(const Plan& p)
 {
     char buf[160];
     const int kind = p.d.nl == NL_NONE ? 1 : (p.d.nl == NL_KPZ ? 2 : 0);
-    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%d|%d|%d|%d", p.g.ndim, p.g.cplx, p.g.prec, p.g.dealias, p.g.n[0],
-             p.g.n[1], p.g.n[2], kind, p.lean ? 1 : 0);
+    snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", p.g.ndim, p.g.cplx, p.g.prec, p.g.dealias, p.g.n[0],
+             p.g.n[1], p.g.n[2], kind, p.lean ? 1 : 0, p.g.rsn);
     return buf;
 }
 

@@ -19,6 +19,7 @@ struct Geo {
     int kp[3];        // largest stored FFT index on the low side of each axis
     int pitch;        // padded length of the stored last axis (elements)
     int nh_last;      // unpruned spectral length of the last axis (n/2+1 or n)
+    int rsn;          // noise drawn in real space and transformed (1D lines)
 };
 
 // stored rows of a realization: [kept0][kept1] lines of the last axis (3D),

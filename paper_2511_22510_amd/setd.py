@@ -44,7 +44,7 @@ class setd_desc(ctypes.Structure):
         ("h", ctypes.c_double), ("order", ctypes.c_int), ("precision", ctypes.c_int),
         ("realizations", ctypes.c_int), ("seed", ctypes.c_uint64), ("dealias", ctypes.c_int),
         ("ic_kind", ctypes.c_int), ("ic_sigma", ctypes.c_double),
-        ("history_readback", ctypes.c_int), ("series_len", ctypes.c_int),
+        ("history_readback", ctypes.c_int), ("series_len", ctypes.c_int), ("noise_space", ctypes.c_int),
     ]
 
 
@@ -168,6 +168,7 @@ def make_desc(p):
     d.ic_kind = int(p.get("ic_kind", 0))
     d.ic_sigma = float(p.get("ic_sigma", 0.0))
     d.history_readback = int(p.get("history_readback", 0))
+    d.noise_space = int(p.get("noise_space", 0))
     d.series_len = int(p.get("series_len", 0))
     return d
 

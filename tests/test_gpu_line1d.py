@@ -194,3 +194,36 @@ def test_line_stationary_spectrum_of_the_paper_figure():
     say("line S(k) z max", float(np.max(np.abs(z))))
     assert np.max(np.abs(z)) < 5.0
     g.close()
+
+
+RS_CASES = [
+    W.model_a([256], precision=64, order=2, realizations=3, dx=0.25, noise_space=1),
+    W.model_a([64], precision=32, order=1, realizations=2, dealias=0, noise_space=1),
+    W.kpz([1024], precision=32, order=2, realizations=2, dx=0.5, lam=50.0, D=0.01, h=2e-3, noise_space=1),
+    W.cgl([64], precision=64, order=2, realizations=2, noise_space=1),
+    W.cgl([32], precision=32, order=1, realizations=1, dealias=0, noise_space=1),
+    W.model_a([128], precision=64, nl="none", u=0.0, r=0.5, realizations=3, noise_space=1),
+    W.cgl([16], precision=64, nl="none", realizations=1, noise_space=1),
+]
+
+
+@pytest.mark.parametrize("p", RS_CASES, ids=lambda p: "rs-%s-%d-f%d-o%d-d%d-R%d" % (
+    p["nl"], p["n"][0], p["precision"], p["order"], p["dealias"], p["realizations"]))
+def test_line_real_space_noise_parity(p):
+    """Noise drawn per site in real space and transformed (Sec. 4 step 2's
+    alternative) against the oracle's draws and transform."""
+    err = run_pair(p, steps=60, every=30)
+    say("max rel err", err)
+    assert err <= TOL[p["precision"]]
+
+
+def test_real_space_noise_limits():
+    S = _setd()
+    with pytest.raises(S.SetdError) as e:
+        S.Plan(W.model_a([32, 32], precision=32, noise_space=1))
+    assert e.value.status == S.SETD_E_UNSUPPORTED
+    g = S.Plan(W.model_a([64], precision=32, realizations=2, noise_space=1))
+    with pytest.raises(S.SetdError) as e:
+        g.observe(S.OBS_KICK)
+    assert e.value.status == S.SETD_E_UNSUPPORTED
+    g.close()
