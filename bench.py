@@ -206,11 +206,20 @@ def other_workloads(setd, W, steps):
         res.append({"workload": name, "site_updates_per_s": float(info.site_updates_per_step) / sec,
                     "ms_per_step": 1e3 * sec, "alg_bytes_per_step": float(info.alg_bytes_per_step),
                     "step_frac": float(info.alg_bytes_per_step / sec / 1e9 / PEAK_HBM_GBS), "ok": bool(ok)})
-    # 1D lines: up to 256 steps per launch with the state in registers, so the
-    # state crosses HBM once per launch and the transforms and noise bound it
-    for name, cfg in (("Model A line N=256 (L=64), SETD1, FP32, 16384 realizations", W.LINE_MODEL_A),
-                      ("KPZ line N=1024 (L=512), SETD2, FP32, 4096 realizations", W.LINE_KPZ)):
-        p = W.problem(cfg)
+    return res + line_workloads(setd, W, "ak")
+
+
+LINES = {"a": ("Model A line N=256 (L=64), SETD1, FP32, 16384 realizations", "LINE_MODEL_A"),
+         "k": ("KPZ line N=1024 (L=512), SETD2, FP32, 4096 realizations", "LINE_KPZ")}
+
+
+def line_workloads(setd, W, which):
+    """1D lines: up to 256 steps per launch with the state in registers, so the
+    state crosses HBM once per launch and the transforms and noise bound it."""
+    res = []
+    for key in which:
+        name, cfg = LINES[key]
+        p = W.problem(getattr(W, cfg))
         k = 8 * LINE_STEPS_PER_LAUNCH
         el, _, info, ok, _ = time_plan(setd, p, k, LINE_STEPS_PER_LAUNCH, profile=False)
         sec = el / k
@@ -267,6 +276,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--serving-jobs", type=int, default=40, help="0 skips the serving run")
     ap.add_argument("--no-other", action="store_true", help="skip the KPZ and CGL step rates")
+    ap.add_argument("--lines", choices=["a", "k", "ak"], default=None,
+                    help="time only the 1D line workloads (a: Model A, k: KPZ) and print them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 512 MiB device-to-device (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -280,6 +291,9 @@ def main():
     from paper_2511_22510_amd import setd, workloads as W
 
     torch.cuda.set_device(0)
+    if args.lines:
+        print(json.dumps({"line_workloads": line_workloads(setd, W, args.lines)}), flush=True)
+        return
     if args.copy_calibration:
         src = torch.ones(2**27, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

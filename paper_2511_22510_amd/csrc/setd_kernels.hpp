@@ -1528,6 +1528,7 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
 
     // state, F_{n-1}, coefficients and steps of both realizations
     cx<T> fa[QS], fb[QS];
+    Coef<T> ca[QS], cb[QS];
     const cx<T>* phia0 = reinterpret_cast<const cx<T>*>(ia.phi);
     const cx<T>* phib0 = reinterpret_cast<const cx<T>*>(ib.phi);
     const cx<T>* preva = reinterpret_cast<const cx<T>*>(ia.prev);
@@ -1538,6 +1539,7 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
 #pragma unroll
     for (int q = 0; q < QS; q++) {
         pa[q] = pb[q] = fa[q] = fb[q] = czero<T>();
+        ca[q] = cb[q] = Coef<T>{czero<T>(), czero<T>(), czero<T>(), T(0)};
         if (!stored(q)) continue;
         const int m = mode_of(q);
         // a realization that does not step in this launch is no partner: its
@@ -1545,10 +1547,12 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
         if (acta) {
             pa[q] = phia0[m];
             if (o2 && hpa) fa[q] = preva[m];
+            ca[q] = load_coef_t<T, false>(ia.coef, m);   // real fields: real tables, keyed by |a|
         }
         if (actb) {
             pb[q] = phib0[m];
             if (o2 && hpb) fb[q] = prevb[m];
+            cb[q] = load_coef_t<T, false>(ib.coef, m);
         }
         if (m == 0 || 2 * m == N) {
             pa[q].y = T(0);
@@ -1666,80 +1670,94 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
             for (int q = 0; q < 8; q++) L[LL + lds_slot<PAD>(t + q * M)] = e[q];
             __syncthreads();
         }
-        // per Philox block: split W into the two spectra, the model prefactor,
-        // the noise and the update of Eq. SETD1 / SETD2 (the first step of a
-        // fresh state takes F_{n-1} = F_n); block t serves modes t and t + 2M,
-        // block t + M modes t + M and t + 3M, block 2M the Nyquist mode
-        // (thread 0).  The table entries (real for real fields, keyed by |a|)
-        // come from the cache each step, which keeps registers free.
-        const bool upa = o2 && (s > 0 || hpa), upb = o2 && (s > 0 || hpb);
-        auto update = [&](int q, const uint32_t (&xa)[4], const uint32_t (&xb)[4], uint32_t P, uint32_t half, int kind) {
-            if (!stored(q)) return;
-            const int m = mode_of(q);
-            cx<T> eta_a, eta_b;
-            if constexpr (RS) {
-                // the transformed site noise of both realizations, split
-                const cx<T> Ek = L[LL + lds_slot<PAD>(m)], Em = L[LL + lds_slot<PAD>((N - m) & (N - 1))];
-                eta_a = {rsq * T(0.5) * (Ek.x + Em.x), rsq * T(0.5) * (Ek.y - Em.y)};
-                eta_b = {rsq * T(0.5) * (Ek.y + Em.y), rsq * T(0.5) * (Em.x - Ek.x)};
-            } else {
-                NoiseSlot ns;
-                ns.P = P;
-                ns.half = half;
-                ns.kind = kind;
-                eta_a = acta ? eta_of<T>(xa, ns) : czero<T>();
-                eta_b = actb ? eta_of<T>(xb, ns) : czero<T>();
-            }
-            cx<T> F1 = czero<T>(), F2 = czero<T>();
+        // split W into the two spectra with the model prefactor
+        cx<T> F1[QS], F2[QS];
+#pragma unroll
+        for (int q = 0; q < QS; q++) {
+            F1[q] = F2[q] = czero<T>();
             if constexpr (KIND != 2) {
-                const cx<T> Zk = L[lds_slot<PAD>(m)], Zm = L[lds_slot<PAD>((N - m) & (N - 1))];
+                const int k = mode_of(q) & (N - 1);
+                const cx<T> Zk = L[lds_slot<PAD>(k)], Zm = L[lds_slot<PAD>((N - k) & (N - 1))];
                 const cx<T> wa = {T(0.5) * (Zk.x + Zm.x), T(0.5) * (Zk.y - Zm.y)};
                 const cx<T> wb = {T(0.5) * (Zk.y + Zm.y), T(0.5) * (Zm.x - Zk.x)};
-                const T k2a = (dka * (T)m) * (dka * (T)m), k2b = (dkb * (T)m) * (dkb * (T)m);
+                const T k2a = (dka * (T)k) * (dka * (T)k), k2b = (dkb * (T)k) * (dkb * (T)k);
                 // Model B: -u k^2; the others a constant
                 const T sa = (ia.nl == NL_PHI3_CONS) ? -(T)ia.par0 * k2a : pra.x;
                 const T sb = (ib.nl == NL_PHI3_CONS) ? -(T)ib.par0 * k2b : prb.x;
-                F1 = sa * wa;
-                F2 = sb * wb;
+                F1[q] = sa * wa;
+                F2[q] = sb * wb;
             }
-            if (acta) {
-                const Coef<T> c = load_coef_t<T, false>(ia.coef, m);
-                cx<T> nw = cmul(c.E, pa[q]) + cmul(c.wa, F1) + c.G * eta_a;
-                if (o2) {
-                    nw = nw + cmul(c.wb, upa ? fa[q] : F1);
-                    fa[q] = F1;
-                }
-                if (m == 0 || 2 * m == N) nw.y = T(0);
-                pa[q] = nw;
-            }
-            if (actb) {
-                const Coef<T> c = load_coef_t<T, false>(ib.coef, m);
-                cx<T> nw = cmul(c.E, pb[q]) + cmul(c.wa, F2) + c.G * eta_b;
-                if (o2) {
-                    nw = nw + cmul(c.wb, upb ? fb[q] : F2);
-                    fb[q] = F2;
-                }
-                if (m == 0 || 2 * m == N) nw.y = T(0);
-                pb[q] = nw;
-            }
-        };
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            uint32_t xa[4] = {0u, 0u, 0u, 0u}, xb[4] = {0u, 0u, 0u, 0u};
-            const uint32_t P = (uint32_t)(t + h * M);
-            if (!RS && acta) philox_block(ia.seed, P, (uint32_t)(stepa + s), ia.r, 0u, xa);
-            if (!RS && actb) philox_block(ib.seed, P, (uint32_t)(stepb + s), ib.r, 0u, xb);
-            update(h, xa, xb, P, 0u, (h == 0 && t == 0) ? 1 : 0);
-            if (h + 2 < QS) update(h + 2, xa, xb, P, 1u, 0);
         }
-        if constexpr (!DA) {
-            if (t == 0) {
-                uint32_t xa[4] = {0u, 0u, 0u, 0u}, xb[4] = {0u, 0u, 0u, 0u};
-                const uint32_t P = (uint32_t)(2 * M);
-                if (!RS && acta) philox_block(ia.seed, P, (uint32_t)(stepa + s), ia.r, 0u, xa);
-                if (!RS && actb) philox_block(ib.seed, P, (uint32_t)(stepb + s), ib.r, 0u, xb);
-                update(4, xa, xb, P, 0u, 1);
+        cx<T> ea[QS], eb[QS];
+        if constexpr (RS) {
+            // the transformed site noise of both realizations, split
+#pragma unroll
+            for (int q = 0; q < QS; q++) {
+                const int k = mode_of(q) & (N - 1);
+                const cx<T> Ek = L[LL + lds_slot<PAD>(k)], Em = L[LL + lds_slot<PAD>((N - k) & (N - 1))];
+                ea[q] = {rsq * T(0.5) * (Ek.x + Em.x), rsq * T(0.5) * (Ek.y - Em.y)};
+                eb[q] = {rsq * T(0.5) * (Ek.y + Em.y), rsq * T(0.5) * (Em.x - Ek.x)};
             }
+        } else {
+            // Fourier draws: block t serves modes t and t + 2M, block t + M
+            // serves t + M and t + 3M, block 2M the Nyquist mode (thread 0)
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                uint32_t xa[4], xb[4];
+                const uint32_t P = (uint32_t)(t + h * M);
+                if (acta) philox_block(ia.seed, P, (uint32_t)(stepa + s), ia.r, 0u, xa);
+                if (actb) philox_block(ib.seed, P, (uint32_t)(stepb + s), ib.r, 0u, xb);
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+                    const int q = h + 2 * u;
+                    if (q >= QS) continue;
+                    NoiseSlot ns;
+                    ns.P = P;
+                    ns.half = (uint32_t)u;
+                    ns.kind = (q == 0 && t == 0) ? 1 : 0;
+                    ea[q] = acta ? eta_of<T>(xa, ns) : czero<T>();
+                    eb[q] = actb ? eta_of<T>(xb, ns) : czero<T>();
+                }
+            }
+            if constexpr (!DA) {
+                ea[4] = eb[4] = czero<T>();
+                if (t == 0) {
+                    uint32_t xa[4], xb[4];
+                    NoiseSlot ns;
+                    ns.P = (uint32_t)(2 * M);
+                    ns.half = 0u;
+                    ns.kind = 1;
+                    if (acta) {
+                        philox_block(ia.seed, ns.P, (uint32_t)(stepa + s), ia.r, 0u, xa);
+                        ea[4] = eta_of<T>(xa, ns);
+                    }
+                    if (actb) {
+                        philox_block(ib.seed, ns.P, (uint32_t)(stepb + s), ib.r, 0u, xb);
+                        eb[4] = eta_of<T>(xb, ns);
+                    }
+                }
+            }
+        }
+        // Eq. SETD1 / SETD2 (the first step of a fresh state takes F_{n-1} = F_n)
+        const bool upa = o2 && (s > 0 || hpa), upb = o2 && (s > 0 || hpb);
+#pragma unroll
+        for (int q = 0; q < QS; q++) {
+            if (!stored(q)) continue;
+            const int m = mode_of(q);
+            cx<T> na = cmul(ca[q].E, pa[q]) + cmul(ca[q].wa, F1[q]) + ca[q].G * ea[q];
+            cx<T> nb = cmul(cb[q].E, pb[q]) + cmul(cb[q].wa, F2[q]) + cb[q].G * eb[q];
+            if (o2) {
+                na = na + cmul(ca[q].wb, upa ? fa[q] : F1[q]);
+                nb = nb + cmul(cb[q].wb, upb ? fb[q] : F2[q]);
+                fa[q] = F1[q];
+                fb[q] = F2[q];
+            }
+            if (m == 0 || 2 * m == N) {
+                na.y = T(0);
+                nb.y = T(0);
+            }
+            if (acta) pa[q] = na;
+            if (actb) pb[q] = nb;
         }
     }
     cx<T>* phia = reinterpret_cast<cx<T>*>(ia.phi);
