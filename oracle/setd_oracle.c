@@ -72,7 +72,7 @@ typedef struct {
     int order;             /* 1 SETD1, 2 SETD2                              */
     int realizations;
     uint64_t seed;
-    int dealias;           /* 0 none, 1 the 2/3 rule                        */
+    int dealias;           /* 0 none, 1 the 2/3 rule, 2 phase shift (1D)    */
     int ic_kind;           /* 0 zero, 1 Gaussian per site                   */
     double ic_sigma;
     int noise_space;       /* 0 Fourier-space draws (App. B), 1 real space  */
@@ -419,6 +419,7 @@ orc_sim* orc_create_subset(const orc_desc* d, int r_first, int r_count)
     if (d->ndim < 1 || d->ndim > 3) return NULL;
     for (int i = 0; i < d->ndim; i++) if (!is_pow2(d->n[i]) || d->n[i] < 4) return NULL;
     if (d->order != 1 && d->order != 2) return NULL;
+    if (d->dealias < 0 || d->dealias > 2 || (d->dealias == 2 && d->ndim != 1)) return NULL;
     if (!(d->h > 0) || !(d->dx > 0)) return NULL;
     if (d->realizations < 1 || r_first < 0 || r_count < 1 || r_first + r_count > d->realizations) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
@@ -473,7 +474,8 @@ orc_sim* orc_create_subset(const orc_desc* d, int r_first, int r_count)
             s->kidx[3 * e + i] = a;
             double dk = 2.0 * M_PI / (d->n[i] * d->dx);
             k2 += (dk * a) * (dk * a);
-            if (d->dealias && 3 * abs(a) >= d->n[i]) keep = 0;
+            if (d->dealias == 1 && 3 * abs(a) >= d->n[i]) keep = 0;
+            if (d->dealias == 2 && 2 * abs(a) >= d->n[i]) keep = 0;   /* the Nyquist mode has no shift */
         }
         for (int i = d->ndim; i < 3; i++) s->kidx[3 * e + i] = 0;
         s->k2[e] = k2;
@@ -552,11 +554,38 @@ int orc_threads(void) { return omp_get_max_threads(); }
 /* ------------------------------------------------------------------------ */
 /* Step 1 of Sec. 4: F_a = M_a pref_a FFT[N(IFFT[phi])]                      */
 /* ------------------------------------------------------------------------ */
+static void nonlinear_raw(orc_sim* s, const cplx* ph, cplx* F);
+
+/* Phase-shift dealiasing on a line (Sec. 4; the paper names the method, the
+   rule here is this implementation's reading): the nonlinearity is also
+   evaluated on the grid shifted by dx/2, i.e. from e^{i k dx/2} phi_a, and
+   transformed back with e^{-i k dx/2}; the mean of the two transforms has the
+   single aliases a +- N with opposite signs, so they cancel.  With the
+   Nyquist mode dropped, the quadratic and cubic products of modes |a| < N/2
+   alias at most once, so F is alias-free. */
 static void nonlinear_term(orc_sim* s, const cplx* ph, cplx* F)
 {
     const orc_desc* d = &s->d;
-    size_t ns = s->nspec, nr = s->nreal;
+    size_t ns = s->nspec;
     if (d->nl == NL_NONE) { for (size_t e = 0; e < ns; e++) F[e] = 0; return; }
+    nonlinear_raw(s, ph, F);
+    if (d->dealias == 2) {
+        cplx* shifted = (cplx*)malloc(sizeof(cplx) * ns);
+        cplx* Fs = (cplx*)malloc(sizeof(cplx) * ns);
+        for (size_t e = 0; e < ns; e++) shifted[e] = cexp(I * M_PI * s->kidx[3 * e] / d->n[0]) * ph[e];
+        nonlinear_raw(s, shifted, Fs);
+        for (size_t e = 0; e < ns; e++) F[e] = 0.5 * (F[e] + cexp(-I * M_PI * s->kidx[3 * e] / d->n[0]) * Fs[e]);
+        free(shifted);
+        free(Fs);
+    }
+    for (size_t e = 0; e < ns; e++) F[e] = s->mask[e] ? s->pref[e] * F[e] : 0;
+}
+
+/* FFT[N(IFFT[phi])] without mask or prefactor */
+static void nonlinear_raw(orc_sim* s, const cplx* ph, cplx* F)
+{
+    const orc_desc* d = &s->d;
+    size_t ns = s->nspec, nr = s->nreal;
     if (d->complex_field) {
         for (size_t e = 0; e < nr; e++) s->work2[e] = ph[e];
         fftn(s->work2, d->ndim, d->n, +1);
@@ -566,7 +595,7 @@ static void nonlinear_term(orc_sim* s, const cplx* ph, cplx* F)
             else s->work2[e] = A * A * A;   /* phi^3 on a complex field */
         }
         fftn(s->work2, d->ndim, d->n, -1);
-        for (size_t e = 0; e < ns; e++) F[e] = s->mask[e] ? s->pref[e] * s->work2[e] : 0;
+        for (size_t e = 0; e < ns; e++) F[e] = s->work2[e];
         return;
     }
     if (d->nl == NL_KPZ) {
@@ -587,7 +616,6 @@ static void nonlinear_term(orc_sim* s, const cplx* ph, cplx* F)
         for (size_t e = 0; e < nr; e++) { double p = s->rwork[e]; s->rwork2[e] = p * p * p; }
     }
     rfftn(s->rwork2, F, d->ndim, d->n, s->work);
-    for (size_t e = 0; e < ns; e++) F[e] = s->mask[e] ? s->pref[e] * F[e] : 0;
 }
 
 /* App. B: the mode whose draw gives eta_a of mode e (e itself, or on the
