@@ -144,7 +144,11 @@ typedef struct {
                                  evaluated in FP64 and rounded; 64: complex128     */
     int realizations;         /* independent noise realizations in one plan (>= 1) */
     uint64_t seed;            /* Philox4x32-10 key                                 */
-    int dealias;              /* 0: none; 1: 2/3 rule, keep 3|a_i| < n[i]          */
+    int dealias;              /* 0: none; 1: 2/3 rule, keep 3|a_i| < n[i]; 2 (1D
+                                 lines, Fourier-space noise): phase shift, the
+                                 nonlinearity averaged over the grid and the grid
+                                 moved by dx/2, keeping 2|a| < n (alias-free for
+                                 the quadratic and cubic terms)                */
     int ic_kind;              /* 0: phi = 0; 1: i.i.d. N(0, ic_sigma^2) per site
                                  (complex fields: ic_sigma (z1 + i z2))             */
     double ic_sigma;

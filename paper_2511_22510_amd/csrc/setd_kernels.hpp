@@ -1431,6 +1431,16 @@ struct Line1dArgs {
     int nsteps;   // MODE_STEP: steps of this launch
 };
 
+// e^{i pi x}
+template <typename T>
+__device__ __forceinline__ cx<T> cispi(T x)
+{
+    T s, c;
+    if constexpr (sizeof(T) == 4) sincospif(x, &s, &c);
+    else sincospi(x, &s, &c);
+    return {c, s};
+}
+
 // Twiddles of a line kernel: every power in registers (FP32) or the stage
 // bases only (FP64, whose registers are twice as wide).
 template <typename T, int N, int KIND>
@@ -1459,14 +1469,16 @@ __device__ __forceinline__ void line1d_tw(Line1dTw<T, N, KIND>& tw, int t, const
 // per realization with its own noise, table and step.  KIND 0: phi^3 (Model A,
 // and Model B with its k^2 in the prefactor), 1: KPZ ((lambda/2) h'^2 from the
 // line of h + i h' per realization pair), 2: no nonlinearity.
-template <typename T, int N, int PAD, bool DA, int KIND, bool RS>
+template <typename T, int N, int PAD, int DM, int KIND, bool RS>
 __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr bool DA = DM == 1, PS = DM == 2;   // 2/3 truncation, phase shift
+    static_assert(!(RS && PS), "real-space noise and phase shifts are not combined");
     constexpr int TPL = N / 8, M = N / 8;
     constexpr int LPB = 256 / TPL;
     constexpr int LL = lds_len<N, PAD>();
-    constexpr int QS = DA ? 3 : 5;    // register slots of stored modes
+    constexpr int QS = DA ? 3 : (PS ? 4 : 5);    // register slots of stored modes
     const Geo& g = a.g;
     const int tid = threadIdx.x;
     const int l = tid / TPL, t = tid - l * TPL;
@@ -1477,13 +1489,19 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
     const Item& ia = a.items[va ? ra : 0];
     const Item& ib = a.items[vb ? rb : (va ? ra : 0)];
     const bool acta = va && a.sub < ia.steps, actb = vb && a.sub < ib.steps;
-    const int K = DA ? (N - 1) / 3 : N / 2;
+    const int K = DA ? (N - 1) / 3 : (PS ? N / 2 - 1 : N / 2);
     Line1dTw<T, N, KIND> tw;
     line1d_tw<T, N, KIND>(tw, t, twid<T>(ia.tw0));
     const T inv = (T)ia.inv_vol;
     // mode of slot q, and whether it is stored
     auto mode_of = [&](int q) { return t + q * M; };
-    auto stored = [&](int q) { return q < 4 ? (t + q * M <= K) : (!DA && t == 0); };
+    auto stored = [&](int q) { return q < 4 ? (t + q * M <= K) : (DM == 0 && t == 0); };
+    // phase shift: e^{i pi a/N} of bin t + qM (signed a), the grid moved by dx/2
+    cx<T> phs[PS ? 8 : 1];
+    if constexpr (PS) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) phs[q] = cispi<T>((T)sgn_idx(t + q * M, N) / (T)N);
+    }
 
     cx<T> pa[QS], pb[QS];
     if (a.mode == MODE_IC) {
@@ -1630,13 +1648,42 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
                     z[q] = {A.x + B.y, B.x - A.y};
                 }
             }
-            fft_line<T, N, +1, PAD>(z, t, L, 1, tw);
+            if constexpr (PS) {
+                // the nonlinearity on the grid and on the grid shifted by
+                // dx/2, through the stages together; the mean of the two
+                // transforms (the second shifted back) cancels single aliases
+                cx<T> w[2][8];
 #pragma unroll
-            for (int q = 0; q < 8; q++) {
-                const T x = z[q].x * inv, y = z[q].y * inv;
-                z[q] = (KIND == 1) ? cx<T>{x * x, y * y} : cx<T>{x * x * x, y * y * y};
+                for (int q = 0; q < 8; q++) {
+                    w[0][q] = z[q];
+                    w[1][q] = cmul(phs[q], z[q]);
+                }
+                fft_lines<T, N, +1, PAD, 2>(w, t, L, 2, 1, tw);
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        const T x = w[u][q].x * inv, y = w[u][q].y * inv;
+                        w[u][q] = (KIND == 1) ? cx<T>{x * x, y * y} : cx<T>{x * x * x, y * y * y};
+                    }
+                }
+                fft_lines<T, N, -1, PAD, 2>(w, t, L, 2, 1, tw);
+#pragma unroll
+                for (int q = 0; q < 8; q++) z[q] = T(0.5) * (w[0][q] + cmulc(w[1][q], phs[q]));
+            } else {
+                fft_line<T, N, +1, PAD>(z, t, L, 1, tw);
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const T x = z[q].x * inv, y = z[q].y * inv;
+                    z[q] = (KIND == 1) ? cx<T>{x * x, y * y} : cx<T>{x * x * x, y * y * y};
+                }
             }
-            if constexpr (RS) {
+            if constexpr (PS) {
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 8; q++) L[lds_slot<PAD>(t + q * M)] = z[q];
+                __syncthreads();
+            } else if constexpr (RS) {
                 // the nonlinearity and the site noise of both realizations
                 // through the forward stages together (interleaved in LDS)
                 cx<T> w2[2][8];
@@ -1719,7 +1766,7 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
                     eb[q] = actb ? eta_of<T>(xb, ns) : czero<T>();
                 }
             }
-            if constexpr (!DA) {
+            if constexpr (DM == 0) {
                 ea[4] = eb[4] = czero<T>();
                 if (t == 0) {
                     uint32_t xa[4], xb[4];
@@ -1800,10 +1847,12 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
 // Complex field, one realization per line: thread t keeps bins j = t + q N/8
 // of phi (FFT order).  KIND 0: CGL, F = -(1 + i beta) FFT[|phi|^2 phi];
 // 1: no nonlinearity.  The noise block t + qM (q < 4) serves bins q and 7 - q.
-template <typename T, int N, int PAD, bool DA, int KIND, bool RS>
+template <typename T, int N, int PAD, int DM, int KIND, bool RS>
 __global__ void __launch_bounds__(256) k_line1d_cplx(Line1dArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr bool DA = DM == 1, PS = DM == 2;   // 2/3 truncation, phase shift
+    static_assert(!(RS && PS), "real-space noise and phase shifts are not combined");
     constexpr int TPL = N / 8, M = N / 8;
     constexpr int LPB = 256 / TPL;
     constexpr int LL = lds_len<N, PAD>();
@@ -1883,12 +1932,35 @@ __global__ void __launch_bounds__(256) k_line1d_cplx(Line1dArgs a)
             cx<T> z[2][8];
 #pragma unroll
             for (int q = 0; q < 8; q++) z[0][q] = p[q];
-            fft_line<T, N, +1, PAD>(z[0], t, L, 1, tw);
+            if constexpr (PS) {
+                // the grid and the grid shifted by dx/2 together
+                cx<T> phs[8];
 #pragma unroll
-            for (int q = 0; q < 8; q++) {
-                const T x = z[0][q].x * inv, y = z[0][q].y * inv;
-                const T m2 = x * x + y * y;
-                z[0][q] = {m2 * x, m2 * y};
+                for (int q = 0; q < 8; q++) {
+                    phs[q] = cispi<T>((T)sgn_idx(t + q * M, N) / (T)N);
+                    z[1][q] = cmul(phs[q], p[q]);
+                }
+                fft_lines<T, N, +1, PAD, 2>(z, t, L, 2, 1, tw);
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        const T x = z[u][q].x * inv, y = z[u][q].y * inv;
+                        const T m2 = x * x + y * y;
+                        z[u][q] = {m2 * x, m2 * y};
+                    }
+                }
+                fft_lines<T, N, -1, PAD, 2>(z, t, L, 2, 1, tw);
+#pragma unroll
+                for (int q = 0; q < 8; q++) z[0][q] = T(0.5) * (z[0][q] + cmulc(z[1][q], phs[q]));
+            } else {
+                fft_line<T, N, +1, PAD>(z[0], t, L, 1, tw);
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const T x = z[0][q].x * inv, y = z[0][q].y * inv;
+                    const T m2 = x * x + y * y;
+                    z[0][q] = {m2 * x, m2 * y};
+                }
             }
             if constexpr (RS) {
                 // the nonlinearity and the site noise through the forward
@@ -1898,7 +1970,7 @@ __global__ void __launch_bounds__(256) k_line1d_cplx(Line1dArgs a)
                 fft_lines<T, N, -1, PAD, 2>(z, t, L, 2, 1, tw);
 #pragma unroll
                 for (int q = 0; q < 8; q++) e[q] = z[1][q];
-            } else {
+            } else if constexpr (!PS) {
                 fft_line<T, N, -1, PAD>(z[0], t, L, 1, tw);
             }
 #pragma unroll

@@ -251,7 +251,7 @@ hipError_t launch_linear(const Geo& g, const Item* items, int nitems, int sub, i
 
 // 1D lattices: one launch takes nsteps steps (MODE_STEP) or draws the initial
 // condition (MODE_IC)
-template <typename T, int N, bool DA, bool RS>
+template <typename T, int N, int DM, bool RS>
 static hipError_t launch_line1d_n(const Geo& g, const Item* items, int nitems, int mode, int sub, int nsteps,
                                   int nl, hipStream_t s)
 {
@@ -267,17 +267,17 @@ static hipError_t launch_line1d_n(const Geo& g, const Item* items, int nitems, i
     if (g.cplx) {
         a.nlines = nitems;
         const dim3 grid((unsigned)((a.nlines + LPB - 1) / LPB));
-        const size_t lds = (size_t)LPB * (RS ? 2 : 1) * LL * sizeof(cx<T>);
-        if (nl == NL_NONE) hipLaunchKernelGGL((k_line1d_cplx<T, N, PAD, DA, 1, RS>), grid, dim3(256), lds, s, a);
-        else hipLaunchKernelGGL((k_line1d_cplx<T, N, PAD, DA, 0, RS>), grid, dim3(256), lds, s, a);
+        const size_t lds = (size_t)LPB * ((RS || DM == 2) ? 2 : 1) * LL * sizeof(cx<T>);
+        if (nl == NL_NONE) hipLaunchKernelGGL((k_line1d_cplx<T, N, PAD, DM, 1, RS>), grid, dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((k_line1d_cplx<T, N, PAD, DM, 0, RS>), grid, dim3(256), lds, s, a);
         return hipGetLastError();
     }
     a.nlines = (nitems + 1) / 2;
     const dim3 grid((unsigned)((a.nlines + LPB - 1) / LPB));
     const size_t lds = (size_t)LPB * 2 * LL * sizeof(cx<T>);
-    if (nl == NL_KPZ) hipLaunchKernelGGL((k_line1d_real<T, N, PAD, DA, 1, RS>), grid, dim3(256), lds, s, a);
-    else if (nl == NL_NONE) hipLaunchKernelGGL((k_line1d_real<T, N, PAD, DA, 2, RS>), grid, dim3(256), lds, s, a);
-    else hipLaunchKernelGGL((k_line1d_real<T, N, PAD, DA, 0, RS>), grid, dim3(256), lds, s, a);
+    if (nl == NL_KPZ) hipLaunchKernelGGL((k_line1d_real<T, N, PAD, DM, 1, RS>), grid, dim3(256), lds, s, a);
+    else if (nl == NL_NONE) hipLaunchKernelGGL((k_line1d_real<T, N, PAD, DM, 2, RS>), grid, dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((k_line1d_real<T, N, PAD, DM, 0, RS>), grid, dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
@@ -286,14 +286,18 @@ hipError_t launch_line1d(const Geo& g, const Item* items, int nitems, int mode, 
                          hipStream_t s)
 {
     if (g.ndim != 1 || nitems <= 0) return hipErrorInvalidValue;
-    if (g.dealias && g.rsn) {
-        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, true, true>(g, items, nitems, mode, sub, nsteps, nl, s)));
-    } else if (g.dealias) {
-        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, true, false>(g, items, nitems, mode, sub, nsteps, nl, s)));
+    // dealias 0 none, 1 the 2/3 rule, 2 phase shift (not with real-space noise)
+    if (g.dealias == 2 && g.rsn) return hipErrorInvalidValue;
+    if (g.dealias == 1 && g.rsn) {
+        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, 1, true>(g, items, nitems, mode, sub, nsteps, nl, s)));
+    } else if (g.dealias == 1) {
+        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, 1, false>(g, items, nitems, mode, sub, nsteps, nl, s)));
+    } else if (g.dealias == 2) {
+        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, 2, false>(g, items, nitems, mode, sub, nsteps, nl, s)));
     } else if (g.rsn) {
-        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, false, true>(g, items, nitems, mode, sub, nsteps, nl, s)));
+        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, 0, true>(g, items, nitems, mode, sub, nsteps, nl, s)));
     } else {
-        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, false, false>(g, items, nitems, mode, sub, nsteps, nl, s)));
+        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, 0, false>(g, items, nitems, mode, sub, nsteps, nl, s)));
     }
     return hipErrorInvalidValue;
 }

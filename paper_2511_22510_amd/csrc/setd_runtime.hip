@@ -56,7 +56,10 @@ setd_status validate(const setd_desc& d)
     if (d.noise_kpow != 0 && d.noise_kpow != 2) return fail(SETD_E_INVAL, "noise_kpow must be 0 or 2");
     if (d.precision != 32 && d.precision != 64) return fail(SETD_E_INVAL, "precision must be 32 or 64");
     if (d.realizations < 1) return fail(SETD_E_INVAL, "realizations must be >= 1");
-    if (d.dealias != 0 && d.dealias != 1) return fail(SETD_E_INVAL, "dealias must be 0 or 1");
+    if (d.dealias < 0 || d.dealias > 2) return fail(SETD_E_INVAL, "dealias must be 0, 1 or 2");
+    if (d.dealias == 2 && d.ndim != 1) return fail(SETD_E_UNSUPPORTED, "phase-shift dealiasing is built for 1D lines");
+    if (d.dealias == 2 && d.noise_space == 1)
+        return fail(SETD_E_UNSUPPORTED, "phase-shift dealiasing is not combined with real-space noise");
     if (d.series_len != 0 && !pow2_in(d.series_len, 8, 1024))
         return fail(SETD_E_INVAL, "series_len must be 0 or a power of two in [8, 1024]");
     if (d.ic_kind != 0 && d.ic_kind != 1) return fail(SETD_E_INVAL, "ic_kind must be 0 or 1");
@@ -103,11 +106,12 @@ setd_status Plan::init(const setd_desc& desc)
         const int n = d.n[i];
         g.n[i] = n;
         if (!g.cplx && i == last) {
-            const int K = d.dealias ? (n - 1) / 3 : n / 2;
+            // 2/3 rule: 3|a| < n; phase shift: the Nyquist mode dropped
+            const int K = d.dealias == 1 ? (n - 1) / 3 : (d.dealias == 2 ? n / 2 - 1 : n / 2);
             g.kept[i] = K + 1;
             g.kp[i] = K;
         } else if (d.dealias) {
-            const int K = (n - 1) / 3;
+            const int K = d.dealias == 1 ? (n - 1) / 3 : n / 2 - 1;
             g.kept[i] = 2 * K + 1;
             g.kp[i] = K;
         } else {
@@ -141,7 +145,8 @@ setd_status Plan::init(const setd_desc& desc)
     for (int i = 1; i < d.ndim; i++)
         if (d.n[i] != d.n[0]) iso = 0;
     int kmax[3] = {0, 0, 0};
-    for (int i = 0; i < d.ndim; i++) kmax[i] = d.dealias ? (d.n[i] - 1) / 3 : d.n[i] / 2;
+    for (int i = 0; i < d.ndim; i++)
+        kmax[i] = d.dealias == 1 ? (d.n[i] - 1) / 3 : (d.dealias == 2 ? d.n[i] / 2 - 1 : d.n[i] / 2);
     if (d.ndim == 1) {
         coef_mode = COEF_SEPARABLE;  // one entry per |a| of the line
         keydim[0] = kmax[0] + 1;

@@ -227,3 +227,33 @@ def test_real_space_noise_limits():
         g.observe(S.OBS_KICK)
     assert e.value.status == S.SETD_E_UNSUPPORTED
     g.close()
+
+
+PS_CASES = [
+    W.model_a([256], precision=64, order=2, realizations=3, dx=0.25, dealias=2),
+    W.model_a([128], precision=32, order=1, realizations=2, dealias=2, ic_kind=1, ic_sigma=0.4),
+    W.kpz([1024], precision=32, order=2, realizations=2, dx=0.5, lam=50.0, D=0.01, h=2e-3, dealias=2),
+    W.kpz([64], precision=64, order=1, realizations=1, dealias=2, ic_kind=1, ic_sigma=0.3),
+    W.cgl([64], precision=64, order=2, realizations=2, dealias=2),
+    W.cgl([256], precision=32, order=1, realizations=1, dealias=2),
+    W.model_b([8], precision=64, order=2, realizations=3, dealias=2),
+]
+
+
+@pytest.mark.parametrize("p", PS_CASES, ids=lambda p: "ps-%s-%d-f%d-o%d-R%d" % (
+    p["nl"], p["n"][0], p["precision"], p["order"], p["realizations"]))
+def test_line_phase_shift_parity(p):
+    """Phase-shift dealiasing on a line: the grid and the grid moved by dx/2
+    through the same stages, their mean against the oracle's two transforms."""
+    err = run_pair(p, steps=60, every=30)
+    say("max rel err", err)
+    assert err <= TOL[p["precision"]]
+
+
+def test_phase_shift_limits():
+    S = _setd()
+    for bad in (W.model_a([32, 32], precision=32, dealias=2),
+                W.model_a([64], precision=32, dealias=2, noise_space=1)):
+        with pytest.raises(S.SetdError) as e:
+            S.Plan(bad)
+        assert e.value.status == S.SETD_E_UNSUPPORTED
