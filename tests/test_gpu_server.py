@@ -46,6 +46,9 @@ MIX = [
     (W.model_a([256], precision=32, realizations=1, seed=110, dx=0.25), 19),
     (W.kpz([128], precision=32, order=2, realizations=2, seed=111, ic_kind=1, ic_sigma=0.2), 21),
     (W.cgl([64], precision=64, realizations=1, seed=112), 15),
+    # line options: their own launch classes
+    (W.model_a([256], precision=32, realizations=2, seed=113, dx=0.25, dealias=2), 17),
+    (W.model_a([256], precision=32, realizations=1, seed=114, dx=0.25, noise_space=1), 23),
 ]
 
 
