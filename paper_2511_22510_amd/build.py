@@ -14,7 +14,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libsetd.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["setd_k32.hip", "setd_k64.hip", "setd_kmisc.hip", "setd_runtime.hip", "setd_server.hip", "setd_sde.hip"]
+SOURCES = ["setd_k32.hip", "setd_k64.hip", "setd_line32.hip", "setd_line64.hip", "setd_kmisc.hip",
+           "setd_runtime.hip", "setd_server.hip", "setd_sde.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -39,7 +40,7 @@ def _compile(src):
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with cf.ThreadPoolExecutor(max_workers=min(len(srcs), 4)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(srcs), 8)) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]

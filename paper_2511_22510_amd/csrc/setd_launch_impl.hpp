@@ -366,7 +366,11 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
     template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, int64_t, hipStream_t); \
     template hipError_t launch_spectrum<T>(const SpecArgs&, int, hipStream_t);                                    \
     template hipError_t launch_boxwidth<T>(const BoxArgs&, size_t, hipStream_t);                                  \
-    template hipError_t launch_line1d<T>(const Geo&, const Item*, int, int, int, int, int, hipStream_t);          \
     template hipError_t launch_hermitian<T>(const Geo&, const Item*, int, int, hipStream_t);
+
+// the 1D line kernels, in translation units of their own (they compile in
+// parallel with the others)
+#define SETD_INSTANTIATE_LINES(T) \
+    template hipError_t launch_line1d<T>(const Geo&, const Item*, int, int, int, int, int, hipStream_t);
 
 }  // namespace setd

@@ -1,0 +1,6 @@
+// Double-precision (complex128) instantiation of the 1D line kernels.
+#include "setd_launch_impl.hpp"
+
+namespace setd {
+SETD_INSTANTIATE_LINES(double)
+}
