@@ -259,9 +259,18 @@ def valu_roofline(names, avg_s, dom):
     passes = []
     for i, nm in enumerate(names):
         c = counts.get(nm)
+        src = nm
+        if c is None:
+            # the autotuner may pick another variant of the kernel than the
+            # counter run did (launch shape only; the counts differ by a few
+            # percent): use that variant's count and name it
+            same = [k for k in counts if k.split("<")[0] == nm.split("<")[0]]
+            if same:
+                src = same[0]
+                c = counts[src]
         rate = c / avg_s[i] if c else None
-        passes.append({"kernel": nm, "valu_insts_per_launch": c, "achieved": rate,
-                       "frac": rate / PEAK_VALU_WINST if rate else None})
+        passes.append({"kernel": nm, "valu_insts_per_launch": c, "counted_variant": src if c else None,
+                       "achieved": rate, "frac": rate / PEAK_VALU_WINST if rate else None})
     return {"bound": "alu", "unit": "wave-instructions/s", "peak": PEAK_VALU_WINST,
             "achieved": passes[dom]["achieved"], "frac": passes[dom]["frac"], "kernel": names[dom],
             "passes": passes}

@@ -42,3 +42,18 @@ def test_valu_roofline_uses_the_issue_peak():
     r = bench.valu_roofline(names, [1e-5, 2e-5], 1)
     assert r["bound"] == "alu" and r["peak"] == 256 * 2.4e9
     assert r["kernel"] == "b"
+
+
+def test_valu_roofline_falls_back_to_a_counted_variant(tmp_path, monkeypatch):
+    f = tmp_path / "valu.txt"
+    monkeypatch.setattr(bench, "VALU_FILE", str(f))
+    _write(f, "source_hash = %s\n"
+              "valu_insts_per_launch k_axis0r<float,512,tile=8> = 2000\n"
+              "valu_insts_per_launch k_row_real<float,512,pad=3,block=256,pair_groups=1> = 1000\n"
+              % bench.kernel_source_hash())
+    names = ["k_row_real<float,512,pad=3,block=64,pair_groups=2>", "k_axis0r<float,512,tile=8>"]
+    r = bench.valu_roofline(names, [1e-5, 2e-5], 1)
+    row, ax = r["passes"]
+    assert row["valu_insts_per_launch"] == 1000
+    assert row["counted_variant"] == "k_row_real<float,512,pad=3,block=256,pair_groups=1>"
+    assert ax["counted_variant"] == names[1] and r["achieved"] == 2000 / 2e-5
