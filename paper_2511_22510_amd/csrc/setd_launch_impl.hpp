@@ -255,7 +255,9 @@ template <typename T, int N, int DM, bool RS>
 static hipError_t launch_line1d_n(const Geo& g, const Item* items, int nitems, int mode, int sub, int nsteps,
                                   int nl, hipStream_t s)
 {
-    constexpr int TPL = N / 8, LPB = 256 / TPL, PAD = 0;
+    // FP32 lines pad LDS by one slot per 8 (fewer bank conflicts in the
+    // exchanges); FP64 lines would exceed 64 KiB of LDS with it
+    constexpr int TPL = N / 8, LPB = 256 / TPL, PAD = sizeof(T) == 4 ? 3 : 0;
     constexpr int LL = lds_len<N, PAD>();
     Line1dArgs a;
     a.g = g;

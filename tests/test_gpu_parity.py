@@ -248,7 +248,8 @@ def test_split_streams_match_one_stream(p, monkeypatch):
 
 @pytest.mark.parametrize("split", ["1", "2"])
 @pytest.mark.parametrize("p", [W.model_b([64, 64], precision=32, realizations=5),
-                               W.cgl([32, 32, 32], precision=64, realizations=3)])
+                               W.cgl([32, 32, 32], precision=64, realizations=3),
+                               W.kpz([256], precision=32, order=2, realizations=3)])
 def test_graph_replays_match_eager_launches(p, split, monkeypatch):
     """setd_step replays a captured graph of 4 steps: every replay, with eager
     steps, field reads and observables between replays, gives bitwise the
