@@ -257,3 +257,22 @@ def test_phase_shift_limits():
         with pytest.raises(S.SetdError) as e:
             S.Plan(bad)
         assert e.value.status == S.SETD_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("name", ["LINE_MODEL_A", "LINE_KPZ"])
+def test_line_workloads_full_size_sampled(name):
+    """The 1D workloads bench.py times (16,384 and 4,096 realizations), in one
+    fused launch of 256 steps: the first, a middle and the last realization
+    against the oracle."""
+    S = _setd()
+    p = W.problem(getattr(W, name))
+    R = p["realizations"]
+    g = S.Plan(p)
+    g.step(256)
+    for r in (0, R // 2 + 1, R - 1):
+        o = O.Sim(p, r_first=r, r_count=1)
+        o.step(256)
+        err = relerr(g.get(r), o.get(0))
+        say(name, "realization", r, "rel err", err)
+        assert err <= TOL[p["precision"]]
+    g.close()
