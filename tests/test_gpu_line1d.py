@@ -171,14 +171,17 @@ def test_line_spectrum_window_matches_oracle():
     g.close()
 
 
-def test_line_stationary_spectrum_of_the_paper_figure():
+@pytest.mark.parametrize("model", ["A", "B"])
+def test_line_stationary_spectrum_of_the_paper_figure(model):
     """Sec. 5, Model A/B on a line (u = 0, N = 256, L = 64, D = 0.1, h = 0.01):
     the equal-time correlation relaxes to D/(r + k^2); from phi = 0 after
-    t = n h the exact mode variance is (N^2/L) D (1 - e^{2ct})/(-c)."""
+    t = n h the exact value is D_k (1 - e^{2ct})/(-c) with c = -(r + k^2),
+    D_k = D (Model A) and c = -k^2 (r + k^2), D_k = D k^2 (Model B)."""
     S = _setd()
     r, D, h, R = 1.0, 0.1, 0.01, 512
-    p = W.model_a([256], r=r, u=0.0, T=D, h=h, dx=0.25, order=1, ic_kind=0, realizations=R,
-                  precision=32, seed=3)
+    mk = W.model_a if model == "A" else W.model_b
+    p = mk([256], r=r, u=0.0, T=D, h=h, dx=0.25, order=1, ic_kind=0, realizations=R,
+           precision=32, seed=3)
     g = S.Plan(p)
     nsteps = 400
     g.step(nsteps)
@@ -186,9 +189,11 @@ def test_line_stationary_spectrum_of_the_paper_figure():
     sk = g.observe(S.OBS_SK)[:nb]
     L, N = 64.0, 256
     k = 2 * np.pi / L * np.arange(nb)
-    c = -(r + k**2)
+    c = -(r + k**2) if model == "A" else -k**2 * (r + k**2)
+    Dk = D if model == "A" else D * k**2
     K = (N - 1) // 3
-    want = D * (1 - np.exp(2 * c * nsteps * h)) / (-c)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        want = Dk * (1 - np.exp(2 * c * nsteps * h)) / (-c)
     # shells 1..K hold the modes +-a: 2 R samples of |phi_a|^2 each
     z = (sk[1:K + 1] / want[1:K + 1] - 1) / np.sqrt(1.0 / R)
     say("line S(k) z max", float(np.max(np.abs(z))))
