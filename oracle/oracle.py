@@ -62,6 +62,7 @@ def lib():
         L.orc_sde_run.argtypes = [ctypes.POINTER(_SdeDesc), dp, dp]
         L.orc_series_start.argtypes = [vp, ctypes.c_int]
         L.orc_spectrum.argtypes = [vp, dp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.orc_fdt.argtypes = [vp, dp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
         L.orc_phi12.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         L.orc_phi12.restype = None
         L.orc_create_subset.argtypes = [ctypes.POINTER(_Desc), ctypes.c_int, ctypes.c_int]
@@ -302,6 +303,15 @@ class Sim:
             raise RuntimeError("oracle spectrum failed")
         return (out[:nb * M].reshape(nb, M), out[nb * M:2 * nb * M].reshape(nb, M),
                 out[2 * nb * M:3 * nb * M].reshape(nb, M), out[3 * nb * M:])
+
+    def fdt(self):
+        """(average absolute, signed average) FDT deviation of the recorded
+        window over all modes and frequencies (Sec. 5)."""
+        out = np.zeros(2)
+        ln = ctypes.c_size_t(0)
+        if lib().orc_fdt(self._h, _dptr(out), out.size, ctypes.byref(ln)) != 0:
+            raise RuntimeError("oracle FDT failed")
+        return float(out[0]), float(out[1])
 
     def step_xi(self, xi):
         a = np.ascontiguousarray(xi, dtype=np.complex128).reshape((self.R,) + self.spec_shape)

@@ -906,6 +906,66 @@ int orc_spectrum(orc_sim* s, double* out, size_t cap, size_t* len)
     return 0;
 }
 
+/* FDT check of Sec. 5 (App. C estimators): per mode a and frequency w_b of
+   the completed window, the deviation Delta_{a,b} = 2 Im chi - (w_b/D_a) C
+   of the ensemble means over the realizations, with C and chi as in
+   orc_spectrum (here per mode, not per shell) and w_b = 2 pi b/T, b signed in
+   FFT order (b = M/2 taken as -M/2).  With chi normalised by 1/(2 D_a) the
+   relation holds with D_a = D k^kpow per mode.  out[0] = the average absolute
+   deviation over all N^d modes and M frequencies (an interior mode of a real
+   field stands for -a too: Delta_{-a,b} = -Delta_{a,-b}, so it counts twice),
+   out[1] = the signed average.  Modes with G_a = 0 or D_a = 0 contribute 0. */
+int orc_fdt(orc_sim* s, double* out, size_t cap, size_t* len)
+{
+    const orc_desc* d = &s->d;
+    const int M = s->series_len;
+    if (!s->series || s->series_pos < M || s->d.noise_space || cap < 2) return -1;
+    double vol = 1.0;
+    for (int i = 0; i < d->ndim; i++) vol *= (d->n[i] * d->dx) / ((double)d->n[i] * (double)d->n[i]);
+    cplx* ph = (cplx*)malloc(sizeof(cplx) * M);
+    cplx* xi = (cplx*)malloc(sizeof(cplx) * M);
+    double* dlt = (double*)malloc(sizeof(double) * M);
+    double sabs = 0.0, ssgn = 0.0;
+    for (size_t e = 0; e < s->nspec; e++) {
+        if (!s->mask[e] || !(s->G[e] > 0)) continue;
+        const double Da = d->noise_D * (d->noise_kpow == 2 ? s->k2[e] : 1.0);
+        if (!(Da > 0)) continue;
+        const double w = mode_weight(s, e);
+        for (int b = 0; b < M; b++) dlt[b] = 0.0;
+        for (int rr = 0; rr < s->R; rr++) {
+            for (int m = 0; m < M; m++) {
+                ph[m] = s->series[((size_t)m * s->R + rr) * s->nspec + e];
+                xi[m] = s->G[e] * noise_eta(s, e, s->series_step0 + m, (uint32_t)(s->r_first + rr));
+            }
+            for (int b = 0; b < M; b++) {
+                cplx pb = 0, xb = 0;
+                for (int m = 0; m < M; m++) {
+                    const cplx z = cexp(I * 2.0 * M_PI * (double)(((int64_t)b * m) % M) / (double)M);
+                    pb += z * ph[m];
+                    xb += z * xi[m];
+                }
+                const int bs = (2 * b < M) ? b : b - M;
+                const double wh = 2.0 * M_PI * bs / (double)M;   /* w_b h */
+                const double c2 = creal(pb) * creal(pb) + cimag(pb) * cimag(pb);
+                const double im = cimag(pb * conj(xb));
+                /* 2 Im chi - (w/D_a) C with chi = vol/(2 D_a M) phi conj(xi),
+                   C = vol h/M |phi|^2, both means over the realizations */
+                dlt[b] += vol / (Da * M) * (im - wh * c2) / s->R;
+            }
+        }
+        for (int b = 0; b < M; b++) {
+            sabs += w * fabs(dlt[b]);
+            if (w == 1.0) ssgn += dlt[b];
+        }
+    }
+    const double denom = (double)s->nreal * (double)M;
+    out[0] = sabs / denom;
+    out[1] = ssgn / denom;
+    *len = 2;
+    free(ph); free(xi); free(dlt);
+    return 0;
+}
+
 int orc_step_xi(orc_sim* s, const double* xi)
 {
     return step_once(s, (const cplx*)xi);

@@ -99,3 +99,48 @@ def test_spectrum_needs_a_full_window():
     s.step(3)
     with pytest.raises(RuntimeError):
         s.spectrum()
+
+
+def _exact_fdt(N, dx, r, D, h, M):
+    """Average |E Delta_{a,b}| and signed average E Delta of linear Model A in
+    the stationary state, from the exact window expectations of |phi_b|^2 and
+    phi_b conj xi_b (SETD1 is the exact OU transition)."""
+    L = N * dx
+    vol, lat = L / (N * N), N * N / L
+    d = np.arange(1, M)
+    sabs = ssgn = 0.0
+    for a in range(-N // 2, N // 2):
+        k = 2 * np.pi * a / L
+        c = -(r + k * k)
+        E = np.exp(c * h)
+        G2 = lat * D * np.expm1(2 * c * h) / c
+        C0 = G2 / (1 - E * E)
+        for b in range(M):
+            bs = b if 2 * b < M else b - M
+            th = 2 * np.pi * b / M
+            phib2 = C0 * (M + 2 * np.real(np.sum((M - d) * (E * np.exp(1j * th)) ** d)))
+            cross = G2 * np.sum((M - d) * np.exp(1j * th * d) * E ** (d - 1))
+            delta = vol / (D * M) * (cross.imag - 2 * np.pi * bs / M * phib2)
+            sabs += abs(delta)
+            ssgn += delta
+    return sabs / (N * M), ssgn / (N * M)
+
+
+def test_fdt_deviation_matches_the_exact_window_expectation():
+    """FDT check (Sec. 5): per mode and frequency Delta = 2 Im chi - (w/D) C of
+    the ensemble means.  For linear Model A the estimators' exact window
+    expectations give E Delta (the finite window and step bias); with 96
+    realizations the statistical part is small beside it, so the average
+    |Delta| over all modes and frequencies lands on the average |E Delta|."""
+    N, dx, r, D, h, M, R = 32, 1.0, 1.0, 0.5, 0.1, 128, 96
+    p = W.model_a([N], r=r, u=0.0, T=D, nl="none", h=h, order=1, ic_kind=0, realizations=R, dealias=0,
+                  seed=5, dx=dx)
+    s = O.Sim(p)
+    s.step(100)   # t = 10 >> 1/|c|: stationary
+    s.series_start(M)
+    s.step(M - 1)
+    got_abs, got_sgn = s.fdt()
+    want_abs, want_sgn = _exact_fdt(N, dx, r, D, h, M)
+    assert got_abs == pytest.approx(want_abs, rel=0.03)
+    # the signed average is a sum of cancelling terms: compare on the scale of |Delta|
+    assert abs(got_sgn - want_sgn) < 0.03 * want_abs
