@@ -109,13 +109,22 @@ typedef enum {
                                  -w_b); b in FFT order, w_b = 2 pi b / T.
                                  out: [C (nbins x M), Re chi (nbins x M),
                                  Im chi (nbins x M), count (nbins)]              */
-    SETD_OBS_BOXWIDTH = 11    /* box-averaged width (Sec. 5 KPZ): for l = 2, 4, ..,
+    SETD_OBS_BOXWIDTH = 11,   /* box-averaged width (Sec. 5 KPZ): for l = 2, 4, ..
                                  N (equal n[i] = N) the sqrt of the ensemble mean,
                                  over the N^d/l^d boxes of l^d sites, of the
                                  variance of the field within the box (complex
                                  field: of |phi - box mean|^2).  Computed from the
                                  spectrum without a transform.
                                  out: [w_2, w_4, .., w_N] (log2 N values)        */
+    SETD_OBS_FDT = 12         /* FDT check of Sec. 5 on the completed window: per
+                                 mode a and frequency w_b the deviation
+                                 Delta = 2 Im chi - (w_b / D_a) C of the ensemble
+                                 means (chi with 1/(2 D_a), as for
+                                 SETD_OBS_SPECTRUM; b signed, M/2 taken as -M/2),
+                                 averaged over all prod n_i modes (an interior
+                                 mode of a real field also stands for -a) and
+                                 the M frequencies.
+                                 out: [mean |Delta|, mean Delta]                  */
 } setd_obs_kind;
 
 /*

@@ -2247,6 +2247,14 @@ __global__ void __launch_bounds__(256) k_spectrum(SpecArgs a)
         const double px = v[0][q].x, py = v[0][q].y, xx = v[1][q].x, xy = v[1][q].y;
         double c2 = px * px + py * py;
         double xr = px * xx + py * xy, xi = py * xx - px * xy;   // phi conj(xi)
+        if (a.dacc) {
+            // FDT check (Sec. 5): 2 Im chi - (w_b / D_a) C of this mode (its own
+            // frequencies; the mirror of an interior mode is counted at the end),
+            // w_b h = 2 pi b / M with b signed
+            const int bs = (2 * b < M) ? b : b - M;
+            const double wh = 6.283185307179586476925 * (double)bs / (double)M;
+            atomicAdd(&a.dacc[(size_t)idx * M + b], a.vol / (Da * M) * invR * (xi - wh * c2));
+        }
         if (w == 2.0) {
             const int bm = (M - b) & (M - 1);
             const cx<T> pm = L[lds_slot<PAD>(bm)], km = L[LL + lds_slot<PAD>(bm)];
@@ -2260,6 +2268,39 @@ __global__ void __launch_bounds__(256) k_spectrum(SpecArgs a)
         atomicAdd(&a.acc[((size_t)2 * nb + shell) * M + b], cX * xi);
     }
     if (blockIdx.y == 0 && t == 0) atomicAdd(&a.acc[(size_t)3 * nb * M + shell], w);
+}
+
+// Sums of the FDT deviations: out[0] += w |Delta|, out[1] += Delta of the modes
+// stored with their partner (w = 1); an interior mode of a real field stands
+// for -a as well, whose deviations are -Delta_{a,-b}.
+static __global__ void __launch_bounds__(256) k_fdt_reduce(Geo g, const double* dacc, int total, int M, double* out)
+{
+    __shared__ double ra[256], rs[256];
+    double sa = 0.0, ss = 0.0;
+    const int last = g.ndim - 1;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)total * M;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int col = (int)((i / (size_t)M) % (size_t)g.pitch);
+        if (col >= g.kept[last]) continue;
+        const double v = dacc[i];
+        const bool twice = !g.cplx && col > 0 && 2 * col < g.n[last];
+        sa += (twice ? 2.0 : 1.0) * fabs(v);
+        if (!twice) ss += v;
+    }
+    ra[threadIdx.x] = sa;
+    rs[threadIdx.x] = ss;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            ra[threadIdx.x] += ra[threadIdx.x + st];
+            rs[threadIdx.x] += rs[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], ra[0]);
+        atomicAdd(&out[1], rs[0]);
+    }
 }
 
 }  // namespace setd

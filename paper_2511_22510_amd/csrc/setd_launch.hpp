@@ -46,6 +46,9 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
 // time-frequency observables of a recorded window (M a power of two in [8, 1024])
 template <typename T>
 hipError_t launch_spectrum(const SpecArgs& a, int M, hipStream_t s);
+// sums of |Delta| and Delta of the per-mode FDT deviations
+template <typename T>
+hipError_t launch_fdt_reduce(const Geo& g, const double* dacc, int total, int M, double* out, hipStream_t s);
 // 1D lattices: nsteps steps per launch (MODE_STEP) or the initial condition (MODE_IC)
 template <typename T>
 hipError_t launch_line1d(const Geo& g, const Item* items, int nitems, int mode, int sub, int nsteps, int nl,

@@ -339,6 +339,15 @@ hipError_t launch_spectrum(const SpecArgs& a, int M, hipStream_t s)
 }
 
 template <typename T>
+hipError_t launch_fdt_reduce(const Geo& g, const double* dacc, int total, int M, double* out, hipStream_t s)
+{
+    size_t blocks = ((size_t)total * M + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_fdt_reduce, dim3((unsigned)blocks), dim3(256), 0, s, g, dacc, total, M, out);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind, int nbins, double vol,
                           double* acc, int64_t kick, hipStream_t s)
 {
@@ -367,6 +376,7 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
     template hipError_t launch_linear<T>(const Geo&, const Item*, int, int, int, int64_t, hipStream_t);         \
     template hipError_t launch_observe<T>(const Geo&, const Item*, int, int, int, double, double*, int64_t, hipStream_t); \
     template hipError_t launch_spectrum<T>(const SpecArgs&, int, hipStream_t);                                    \
+    template hipError_t launch_fdt_reduce<T>(const Geo&, const double*, int, int, double*, hipStream_t);         \
     template hipError_t launch_boxwidth<T>(const BoxArgs&, size_t, hipStream_t);                                  \
     template hipError_t launch_hermitian<T>(const Geo&, const Item*, int, int, hipStream_t);
 

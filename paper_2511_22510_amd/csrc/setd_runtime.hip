@@ -235,6 +235,7 @@ setd_status Plan::init(const setd_desc& desc)
     }
     if (d.series_len > 0) {
         lay.specacc = take(((size_t)3 * nbins * d.series_len + nbins) * 8);
+        lay.fdtacc = take(S * (size_t)d.series_len * 8);
         lay.series = take((size_t)d.series_len * R * Sb);
     }
     lay.total = off;
@@ -986,6 +987,53 @@ setd_status Plan::observe(int kind, double* out, size_t cap, size_t* len)
             out[j - 1] = std::sqrt(v > 0.0 ? v : 0.0);
         }
         *len = (size_t)J;
+        int f = 0;
+        if ((st = nonfinite_any(&f)) != SETD_OK) return st;
+        return f ? fail(SETD_E_NONFINITE, "a realization produced a non-finite value") : SETD_OK;
+    }
+    case SETD_OBS_FDT: {
+        const int M = d.series_len;
+        if (g.rsn) return fail(SETD_E_UNSUPPORTED, "the kick estimators regenerate Fourier-space noise");
+        if (M <= 0 || series_pos < M) return fail(SETD_E_INVAL, "no complete time series window");
+        if (cap < 2) return fail(SETD_E_INVAL, "output needs 2 doubles");
+        const size_t nsum = (size_t)3 * nb * M + nb;
+        double* sacc = reinterpret_cast<double*>(ws + lay.specacc);
+        double* dacc = reinterpret_cast<double*>(ws + lay.fdtacc);
+        SETD_HIP(launch_fill64(sacc, (int64_t)nsum, 0.0, stream));
+        SETD_HIP(launch_fill64(dacc, (int64_t)(S * (size_t)M), 0.0, stream));
+        SETD_HIP(launch_fill64(acc, 2, 0.0, stream));
+        SpecArgs sa{};
+        sa.g = g;
+        sa.items = items_dev;
+        sa.nitems = R;
+        sa.nbins = nb;
+        sa.total = (int)(S);
+        sa.series = ws + lay.series;
+        sa.slot = (size_t)R * Sb;
+        sa.rstride = Sb;
+        sa.tw = ws + ((d.precision == 32) ? lay.twm32 : lay.twm64);
+        sa.step0 = series_step0;
+        sa.vol = vol;
+        sa.h = d.h;
+        sa.D = d.noise_D;
+        sa.kpow = d.noise_kpow;
+        sa.acc = sacc;
+        sa.dacc = dacc;
+        if (d.precision == 32) {
+            SETD_HIP((launch_spectrum<float>(sa, M, stream)));
+            SETD_HIP((launch_fdt_reduce<float>(g, dacc, (int)S, M, acc, stream)));
+        } else {
+            SETD_HIP((launch_spectrum<double>(sa, M, stream)));
+            SETD_HIP((launch_fdt_reduce<double>(g, dacc, (int)S, M, acc, stream)));
+        }
+        double sums[2];
+        SETD_HIP(hipMemcpyAsync(sums, acc, sizeof sums, hipMemcpyDeviceToHost, stream));
+        SETD_HIP(hipStreamSynchronize(stream));
+        // averages over all prod n_i modes and M frequencies
+        const double denom = (double)nreal * (double)M;
+        out[0] = sums[0] / denom;
+        out[1] = sums[1] / denom;
+        *len = 2;
         int f = 0;
         if ((st = nonfinite_any(&f)) != SETD_OK) return st;
         return f ? fail(SETD_E_NONFINITE, "a realization produced a non-finite value") : SETD_OK;

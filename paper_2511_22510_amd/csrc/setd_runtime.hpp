@@ -27,7 +27,7 @@ struct Layout {
     size_t tw64[3] = {0, 0, 0}, tw32[3] = {0, 0, 0};
     size_t acc = 0, skacc = 0, out = 0;
     size_t phi = 0, prev = 0, pre0 = 0, pre1 = 0, big = 0, snap = 0;
-    size_t twm64 = 0, twm32 = 0, specacc = 0, series = 0;   // time series (series_len > 0)
+    size_t twm64 = 0, twm32 = 0, specacc = 0, series = 0, fdtacc = 0;   // time series (series_len > 0)
     size_t boxcls = 0, boxn = 0;  // box-width class sums and their count (equal n[i])
     size_t total = 0;
 };

@@ -102,6 +102,7 @@ struct SpecArgs {
     double vol, h, D;             // prod L_i / N_i^2, step, D of D(k) = D k^kpow
     int kpow;
     double* acc;                  // [3][nbins][M] sums, then [nbins] mode counts
+    double* dacc;                 // null, or [total][M]: the FDT deviation per mode and frequency
 };
 
 // arguments of the box-averaged width: class sums of one realization

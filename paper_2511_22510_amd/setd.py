@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "SETD_OK", -1: "SETD_E_INVAL", -2: "SETD_E_NOMEM", -3: "SETD_
 NL = {"phi3": 0, "phi3_cons": 1, "kpz": 2, "cgl": 3, "none": 4}
 
 OBS_SK, OBS_WIDTH, OBS_SNAPSHOT, OBS_TWOTIME, OBS_STEP, OBS_SK_ACCUM, OBS_SK_MEAN, OBS_KICK, OBS_RESPONSE, \
-    OBS_SERIES_START, OBS_SPECTRUM, OBS_BOXWIDTH = range(12)
+    OBS_SERIES_START, OBS_SPECTRUM, OBS_BOXWIDTH, OBS_FDT = range(13)
 
 
 class setd_desc(ctypes.Structure):
@@ -428,6 +428,12 @@ class Plan:
         out = self.observe(OBS_SPECTRUM)
         return (out[:nb * M].reshape(nb, M), out[nb * M:2 * nb * M].reshape(nb, M),
                 out[2 * nb * M:3 * nb * M].reshape(nb, M), out[3 * nb * M:3 * nb * M + nb])
+
+    def fdt(self):
+        """(mean |Delta|, mean Delta): the FDT deviation of the completed
+        window over all modes and frequencies (SETD_OBS_FDT)."""
+        out = self.observe(OBS_FDT)
+        return float(out[0]), float(out[1])
 
     def box_width(self):
         """[w_2, w_4, .., w_N]: the box-averaged widths (SETD_OBS_BOXWIDTH)."""

@@ -338,6 +338,32 @@ def test_spectrum_matches_oracle(p, M):
     g.close()
 
 
+@pytest.mark.parametrize("p,M", [(W.model_a([32], r=1.0, u=0.0, T=0.5, nl="none", h=0.1, realizations=24,
+                                          dealias=0, ic_kind=0, seed=5), 128),
+                                 (W.model_a([32, 32], precision=64, realizations=3, order=2), 16),
+                                 (W.model_b([32, 32], precision=32, realizations=2), 32),
+                                 (W.cgl([16, 16, 16], precision=64, realizations=2), 8)])
+def test_fdt_deviation_matches_oracle(p, M):
+    """FDT check of Sec. 5 on a window: the device adds each realization's
+    per-mode deviation in FP64 and sums |Delta| over modes and frequencies;
+    the oracle forms the per-mode ensemble means directly."""
+    S = _setd()
+    g = S.Plan(dict(p, series_len=M))
+    o = O.Sim(p)
+    g.step(6)
+    o.step(6)
+    g.observe(S.OBS_SERIES_START)
+    o.series_start(M)
+    g.step(M - 1)
+    o.step(M - 1)
+    a, b = g.fdt(), o.fdt()
+    tol = 1e-10 if p["precision"] == 64 else 1e-3
+    say("fdt", p["nl"], p["n"], "f%d" % p["precision"], a, b)
+    assert a[0] == pytest.approx(b[0], rel=tol)
+    assert abs(a[1] - b[1]) <= tol * b[0]
+    g.close()
+
+
 @pytest.mark.parametrize("p", [W.model_a([64, 64], precision=64, realizations=3, order=2),
                                W.kpz([32, 32], precision=32, realizations=2, dealias=0, ic_kind=1, ic_sigma=0.2),
                                W.kpz([64, 64], precision=64, realizations=2, ic_kind=1, ic_sigma=0.3),
