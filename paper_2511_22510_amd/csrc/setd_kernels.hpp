@@ -1860,7 +1860,10 @@ __global__ void __launch_bounds__(256) k_line1d_cplx(Line1dArgs a)
     const int tid = threadIdx.x;
     const int l = tid / TPL, t = tid - l * TPL;
     const int line = blockIdx.x * LPB + l;
-    cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw) + (size_t)l * 2 * LL;
+    // one line of LDS per line, two where a second line shares the stages
+    // (the launcher sizes the allocation the same way)
+    constexpr int LSTR = (RS || PS) ? 2 * LL : LL;
+    cx<T>* L = reinterpret_cast<cx<T>*>(smem_raw) + (size_t)l * LSTR;
     const bool valid = line < a.nlines;
     const Item& it = a.items[valid ? line : 0];
     const bool act = valid && a.sub < it.steps;

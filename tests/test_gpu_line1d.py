@@ -70,6 +70,10 @@ CASES = [
     W.cgl([8], precision=64, order=2, realizations=1, dealias=0),
     W.model_a([128], precision=64, nl="none", u=0.0, r=0.5, realizations=3),
     W.cgl([128], precision=64, nl="none", realizations=2),
+    # every line slot of a workgroup in use (32 lines of N = 64, 4 of N = 512)
+    W.cgl([64], precision=64, order=2, realizations=40, seed=23),
+    W.cgl([512], precision=32, order=1, realizations=6, seed=24),
+    W.model_a([64], precision=64, order=2, realizations=70, seed=25),
 ]
 
 
@@ -281,3 +285,33 @@ def test_line_workloads_full_size_sampled(name):
         say(name, "realization", r, "rel err", err)
         assert err <= TOL[p["precision"]]
     g.close()
+
+
+def test_cgl_line_fluctuations_follow_the_linear_theory():
+    """Sec. 5 CGL about the uniform state (b = 0, q = 0, small D) on lines,
+    1024 realizations in FP32: S(k) equals half of Eq. cgle-cet (the reading
+    that makes its large-k limit the OU variance D/k^2)."""
+    S = _setd()
+    N, dx, D, c, h, R, nsnap = 64, 0.25, 0.01, 0.1, 0.02, 1024, 20
+    p = W.cgl([N], alpha=0.0, beta=c, T=D, dx=dx, h=h, order=2, realizations=R, ic_kind=0, dealias=1,
+              precision=32, seed=19)
+    g = S.Plan(p)
+    one = np.zeros(W.spectral_shape(p), dtype=complex)
+    one[0] = N
+    for r in range(R):
+        g.set(r, one)
+    g.step(2500)
+    for _ in range(nsnap):
+        g.step(50)
+        g.observe(S.OBS_SK_ACCUM)
+    sk = g.observe(S.OBS_SK_MEAN)[:g.nbins]
+    g.close()
+    k = 2 * np.pi / (N * dx) * np.arange(len(sk))
+    K = (N - 1) // 3
+    cet = 2 * D * (k**2 + 1) * (k**4 + 2 * k**2 + 1 + c * c) / (k**2 * (k**6 + 4 * k**4 + 5 * k**2 + 2) + 1e-300)
+    ratio = sk[1:K + 1] / (cet[1:K + 1] / 2)
+    se = 1.0 / np.sqrt(2 * R * nsnap)
+    fast = k[1:K + 1] >= 1.0
+    say("CGL line S(k)/(C_ET/2): fast max dev", float(np.max(np.abs(ratio[fast] - 1))), "mean", float(np.mean(ratio[fast])))
+    assert np.max(np.abs(ratio[fast] - 1)) < 5 * se + 0.01
+    assert np.max(np.abs(ratio[~fast] - 1)) < 0.1

@@ -378,3 +378,42 @@ def test_phase_shift_dealiasing_is_alias_free_on_a_line(kind):
 def test_phase_shift_is_lines_only():
     with pytest.raises(Exception):
         O.Sim(W.model_a([16, 16], dealias=2))
+
+
+def _cgl_line_cet(p, R, nsnap, gap, settle):
+    s = O.Sim(p)
+    N = p["n"][0]
+    one = np.zeros(s.spec_shape, dtype=complex)
+    one[0] = N                      # the uniform state A = 1 (R = 1, q = 0)
+    for r in range(R):
+        s.set(r, one)
+    s.step(settle)
+    for _ in range(nsnap):
+        s.step(gap)
+        s.observe(O.OBS_SK_ACCUM)
+    return s.observe(O.OBS_SK_MEAN)[:s.nbins]
+
+
+def test_cgl_line_fluctuations_follow_the_linear_theory():
+    """Sec. 5 CGL, linear fluctuating theory about the uniform state (b = 0,
+    q = 0, R = 1, small D): the equal-time correlation of u = A e^{i Omega t} - 1
+    has the closed form of Eq. cgle-cet, whose large-k limit 2D/k^2 is twice the
+    OU variance D/k^2 of a mode that relaxes at rate k^2 under noise sqrt(2D) eta
+    with <|eta|^2> = 1; with that reading S(k) = C_ET(k)/2 on every shell.  The
+    uniform state's own modes (a != 0) carry u, so S(k) of phi is that of u."""
+    N, dx, D, c, h, R, nsnap = 64, 0.25, 0.01, 0.1, 0.02, 64, 20
+    p = W.cgl([N], alpha=0.0, beta=c, T=D, dx=dx, h=h, order=2, realizations=R, ic_kind=0, dealias=1,
+              precision=64, seed=9)
+    sk = _cgl_line_cet(p, R, nsnap, 50, 2500)
+    k = 2 * np.pi / (N * dx) * np.arange(len(sk))
+    K = (N - 1) // 3
+    cet = 2 * D * (k**2 + 1) * (k**4 + 2 * k**2 + 1 + c * c) / (k**2 * (k**6 + 4 * k**4 + 5 * k**2 + 2) + 1e-300)
+    ratio = sk[1:K + 1] / (cet[1:K + 1] / 2)
+    # snapshots one time unit apart: nearly independent for k >= 1 (rate k^2);
+    # per shell 2R exponential samples per snapshot
+    se = 1.0 / np.sqrt(2 * R * nsnap)
+    fast = k[1:K + 1] >= 1.0
+    assert np.max(np.abs(ratio[fast] - 1)) < 5 * se + 0.01
+    assert abs(np.mean(ratio[fast]) - 1) < 5 * se / np.sqrt(fast.sum()) + 0.01
+    # the slow phase modes relax over 1/k^2 time units: looser
+    assert np.max(np.abs(ratio[~fast] - 1)) < 0.25
