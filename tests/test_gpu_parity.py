@@ -352,10 +352,16 @@ def test_fdt_deviation_matches_oracle(p, M):
     o = O.Sim(p)
     g.step(6)
     o.step(6)
+    with pytest.raises(S.SetdError):
+        g.fdt()   # no window yet
     g.observe(S.OBS_SERIES_START)
     o.series_start(M)
-    g.step(M - 1)
-    o.step(M - 1)
+    g.step(M - 2)
+    o.step(M - 2)
+    with pytest.raises(S.SetdError):
+        g.fdt()   # one sample short
+    g.step(1)
+    o.step(1)
     a, b = g.fdt(), o.fdt()
     tol = 1e-10 if p["precision"] == 64 else 1e-3
     say("fdt", p["nl"], p["n"], "f%d" % p["precision"], a, b)
