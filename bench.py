@@ -292,7 +292,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(realizations shard across GPUs without communication; see DESIGN.md)", file=sys.stderr)
+              "(realizations would shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
