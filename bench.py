@@ -291,7 +291,7 @@ def main():
                     help="first copy 512 MiB device-to-device (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(realizations would shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
