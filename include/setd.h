@@ -47,7 +47,7 @@ typedef enum {
     SETD_E_NONFINITE = -4,    /* a realization produced NaN/Inf (Sec. 2 warns of
                                  blow-up of explicit schemes); data still returned */
     SETD_E_BUSY = -5,         /* job not finished yet                            */
-    SETD_E_UNSUPPORTED = -6,  /* valid physics this build does not run           */
+    SETD_E_UNSUPPORTED = -6,  /* valid physics the library does not run           */
     SETD_E_STATE = -7         /* call out of order (e.g. step before bind)       */
 } setd_status;
 
