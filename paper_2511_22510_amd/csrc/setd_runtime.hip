@@ -590,6 +590,9 @@ setd_status Plan::autotune()
         Knob& kb = knobs[k];
         float best = 1e30f;
         int best_v = kb.first;
+        // two rounds over the variants, each variant's best kept: a slow
+        // outlier of one timing does not decide the choice
+        for (int round = 0; round < 2 && st == SETD_OK; round++)
         for (int v = kb.first; v < kb.nvar && st == SETD_OK; v++) {
             *kb.var = v;
             auto run = [&]() -> setd_status {
