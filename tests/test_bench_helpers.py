@@ -57,3 +57,12 @@ def test_valu_roofline_falls_back_to_a_counted_variant(tmp_path, monkeypatch):
     assert row["valu_insts_per_launch"] == 1000
     assert row["counted_variant"] == "k_row_real<float,512,pad=3,block=256,pair_groups=1>"
     assert ax["counted_variant"] == names[1] and r["achieved"] == 2000 / 2e-5
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
