@@ -523,3 +523,46 @@ def test_every_kernel_variant_matches_oracle(variant, history, monkeypatch):
         err = run_pair(p, steps=12, every=6)
         say("variant", variant, "history", history, p["nl"], p["n"], "err", err)
         assert err <= TOL[p["precision"]]
+
+
+def test_full_configurations_run_to_completion():
+    """The 2D/3D workloads at their full sizes and step counts: Model B 512^2 x 64
+    for 10^4 steps keeps every realization's conserved a = 0 mode (c(0) = 0,
+    D(0) = 0 and F_0 = 0 by the k^2 factor; the carry storage takes the state
+    through an FP32 transform pair every step, so the mode random-walks by
+    rounding: within 1e-4 of its column's rms after 10^4 steps, where a
+    systematic drift of one rounding per step would reach 6e-4); KPZ 1024^2 x 16 for
+    5 10^4 steps stays finite with a growing width; CGL 256^3 x 4 for 2 10^4
+    steps stays finite and reaches |A|^2 of order 1 (Parseval over the
+    spectrum)."""
+    S = _setd()
+    p = W.problem(W.CONFIG_B)
+    g = S.Plan(p)
+    a0 = [g.get(r)[0, 0] for r in range(p["realizations"])]
+    g.step(W.CONFIG_B["steps"])
+    st = g.observe(S.OBS_STEP)
+    assert st[0] == W.CONFIG_B["steps"] and st[1] == 0
+    for r in range(p["realizations"]):
+        x = g.get(r)
+        col = float(np.sqrt(np.mean(np.abs(x[:, 0]) ** 2)))   # scale of the rounding in its transforms
+        assert abs(x[0, 0] - a0[r]) <= 1e-4 * col
+    g.close()
+    p = W.problem(W.CONFIG_KPZ)
+    g = S.Plan(p)
+    g.step(1000)
+    w1 = g.observe(S.OBS_WIDTH)[0]
+    g.step(W.CONFIG_KPZ["steps"] - 1000)
+    w2 = g.observe(S.OBS_WIDTH)[0]
+    say("KPZ 1024^2 width after 1e3 and 5e4 steps", w1, w2)
+    assert np.isfinite(w2) and w2 > w1 > 0
+    g.close()
+    p = W.problem(W.CONFIG_CGL)
+    g = S.Plan(p)
+    g.step(W.CONFIG_CGL["steps"])
+    assert g.observe(S.OBS_STEP)[1] == 0
+    spec = g.get(0)
+    n3 = float(np.prod(p["n"]))
+    a2 = float(np.sum(np.abs(spec) ** 2)) / n3 ** 2
+    say("CGL 256^3 mean |A|^2 after 2e4 steps", a2)
+    assert 0.3 < a2 < 1.2
+    g.close()
