@@ -385,7 +385,9 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
             // |grad h|^2 with d0 h = IFFT[i k0 h] (from pre1) and d1 h = IFFT[i k1 h];
             // the two rows' lines go through the stages together (one set of
             // barriers, twice the independent work per exchange), interleaved in LDS
-            const T dkl = (T)it.dk[last];
+            // read from the item in global memory: indexing the private copy
+            // with the run-time axis would keep all of it in scratch memory
+            const T dkl = (T)a.items[blockIdx.y].dk[last];
             cx<T> w[2][8];
 #pragma unroll
             for (int s = 0; s < 2; s++) {
