@@ -34,28 +34,37 @@ def relerr(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_pair(p, steps, every, r_sample=None):
-    """Advance GPU (all realizations) and oracle (sampled realizations)."""
+def run_pair(p, steps, every=1, r_sample=None, progress=False):
+    """Advance GPU (all realizations, one launch per pass) and oracle (the
+    sampled realizations) side by side, comparing the sampled states after
+    every `every` steps; returns the largest relative error seen (steps 1 to
+    `steps`)."""
     S = _setd()
     rs = list(range(p["realizations"])) if r_sample is None else list(r_sample)
     say("case", p["nl"], p["n"], "prec", p["precision"], "R", p["realizations"], "order", p["order"],
-        "dealias", p["dealias"], "steps", steps)
+        "dealias", p["dealias"], "steps", steps, "compared every", every, "realizations", rs)
+    t0 = time.time()
     g = S.Plan(p)
     oracles = [O.Sim(p, r_first=r, r_count=1) for r in rs]
+    t_orc = time.time() - t0
     worst = 0.0
     done = 0
-    while True:
-        num = sum(np.linalg.norm(g.get(r) - o.get(0)) ** 2 for r, o in zip(rs, oracles))
-        den = sum(np.linalg.norm(o.get(0)) ** 2 for o in oracles)
-        worst = max(worst, float(np.sqrt(num / max(den, 1e-300))))
-        if done >= steps:
-            break
+    while done < steps:
         k = min(every, steps - done)
         g.step(k)
+        t1 = time.time()
         for o in oracles:
             o.step(k)
+        t_orc += time.time() - t1
         done += k
+        num = sum(np.linalg.norm(g.get(r) - o.get(0)) ** 2 for r, o in zip(rs, oracles))
+        den = sum(np.linalg.norm(o.get(0)) ** 2 for o in oracles)
+        err = float(np.sqrt(num / max(den, 1e-300)))
+        worst = max(worst, err)
+        if progress:
+            say("  step %d rel err %.3g (oracle %.1f s so far, %d threads)" % (done, err, t_orc, O.threads()))
     g.close()
+    say("  oracle wall time %.1f s for %d realization(s) x %d steps" % (t_orc, len(rs), steps))
     return worst
 
 
@@ -80,7 +89,7 @@ SMALL = [
 @pytest.mark.parametrize("p", SMALL, ids=lambda p: "%s-%s-f%d-o%d-d%d" % (
     p["nl"], "x".join(map(str, p["n"])), p["precision"], p["order"], p["dealias"]))
 def test_trajectory_parity_small(p):
-    err = run_pair(p, steps=100, every=10)
+    err = run_pair(p, steps=100, every=1)
     say("max rel err", err)
     assert err <= TOL[p["precision"]]
 
@@ -88,30 +97,38 @@ def test_trajectory_parity_small(p):
 def test_config_a_full_trajectory():
     """Model A, plain SETD1, FP64, one realization, 64^2, h = 0.01, all 1000 steps."""
     p = W.problem(W.CONFIG_A)
-    err = run_pair(p, steps=1000, every=100)
+    err = run_pair(p, steps=1000, every=1)
     say("config A max rel err", err)
     assert err <= 1e-10
 
 
 def test_config_b_full_size_sampled():
     """Model B, SETD2, complex64, 64 realizations of 512^2 in one launch: the
-    first and last realizations against the oracle over 100 steps."""
+    first and last realizations against the oracle after each of 100 steps."""
     p = W.problem(W.CONFIG_B)
-    err = run_pair(p, steps=100, every=50, r_sample=[0, 63])
+    err = run_pair(p, steps=100, every=1, r_sample=[0, 63])
     say("config B max rel err", err)
     assert err <= 2e-4
 
 
-def test_config_kpz_full_size_sampled():
+@pytest.mark.timeout(900)
+def test_config_kpz_full_size_100_steps():
+    """KPZ, SETD2, FP32, 16 realizations of 1024^2 in one launch (the 1024-point
+    transforms, two gradient inverses): realizations 0 and 15 against the
+    oracle after each of 100 steps."""
     p = W.problem(W.CONFIG_KPZ)
-    err = run_pair(p, steps=20, every=10, r_sample=[15])
+    err = run_pair(p, steps=100, every=1, r_sample=[0, 15], progress=True)
     say("config KPZ max rel err", err)
     assert err <= 2e-4
 
 
-def test_config_cgl_full_size_sampled():
+@pytest.mark.timeout(1200)
+def test_config_cgl_full_size_100_steps():
+    """CGL, SETD2, complex64, 4 realizations of 256^3 in one launch per pass
+    (the four 3D passes at N = 256): realization 3 against the oracle every 5
+    steps over 100 steps."""
     p = W.problem(W.CONFIG_CGL)
-    err = run_pair(p, steps=3, every=3, r_sample=[2])
+    err = run_pair(p, steps=100, every=5, r_sample=[3], progress=True)
     say("config CGL max rel err", err)
     assert err <= 2e-4
 
@@ -139,10 +156,12 @@ def test_long_model_a_3d_stays_on_the_oracle():
     assert err <= 2e-4
 
 
+@pytest.mark.timeout(600)
 def test_fp64_plain_model_b_full_size():
-    """The plain FP64 per-realization run the batched FP32 path is measured against."""
+    """The plain FP64 per-realization run the batched FP32 path is measured
+    against: 512^2, SETD2, compared after each of 100 steps."""
     p = W.problem(W.CONFIG_B, precision=64, realizations=1)
-    err = run_pair(p, steps=30, every=10)
+    err = run_pair(p, steps=100, every=1, progress=False)
     say("model B fp64 max rel err", err)
     assert err <= 1e-10
 
