@@ -315,27 +315,3 @@ def test_cgl_line_fluctuations_follow_the_linear_theory():
     say("CGL line S(k)/(C_ET/2): fast max dev", float(np.max(np.abs(ratio[fast] - 1))), "mean", float(np.mean(ratio[fast])))
     assert np.max(np.abs(ratio[fast] - 1)) < 5 * se + 0.01
     assert np.max(np.abs(ratio[~fast] - 1)) < 0.1
-
-
-def test_kpz_line_grows_with_the_kpz_exponent():
-    """Sec. 5 KPZ on the paper's line (N = 1024, L = 512, lambda = 50, nu = 1,
-    D = 0.01, h = 2e-3), 1024 realizations from h = 0: the width grows as
-    t^beta with the 1D KPZ beta = 1/3 over t = 2..32; with lambda = 0 the same
-    run is Edwards-Wilkinson growth, beta = 1/4."""
-    S = _setd()
-    betas = {}
-    for lam in (50.0, 0.0):
-        p = W.problem(W.LINE_KPZ, realizations=1024, seed=31, nl_par=(lam, 0.0))
-        g = S.Plan(p)
-        h, done, ts, ws = p["h"], 0, [], []
-        for k in range(1, 6):
-            target = int(round(2 ** k / h))
-            g.step(target - done)
-            done = target
-            ts.append(done * h)
-            ws.append(g.observe(S.OBS_WIDTH)[0])
-        g.close()
-        betas[lam] = float(np.polyfit(np.log(ts), np.log(ws), 1)[0])
-    say("KPZ line beta", betas)
-    assert 0.30 < betas[50.0] < 0.36
-    assert 0.23 < betas[0.0] < 0.27
