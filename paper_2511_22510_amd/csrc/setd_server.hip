@@ -99,6 +99,7 @@ struct Job {
     int64_t nsteps = 0, done_steps = 0;
     std::unique_ptr<Plan> plan;
     size_t off = 0, bytes = 0;
+    size_t nitems = 0;   // entries of the per-tick item table the job takes
     int state = JOB_QUEUED;
     setd_status status = SETD_OK;
     double t_submit = 0, t_admit = 0, t_done = 0;
@@ -126,8 +127,9 @@ struct setd_server {
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_lane[NLANE] = {};
     Arena alloc;
-    // device item tables, one region per launch class of a tick
-    size_t items_off = 0, items_cap = 0;
+    // device item tables, one region per launch class of a tick; items_used
+    // counts the entries the active jobs take (admission keeps it <= items_cap)
+    size_t items_off = 0, items_cap = 0, items_used = 0;
     Item* items_host = nullptr;   // pinned
 
     std::mutex mu;
@@ -148,6 +150,8 @@ struct setd_server {
 
     void run();
     void admit_locked(std::vector<Job*>& admitted);
+    // a job leaves the active set: its arena block and item entries are freed
+    void retire_locked(Job* j, setd_status st);
     setd_status tick(std::vector<Job*>& act, int* steps_taken);
     void finish(Job* j);
     void retain(Job* j);
@@ -161,10 +165,11 @@ void setd_server::admit_locked(std::vector<Job*>& admitted)
         if ((int)active.size() >= max_active) break;
         Job* j = jobs[*qi].get();
         size_t off = 0;
-        if (!blocked && alloc.alloc(j->bytes, &off)) {
+        if (!blocked && items_used + j->nitems <= items_cap && alloc.alloc(j->bytes, &off)) {
             j->off = off;
             j->state = JOB_ACTIVE;
             j->t_admit = t;
+            items_used += j->nitems;
             active.push_back(j->id);
             admitted.push_back(j);
             qi = queue.erase(qi);
@@ -175,6 +180,16 @@ void setd_server::admit_locked(std::vector<Job*>& admitted)
         if (blocked) break;
         ++qi;
     }
+}
+
+void setd_server::retire_locked(Job* j, setd_status st)
+{
+    j->status = st;
+    j->state = JOB_DONE;
+    j->t_done = now_s();
+    alloc.release(j->off, j->bytes);
+    items_used -= j->nitems;
+    active.erase(std::remove(active.begin(), active.end(), j->id), active.end());
 }
 
 void setd_server::retain(Job* j)
@@ -217,12 +232,8 @@ void setd_server::finish(Job* j)
         j->have_state = true;
     }
     std::lock_guard<std::mutex> lk(mu);
-    j->status = (st == SETD_E_DEVICE) ? SETD_E_DEVICE : (flag ? SETD_E_NONFINITE : SETD_OK);
-    j->state = JOB_DONE;
-    j->t_done = now_s();
-    alloc.release(j->off, j->bytes);
+    retire_locked(j, (st == SETD_E_DEVICE) ? SETD_E_DEVICE : (flag ? SETD_E_NONFINITE : SETD_OK));
     if (j->have_state) retain(j);
-    active.erase(std::remove(active.begin(), active.end(), j->id), active.end());
 }
 
 // One scheduler tick: every active job advances min(remaining, chunk) steps.
@@ -243,13 +254,11 @@ setd_status setd_server::tick(std::vector<Job*>& act, int* steps_taken)
     // them: a job with an odd count gets a partner that never steps (a copy
     // of its last item with no steps), so that every job's realizations pair
     // as in a solo run.
-    auto padded = [](const Job* j) {
-        const Plan& p = *j->plan;
-        return p.g.ndim == 1 && !p.g.cplx && (p.R % 2) == 1;
-    };
+    auto padded = [](const Job* j) { return j->nitems > (size_t)j->plan->R; };
     size_t nitems = 0;
     for (auto& c : classes)
-        for (Job* j : c.second) nitems += (size_t)j->plan->R + (padded(j) ? 1 : 0);
+        for (Job* j : c.second) nitems += j->nitems;
+    // admission keeps the active jobs' entries within the table
     if (nitems > items_cap) return fail(SETD_E_NOMEM, "item table overflow");
     size_t pos = 0;
     struct Launch { Plan* rep; size_t first; int n; };
@@ -323,11 +332,7 @@ void setd_server::run()
             setd_status st = j->plan->bind(arena + j->off, j->bytes, stream);
             if (st != SETD_OK) {
                 std::lock_guard<std::mutex> lk(mu);
-                j->status = st;
-                j->state = JOB_DONE;
-                j->t_done = now_s();
-                alloc.release(j->off, j->bytes);
-                active.erase(std::remove(active.begin(), active.end(), j->id), active.end());
+                retire_locked(j, st);
                 act.erase(std::remove(act.begin(), act.end(), j), act.end());
             }
         }
@@ -337,13 +342,7 @@ void setd_server::run()
             if (st != SETD_OK) {
                 // a device failure ends every job of the tick
                 std::lock_guard<std::mutex> lk(mu);
-                for (Job* j : act) {
-                    j->status = st;
-                    j->state = JOB_DONE;
-                    j->t_done = now_s();
-                    alloc.release(j->off, j->bytes);
-                    active.erase(std::remove(active.begin(), active.end(), j->id), active.end());
-                }
+                for (Job* j : act) retire_locked(j, st);
             } else {
                 for (Job* j : act)
                     if (j->done_steps >= j->nsteps) finish(j);
@@ -362,7 +361,8 @@ setd_status setd_server_create(void* dev_arena, size_t bytes, void* hip_stream, 
 {
     if (!dev_arena || !out) return fail(SETD_E_INVAL, "null argument");
     if (((uintptr_t)dev_arena) % 256 != 0) return fail(SETD_E_INVAL, "arena must be 256-byte aligned");
-    const size_t items_cap = 16384;
+    // entries of the per-tick item table (SETD_SERVER_ITEMS, default 16384)
+    const size_t items_cap = (size_t)std::max(2.0, std::min(1048576.0, env_double("SETD_SERVER_ITEMS", 16384)));
     const size_t table = (items_cap * sizeof(Item) + 255) / 256 * 256;
     if (bytes < table + (1u << 20)) return fail(SETD_E_NOMEM, "arena too small");
     setd_server* s = new (std::nothrow) setd_server();
@@ -416,7 +416,11 @@ setd_status setd_submit(setd_server* s, const setd_desc* desc, int64_t nsteps, s
     j->d = *desc;
     j->nsteps = nsteps;
     j->bytes = j->plan->lay.total;
-    if ((size_t)desc->realizations > s->items_cap) return fail(SETD_E_INVAL, "too many realizations for one job");
+    // a real 1D line with an odd realization count takes one padding entry
+    const Plan& jp = *j->plan;
+    j->nitems = (size_t)jp.R + ((jp.g.ndim == 1 && !jp.g.cplx && (jp.R % 2) == 1) ? 1 : 0);
+    if (j->nitems > s->items_cap)
+        return fail(SETD_E_INVAL, "job takes %zu item entries, the server's table holds %zu", j->nitems, s->items_cap);
     if (j->bytes > s->alloc.size) return fail(SETD_E_NOMEM, "job needs %zu bytes, arena has %zu", j->bytes, s->alloc.size);
     std::lock_guard<std::mutex> lk(s->mu);
     j->id = s->next_id++;

@@ -159,3 +159,31 @@ def test_serving_trace_small():
         lat.append(t[2] - t[0])
     say("p50 %.4f s  p99 %.4f s" % (np.percentile(lat, 50), np.percentile(lat, 99)))
     srv.close()
+
+
+def test_admission_keeps_item_entries_within_the_table(monkeypatch):
+    """Admission counts the per-tick item-table entries (a realization each,
+    plus one padding entry for a real 1D line with an odd count): jobs whose
+    realizations together exceed the table wait instead of failing the tick,
+    and each finishes with its solo result."""
+    monkeypatch.setenv("SETD_SERVER_ITEMS", "48")
+    S = _setd()
+    jobs = [(W.model_a([16, 16], precision=32, order=2, realizations=32, seed=201), 20),
+            (W.model_a([16, 16], precision=32, order=2, realizations=32, seed=202), 20),
+            (W.model_b([16, 16], precision=32, realizations=20, seed=203), 15),
+            # 47 realizations + 1 padding entry fill the table exactly
+            (W.model_a([32], precision=32, order=2, realizations=47, seed=204), 30)]
+    srv = S.Server(64 << 20)
+    ids = [srv.submit(p, n) for p, n in jobs]
+    with pytest.raises(S.SetdError) as e:
+        srv.submit(W.model_a([16, 16], precision=32, order=2, realizations=49, seed=205), 5)
+    assert e.value.status == S.SETD_E_INVAL   # 49 entries never fit
+    srv.drain()
+    for jid, (p, n) in zip(ids, jobs):
+        assert srv.poll(jid) == (True, S.SETD_OK)
+        solo = S.Plan(p)
+        solo.step(n)
+        for r in (0, p["realizations"] - 1):
+            assert np.array_equal(srv.get(jid, r), solo.get(r)), (jid, r)
+        solo.close()
+    srv.close()
