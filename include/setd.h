@@ -366,6 +366,38 @@ typedef struct {
    too large counts, null dev_u with npaths > 0), SETD_E_DEVICE. */
 setd_status setd_sde_run(const setd_sde_desc* desc, double* dev_u, double* dev_w, void* hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code running under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * work of setd_plan_create + setd_plan_bind + setd_step + setd_get_field for
+ * every realization, in one call that calls no hipMalloc / hipFree and
+ * creates no stream, event or graph.
+ *
+ * The plan's workspace is a fixed device array of SETD_NOALLOC_MAX_WORKSPACE
+ * bytes inside the library, one per GPU, held from the first call on that GPU
+ * until the process ends.  Every call on a GPU reuses that GPU's array and
+ * rewrites all of it that the plan uses, so nothing carries over between
+ * calls; calls that overlap on one GPU (from several host threads, or on
+ * streams not ordered against each other) race on it.  Variants are the
+ * defaults (no autotuning) and the realizations step in one launch per pass,
+ * with the same kernels as a bound plan.
+ *
+ * desc:    as setd_plan_create; the plan's workspace (setd_plan_workspace)
+ *          must not exceed SETD_NOALLOC_MAX_WORKSPACE.
+ * nsteps:  time steps from the initial condition (>= 0, < 2^32).
+ * dev_out: caller-owned device memory of cap doubles, cap >= 2 * spectral_len
+ *          * realizations; receives the spectra after nsteps steps in the
+ *          layout of setd_get_field, realization r at dev_out + 2 r
+ *          spectral_len (dealiased modes written as zero).
+ * hip_stream: the work is queued on it and the call returns before the
+ *          steps have finished (the set-up synchronises the stream once).
+ * Errors: SETD_E_INVAL / SETD_E_UNSUPPORTED as setd_plan_create, or a null
+ * pointer, negative nsteps, cap too small; SETD_E_NOMEM when the plan needs
+ * more than SETD_NOALLOC_MAX_WORKSPACE bytes; SETD_E_DEVICE.
+ */
+#define SETD_NOALLOC_MAX_WORKSPACE (64u << 20)
+setd_status setd_run_noalloc(const setd_desc* desc, int64_t nsteps, double* dev_out, size_t cap, void* hip_stream);
+
 /* Seconds on the clock used by setd_job_times. */
 double setd_clock(void);
 

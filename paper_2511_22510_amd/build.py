@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libsetd.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["setd_k32.hip", "setd_k64.hip", "setd_line32.hip", "setd_line64.hip", "setd_kmisc.hip",
-           "setd_runtime.hip", "setd_server.hip", "setd_sde.hip"]
+           "setd_runtime.hip", "setd_server.hip", "setd_sde.hip", "setd_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -123,6 +123,54 @@ __global__ void __launch_bounds__(256) k_copy16(uint4* dst, const uint4* src, in
         dst[i] = src[i];
 }
 
+// Stored position of FFT index j on an axis of n points whose kept entries are
+// 0..kp then the top (kept - kp - 1) indices (a full axis), or 0..kp only (the
+// half-spectrum axis of a real field); -1 for an index dealiasing removed.
+__device__ inline int stored_pos(int j, int n, int kept, int kp, bool half)
+{
+    if (j <= kp) return j;
+    if (half) return -1;
+    const int lo = n - (kept - kp - 1);
+    return j >= lo ? j - (n - kept) : -1;
+}
+
+// Stored state of R realizations (rstride bytes apart, padded last axis) ->
+// the unpruned FFT-order spectra of the ABI as interleaved doubles, realization
+// r at out + 2 r nspec; removed modes are written as zero.
+template <typename T>
+__global__ void __launch_bounds__(256) k_unpack(Geo g, const char* phi, size_t rstride, int R, int64_t nspec,
+                                                double* out)
+{
+    const int64_t total = (int64_t)R * nspec;
+    const int last = g.ndim - 1;
+    const int k1 = (g.ndim == 3) ? g.kept[1] : 1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i / nspec);
+        int64_t e = i - (int64_t)r * nspec;
+        const int jl = (int)(e % g.nh_last);
+        e /= g.nh_last;
+        int j1 = 0, j0 = 0;
+        if (g.ndim == 3) {
+            j1 = (int)(e % g.n[1]);
+            j0 = (int)(e / g.n[1]);
+        } else if (g.ndim == 2) {
+            j0 = (int)e;
+        }
+        const int c = stored_pos(jl, g.n[last], g.kept[last], g.kp[last], !g.cplx);
+        const int i1 = (g.ndim == 3) ? stored_pos(j1, g.n[1], g.kept[1], g.kp[1], false) : 0;
+        const int i0 = (g.ndim >= 2) ? stored_pos(j0, g.n[0], g.kept[0], g.kp[0], false) : 0;
+        double re = 0.0, im = 0.0;
+        if (c >= 0 && i1 >= 0 && i0 >= 0) {
+            const T* src = reinterpret_cast<const T*>(phi + (size_t)r * rstride) +
+                           2 * (((size_t)i0 * k1 + i1) * g.pitch + c);
+            re = (double)src[0];
+            im = (double)src[1];
+        }
+        out[2 * i] = re;
+        out[2 * i + 1] = im;
+    }
+}
+
 // means per shell and the accumulated time series (kind = setd_obs_kind)
 __global__ void k_obs_final(int kind, int nb, const double* acc, double* out, double* skacc, double wscale)
 {
@@ -210,6 +258,22 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s)
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<uint4*>(dst),
                        reinterpret_cast<const uint4*>(src), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const Geo& g, const void* phi, size_t rstride, int R, int64_t nspec, double* out,
+                         hipStream_t s)
+{
+    const int64_t total = (int64_t)R * nspec;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (g.prec == 32)
+        hipLaunchKernelGGL(k_unpack<float>, dim3((unsigned)blocks), dim3(256), 0, s, g,
+                           reinterpret_cast<const char*>(phi), rstride, R, nspec, out);
+    else
+        hipLaunchKernelGGL(k_unpack<double>, dim3((unsigned)blocks), dim3(256), 0, s, g,
+                           reinterpret_cast<const char*>(phi), rstride, R, nspec, out);
     return hipGetLastError();
 }
 

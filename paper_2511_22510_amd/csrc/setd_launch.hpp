@@ -67,6 +67,10 @@ hipError_t launch_ctrl_init(Ctrl* ctrl, int n, int64_t step, hipStream_t s);
 hipError_t launch_ctrl_set(Ctrl* ctrl, int n, int64_t step, int which, hipStream_t s);
 hipError_t launch_fill64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// stored state of R realizations (rstride bytes apart) -> unpruned FFT-order
+// spectra as interleaved doubles in device memory, nspec values each
+hipError_t launch_unpack(const Geo& g, const void* phi, size_t rstride, int R, int64_t nspec, double* out,
+                         hipStream_t s);
 hipError_t launch_obs_final(int kind, int nb, const double* acc, double* out, double* skacc, double wscale,
                             hipStream_t s);
 hipError_t launch_obs_mean(int nb, const double* skacc, double* out, hipStream_t s);

@@ -388,7 +388,7 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
     ws = (char*)dev;
     stream = s;
     const int last = d.ndim - 1;
-    if (R >= 2 && split_ok && !aux) {
+    if (R >= 2 && split_ok && !no_alloc && !aux) {
         SETD_HIP(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
         SETD_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
         SETD_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
@@ -473,7 +473,7 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
         // SETD_GRAPH: steps per captured graph (default 0: kernel launches;
         // replaying graphs measured slower than launching on this runtime)
         const char* ge = std::getenv("SETD_GRAPH");
-        graph_chunk = ge ? std::max(0, std::min(1024, atoi(ge))) : 0;
+        graph_chunk = (ge && !no_alloc) ? std::max(0, std::min(1024, atoi(ge))) : 0;
         SETD_HIP(launch_ctrl_init(ctrl, R, 0, s));
     }
     SETD_HIP(launch_fill64(reinterpret_cast<double*>(ws + lay.skacc), 2 * nbins + 1, 0.0, s));
@@ -558,7 +558,7 @@ setd_status Plan::autotune()
         return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row in 0..15, axis0 in 0..5, axis1 in 0..3");
     }
     const char* env = std::getenv("SETD_AUTOTUNE");
-    if (env && env[0] == '0') return SETD_OK;
+    if ((env && env[0] == '0') || no_alloc) return SETD_OK;
     if (d.nl == NL_NONE || d.ndim == 1) return SETD_OK;   // a line has one kernel
     const std::string key = tune_key(*this);
     {

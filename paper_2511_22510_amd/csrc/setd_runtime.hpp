@@ -62,6 +62,9 @@ struct Plan {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool split_ok = true;         // whether bind may create the auxiliary stream
+    // bind creates no stream, event or graph and times no variant (the
+    // default variants, or those pinned by SETD_VARIANT, are used)
+    bool no_alloc = false;
     // setd_step replays a captured graph of graph_chunk steps (0: eager
     // launches only), captured on a stream of the plan at the first use
     int graph_chunk = 0;

@@ -103,6 +103,7 @@ SIGNATURES = {
     "setd_job_times": (ctypes.c_int, [_P, _I64, _D]),
     "setd_server_destroy": (ctypes.c_int, [_P]),
     "setd_sde_run": (ctypes.c_int, [ctypes.POINTER(setd_sde_desc), _P, _P, _P]),
+    "setd_run_noalloc": (ctypes.c_int, [ctypes.POINTER(setd_desc), _I64, _P, _SZ, _P]),
     "setd_clock": (ctypes.c_double, []),
     "setd_last_error": (ctypes.c_char_p, []),
 }
@@ -322,6 +323,12 @@ def setd_server_destroy(server, lib=None):
     lib.setd_server_destroy(server)
 
 
+def setd_run_noalloc(desc, nsteps, dev_out_ptr, cap, stream_ptr, lib=None):
+    lib = lib or load()
+    _check(lib, lib.setd_run_noalloc(ctypes.byref(desc), int(nsteps), _P(dev_out_ptr), int(cap),
+                                     _P(stream_ptr or 0)))
+
+
 def setd_clock(lib=None):
     lib = lib or load()
     return lib.setd_clock()
@@ -468,6 +475,23 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def run_noalloc(params, nsteps, lib=None):
+    """Spectra of every realization after nsteps steps from the initial
+    condition, computed by setd_run_noalloc (no device allocation inside the
+    library; the output buffer is a torch tensor): [R, *spectral shape]."""
+    import torch
+    lib = lib or load()
+    desc = make_desc(params)
+    shp = spectral_shape(params)
+    nspec = int(np.prod(shp))
+    R = int(desc.realizations)
+    out = torch.empty(2 * nspec * R, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    setd_run_noalloc(desc, nsteps, out.data_ptr(), out.numel(), stream.cuda_stream, lib)
+    stream.synchronize()
+    return out.cpu().numpy().view(np.complex128).reshape((R,) + tuple(shp))
 
 
 def sde_run(scheme, c, h, nsteps, npaths, seed, u0=1.0, f1=0.0, f3=0.0, g0=0.0, g1=0.0, lib=None):
