@@ -181,8 +181,11 @@ typedef struct {
                                  1: eta drawn per site in real space and
                                  transformed, eta_a = DFT[eta_x]_a / sqrt(prod n)
                                  (Sec. 4 step 2's alternative, one more transform
-                                 per step; 1D lines only, SETD_E_UNSUPPORTED
-                                 otherwise).  The kick estimators
+                                 per step).  On 2D/3D lattices each step first
+                                 transforms its site noise into a noise array
+                                 (more workspace, more bytes per step) and the
+                                 plan keeps phi and F_{n-1} (no carry).  Not with
+                                 dealias 2.  The kick estimators
                                  (SETD_OBS_KICK / RESPONSE / SPECTRUM) need 0.  */
 } setd_desc;
 
@@ -196,7 +199,10 @@ typedef struct {
     double alg_bytes_per_step;/* HBM bytes one step must move (all realizations)   */
     double site_updates_per_step; /* prod n[i] * realizations                      */
     double pass_bytes[4];     /* HBM bytes each kernel launch of a step must move,
-                                 in launch order (unused entries 0)                */
+                                 in launch order (unused entries 0); with real-
+                                 space noise on a 2D/3D lattice the launches of
+                                 its transform come first and are counted in
+                                 alg_bytes_per_step only                         */
     int variants[3];          /* kernel variants in use (row, axis 0, axis 1) after
                                  the autotuner; meaningful once bound; row
                                  variant bits: 0 LDS padding, 1 256-thread

@@ -237,6 +237,7 @@ struct AxisArgs {
     int mode;      // axis-0 pass: MODE_STEP / MODE_IC / MODE_SYNC; axis-1 pass: +1 inverse, -1 forward
     int sub;
     int ctab;      // register axis-0 kernel, keyed coefficients: stage them in LDS (the launch sized it)
+    int alt;       // axis-1 pass: the noise intermediate npre in place of pre0
 };
 
 struct LinArgs {
@@ -536,6 +537,113 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
     for (int q = 0; q < 8; q++) bstore<T>(rb, col_off(q), 0, v[q]);
 }
 
+// ---------------------------------------------------------------- real-space noise, last axis
+// Sec. 4 step 2's alternative on 2D/3D lattices: the noise is drawn per site
+// and transformed, eta_a = DFT[eta_x]_a / sqrt(prod n).  This pass draws the
+// site values of step n and transforms the lines of the last axis; the
+// axis-1 (3D) and axis-0 passes finish the transform (MODE_RSN).
+// With R lines of the last axis per realization (line r = i0 n1 + i1) a site
+// is x = r N + c, and its Philox4x32-10 block is (x mod Q, n, realization, 3)
+// with Box-Muller normals of the word pairs (x0, x1) and (x2, x3):
+//   real field, Q = R N / 4: the sites x + m Q (lines rho + m R/4, m = 0..3,
+//     column c) take z1, z2 of the first pair and z1, z2 of the second;
+//   complex field, Q = R N / 2: line rho takes (z1 + i z2)/sqrt2 of the first
+//     pair, line rho + R/2 that of the second.
+// A thread group owns group rho and draws each block once: a real field's
+// four lines travel as two complex lines (rho + i (rho + R/4), rho + R/2 +
+// i (rho + 3R/4)), split into the four half spectra through LDS after the
+// transform; a complex field's two lines are transformed as they are.  The
+// stored columns go to npre (2D) or big (3D).  The scale 1/sqrt(prod n) (and
+// 1/sqrt2 of a complex draw) multiplies the site values.
+struct RsnArgs {
+    Geo g;
+    const Item* items;
+    int nrows;     // lines of the last axis per realization (R)
+    int ngroups;   // R/4 (real field) or R/2 (complex field)
+    int lpb;       // thread groups per block
+    int sub;
+    double scale;
+};
+
+template <typename T, int N, int PAD, bool CPLX>
+__global__ void __launch_bounds__(256) k_rsn_rows(RsnArgs a)
+{
+    const Item it = a.items[blockIdx.y];
+    if (a.sub >= it.steps) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+    constexpr int TPL = N / 8;
+    constexpr int LL = lds_len<N, PAD>();
+    const int tid = threadIdx.x;
+    const int l = tid / TPL, t = tid - l * TPL;
+    cx<T>* L = lds + l * 2 * LL;   // the group's two lines
+    const Geo& g = a.g;
+    const int last = g.ndim - 1;
+    const int grp = blockIdx.x * a.lpb + l;
+    const bool valid = grp < a.ngroups;
+    const uint32_t n = (uint32_t)it.ctrl->step;
+    const T sc = (T)a.scale;
+    LineTw<T, N> tw;
+    line_tw_load(tw, t, twid<T>(last == 1 ? it.tw1 : it.tw2));
+    cx<T> v[2][8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        v[0][q] = czero<T>();
+        v[1][q] = czero<T>();
+        if (valid) {
+            uint32_t x[4];
+            philox_block(it.seed, (uint32_t)grp * (uint32_t)N + (uint32_t)(t + q * TPL), n, it.r, 3u, x);
+            T z1, z2, z3, z4;
+            box_muller32(x[0], x[1], z1, z2);
+            box_muller32(x[2], x[3], z3, z4);
+            v[0][q] = {sc * z1, sc * z2};
+            v[1][q] = {sc * z3, sc * z4};
+        }
+    }
+    fft_lines<T, N, -1, PAD, 2>(v, t, L, 1, LL, tw);
+    cx<T>* const dst = reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.npre : it.big);
+    const size_t pitch = (size_t)g.pitch;
+    const int K = g.kp[last];
+    if constexpr (CPLX) {
+        const int kept = g.kept[last];
+        const size_t rows[2] = {(size_t)grp, (size_t)grp + (size_t)(a.nrows / 2)};
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int k = t + q * TPL;
+            const int c = k <= K ? k : (k >= N - (kept - K - 1) ? k - (N - kept) : -1);
+            if (valid && c >= 0) {
+                dst[rows[0] * pitch + c] = v[0][q];
+                dst[rows[1] * pitch + c] = v[1][q];
+            }
+        }
+    } else {
+        // Z = A + i B: A_k = (Z_k + conj Z_{N-k}) / 2, B_k = -i (Z_k - conj Z_{N-k}) / 2
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            L[lds_slot<PAD>(t + q * TPL)] = v[0][q];
+            L[LL + lds_slot<PAD>(t + q * TPL)] = v[1][q];
+        }
+        __syncthreads();
+        const size_t quarter = (size_t)(a.nrows / 4);
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int k = t + q * TPL;
+            if (!(valid && k <= K)) continue;
+            const int m = (N - k) & (N - 1);
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const cx<T> z = v[h][q], zm = L[h * LL + lds_slot<PAD>(m)];
+                const cx<T> A = {T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
+                const cx<T> B = {T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)};
+                const size_t ra = (size_t)grp + (size_t)(2 * h) * quarter;
+                dst[ra * pitch + k] = A;
+                dst[(ra + quarter) * pitch + k] = B;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- axis-0 pass
 // A block owns TILE adjacent columns of the stored last axis (3D: at one
 // stored index of axis 1).  Each thread carries LPT columns: thread
@@ -578,9 +686,12 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
         col[k] = c0 + k * CW;   // column within the tile
         cv[k] = tile * TILE + col[k] < keptl;
     }
-    cx<T>* __restrict__ pre0 = reinterpret_cast<cx<T>*>(it.pre0);
-    cx<T>* __restrict__ phi = reinterpret_cast<cx<T>*>(it.phi);
+    // MODE_RSN transforms the real-space noise: npre in, eta_a out to noise
+    const bool rsn_mode = a.mode == MODE_RSN;
+    cx<T>* __restrict__ pre0 = reinterpret_cast<cx<T>*>(rsn_mode ? it.npre : it.pre0);
+    cx<T>* __restrict__ phi = reinterpret_cast<cx<T>*>(rsn_mode ? it.noise : it.phi);
     cx<T>* __restrict__ prev = reinterpret_cast<cx<T>*>(it.prev);
+    const cx<T>* __restrict__ rnoise = reinterpret_cast<const cx<T>*>(it.noise);
     LineTw<T, N0> tw;
     line_tw_load(tw, t, twid<T>(it.tw0));
     cx<T>* L = lds + c0;   // line k at L + k * CW, element stride TILE
@@ -676,7 +787,7 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
             cx<T>* slot = lds + lds_slot<PAD>(j0) * TILE + cc;
             if (colm < keptl) {
                 const size_t si = (size_t)i0 * lstride + plane + cc;
-                if (a.mode == MODE_IC) {
+                if (a.mode == MODE_IC || rsn_mode) {
                     phi[si] = *slot;
                 } else if (a.mode == MODE_RECOVER) {
                     // pre holds the unscaled axis-0 inverse of phi: divide by N0
@@ -689,7 +800,8 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
                     const T km = (g.ndim == 3) ? dk1 * (T)a1 : T(0);
                     const T k2 = (dk0 * (T)a0) * (dk0 * (T)a0) + km * km + kl * kl;
                     const cx<T> F = cmul(nl_pref<T>(it, k2), *slot);
-                    const cx<T> eta = noise_eta<T>(g, it, j0, j1, jlm, (uint32_t)nstep);
+                    // Fourier-space draws (App. B), or the transformed real-space noise
+                    const cx<T> eta = g.rsn ? rnoise[si] : noise_eta<T>(g, it, j0, j1, jlm, (uint32_t)nstep);
                     cx<T> nw = cmul(cur.cf.E, cur.ph) + cmul(cur.cf.wa, F) + cur.cf.G * eta;
                     if (it.order == 2) {
                         nw = nw + cmul(cur.cf.wb, use_prev ? cur.pv : F);
@@ -711,8 +823,8 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
         }
         // one flag update per block
         if (__syncthreads_or(bad) && tid == 0) atomicOr(&it.ctrl->nonfinite, 1);
-        // recovery reads pre and writes phi only
-        if (a.mode == MODE_RECOVER) return;
+        // recovery reads pre and writes phi only; the noise transform writes eta_a only
+        if (a.mode == MODE_RECOVER || rsn_mode) return;
 #pragma unroll
         for (int k = 0; k < LPT; k++) {
 #pragma unroll
@@ -891,6 +1003,16 @@ k_axis0r(AxisArgs a)
     cx<T> elo[3], ehi[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) elo[k] = ehi[k] = czero<T>();
+    // real-space noise (plans without the carry): eta_a of the step was
+    // transformed into the noise array, which has the layout of phi
+    const rsrc_t rnoise = make_rsrc(it.noise, g.rsn ? (uint32_t)kept0 * lstride : 0u);
+    if (g.rsn) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            elo[k] = bload<T>(rnoise, voff(k), soff(k));
+            ehi[2 - k] = bload<T>(rnoise, voff(7 - k), soff(7 - k));
+        }
+    }
     const uint32_t nn = (uint32_t)(LEAN ? nstep + 1 : nstep);
     // off the a_last in {0, N_last/2} planes of a real field the pair's block
     // is the one of row t + k N0/8 (bin k half 0, bin 7 - k half 1); on them a
@@ -899,7 +1021,7 @@ k_axis0r(AxisArgs a)
     const uint32_t S = (g.ndim == 3) ? (uint32_t)g.n[1] * (uint32_t)g.nh_last : (uint32_t)g.nh_last;
     const uint32_t rest = (g.ndim == 3) ? (uint32_t)j1 * (uint32_t)g.nh_last + (uint32_t)jl : (uint32_t)jl;
 #pragma unroll 1
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < (g.rsn ? 0 : 3); k++) {
         const int ja = t + k * TPL, jb = t + (7 - k) * TPL;
         NoiseSlot sa, sb;
         if (herm) {
@@ -1173,7 +1295,7 @@ __global__ void __launch_bounds__(TILE / LPT * N1 / 8) k_axis1(AxisArgs a)
         col[k] = tile * TILE + c0 + k * CW;
         cv[k] = col[k] < g.kept[2];
     }
-    cx<T>* __restrict__ small = reinterpret_cast<cx<T>*>(it.pre0) + (size_t)n0 * kept1 * pitch;
+    cx<T>* __restrict__ small = reinterpret_cast<cx<T>*>(a.alt ? it.npre : it.pre0) + (size_t)n0 * kept1 * pitch;
     cx<T>* __restrict__ big = reinterpret_cast<cx<T>*>(it.big) + (size_t)n0 * N1 * pitch;
     LineTw<T, N1> tw;
     line_tw_load(tw, t, twid<T>(it.tw1));
@@ -1246,7 +1368,10 @@ __global__ void __launch_bounds__(256) k_linear(LinArgs a)
             const int key = (it.coef_mode == COEF_PER_MODE) ? i0 * g.pitch + col
                             : (g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0);
             const Coef<T> cf = load_coef<T>(it, key);
-            const cx<T> eta = noise_eta<T>(g, it, j0, j1, jl, (uint32_t)nstep);
+            // Fourier-space draws, or the transformed real-space noise (separate
+            // storage only: plans with it keep no carry)
+            const cx<T> eta = g.rsn ? reinterpret_cast<const cx<T>*>(it.noise)[idx]
+                                    : noise_eta<T>(g, it, j0, j1, jl, (uint32_t)nstep);
             cx<T>* phi = reinterpret_cast<cx<T>*>(it.phi);
             cx<T>* carry = reinterpret_cast<cx<T>*>(it.prev);
             cx<T> nw;
@@ -1280,7 +1405,7 @@ __global__ void __launch_bounds__(256) k_linear(LinArgs a)
 struct HermArgs {
     Geo g;
     const Item* items;
-    int which;    // 0: phi, 1: the F_{n-1} array (the SETD2 carry of lean plans)
+    int which;    // 0: phi, 1: the F_{n-1} array (the SETD2 carry of lean plans), 2: the noise array
     int nplane;   // stored modes per plane and realization
     int ncol;     // planes: 1 (a_last = 0), or 2 when a_last = N_last/2 is stored
     int sub;
@@ -1309,7 +1434,7 @@ __global__ void __launch_bounds__(256) k_hermitian(HermArgs a)
                                      : (uint32_t)j0 * nh + (uint32_t)jl;
     const uint32_t ep = (g.ndim == 3) ? ((uint32_t)p0 * (uint32_t)g.n[1] + (uint32_t)p1) * nh + (uint32_t)jl
                                       : (uint32_t)p0 * nh + (uint32_t)jl;
-    cx<T>* arr = reinterpret_cast<cx<T>*>(a.which ? it.prev : it.phi);
+    cx<T>* arr = reinterpret_cast<cx<T>*>(a.which == 2 ? it.noise : (a.which ? it.prev : it.phi));
     const size_t lstride = (g.ndim == 3) ? (size_t)g.kept[1] * g.pitch : (size_t)g.pitch;
     const size_t own = (size_t)i0 * lstride + (size_t)i1 * g.pitch + col;
     if (ep == e) {

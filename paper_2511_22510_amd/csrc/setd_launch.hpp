@@ -49,6 +49,11 @@ hipError_t launch_spectrum(const SpecArgs& a, int M, hipStream_t s);
 // sums of |Delta| and Delta of the per-mode FDT deviations
 template <typename T>
 hipError_t launch_fdt_reduce(const Geo& g, const double* dacc, int total, int M, double* out, hipStream_t s);
+// the noise of the current step of plans that draw it in real space (2D/3D):
+// site draws and transforms into each item's noise array (var1, var0: the
+// axis-1 and axis-0 pass variants)
+template <typename T>
+hipError_t launch_rsn(const Geo& g, const Item* items, int nitems, int sub, int var1, int var0, hipStream_t s);
 // 1D lattices: nsteps steps per launch (MODE_STEP) or the initial condition (MODE_IC)
 template <typename T>
 hipError_t launch_line1d(const Geo& g, const Item* items, int nitems, int mode, int sub, int nsteps, int nl,

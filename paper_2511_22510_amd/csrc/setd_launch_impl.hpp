@@ -10,6 +10,9 @@
 //              tile tm/2 (variant 4) or tm (variant 5)
 #pragma once
 
+#include <cmath>
+#include <cstdlib>
+
 #include "setd_kernels.hpp"
 #include "setd_launch.hpp"
 
@@ -112,7 +115,9 @@ static hipError_t launch_axis_nt(const Geo& g, const Item* items, int nitems, in
     a.items = items;
     a.ntiles = g.pitch / TILE;
     a.per_item = a.ntiles * (AX0 ? ((g.ndim == 3) ? g.kept[1] : 1) : g.n[0]);
-    a.mode = mode;
+    // axis-1 mode -2: the forward transform into the noise intermediate npre
+    a.alt = (!AX0 && mode == -2) ? 1 : 0;
+    a.mode = a.alt ? -1 : mode;
     a.sub = sub;
     dim3 grid(a.per_item * nitems);
     dim3 block(TILE / LPT * (N / 8));
@@ -205,9 +210,10 @@ static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int
     case 2: e = launch_axis_nt<T, N, TM, 4, AX0>(g, items, nitems, mode, sub, kpz, s); break;
     default: e = launch_axis_nt<T, N, TM / 2, 1, AX0>(g, items, nitems, mode, sub, kpz, s); break;
     }
-    // the state a step or an initial condition wrote: Hermitian planes
-    if (AX0 && e == hipSuccess && (mode == MODE_STEP || mode == MODE_IC))
-        e = launch_hermitian_t<T>(g, items, nitems, 0, sub, s);
+    // the state a step or an initial condition wrote, or the transformed
+    // real-space noise: Hermitian planes
+    if (AX0 && e == hipSuccess && (mode == MODE_STEP || mode == MODE_IC || mode == MODE_RSN))
+        e = launch_hermitian_t<T>(g, items, nitems, mode == MODE_RSN ? 2 : 0, sub, s);
     return e;
 }
 
@@ -231,6 +237,51 @@ hipError_t launch_axis1(const Geo& g, const Item* items, int nitems, int dir, in
 {
     SETD_DISPATCH_N(g.n[1], return (launch_axis_n<T, NN, false>(g, items, nitems, dir, sub, var, false, false, s)));
     return hipSuccess;
+}
+
+// last-axis pass of the real-space noise (k_rsn_rows): thread groups of N/8
+// threads, as many per block as fit 256 threads and 32 KiB of LDS
+template <typename T, int N>
+static hipError_t launch_rsn_rows_n(const Geo& g, const Item* items, int nitems, int sub, hipStream_t s)
+{
+    constexpr int TPL = N / 8, PAD = 3;
+    constexpr int BY_THREADS = TPL >= 256 ? 1 : 256 / TPL;
+    constexpr int BY_LDS = 32768 / (2 * lds_len<N, PAD>() * (int)sizeof(cx<T>));
+    constexpr int CAP = BY_THREADS < BY_LDS ? BY_THREADS : BY_LDS;
+    constexpr int LPB = CAP >= 1 ? (1 << ilog2(CAP)) : 1;
+    RsnArgs a;
+    a.g = g;
+    a.items = items;
+    a.nrows = (g.ndim == 3) ? g.n[0] * g.n[1] : g.n[0];
+    a.ngroups = g.cplx ? a.nrows / 2 : a.nrows / 4;
+    a.lpb = LPB;
+    a.sub = sub;
+    double sites = 1.0;
+    for (int i = 0; i < g.ndim; i++) sites *= (double)g.n[i];
+    a.scale = (g.cplx ? std::sqrt(0.5) : 1.0) / std::sqrt(sites);
+    dim3 grid((a.ngroups + LPB - 1) / LPB, nitems);
+    dim3 block(LPB * TPL);
+    const size_t lds = (size_t)LPB * 2 * lds_len<N, PAD>() * sizeof(cx<T>);
+    if (g.cplx) hipLaunchKernelGGL((k_rsn_rows<T, N, PAD, true>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_rsn_rows<T, N, PAD, false>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rsn(const Geo& g, const Item* items, int nitems, int sub, int var1, int var0, hipStream_t s)
+{
+    if (g.ndim < 2 || !g.rsn) return hipErrorInvalidValue;
+    hipError_t e = hipErrorInvalidValue;
+    SETD_DISPATCH_N(g.n[g.ndim - 1], e = (launch_rsn_rows_n<T, NN>(g, items, nitems, sub, s)));
+    if (e != hipSuccess) return e;
+    if (g.ndim == 3) {
+        SETD_DISPATCH_N(g.n[1], e = (launch_axis_n<T, NN, false>(g, items, nitems, -2, sub, var1, false, false, s)));
+        if (e != hipSuccess) return e;
+    }
+    // the axis-0 transform writes eta_a into the noise array and keeps a real
+    // field's Hermitian planes
+    SETD_DISPATCH_N(g.n[0], e = (launch_axis_n<T, NN, true>(g, items, nitems, MODE_RSN, sub, var0, false, false, s)));
+    return e;
 }
 
 template <typename T>
@@ -378,7 +429,8 @@ hipError_t launch_observe(const Geo& g, const Item* items, int nitems, int kind,
     template hipError_t launch_spectrum<T>(const SpecArgs&, int, hipStream_t);                                    \
     template hipError_t launch_fdt_reduce<T>(const Geo&, const double*, int, int, double*, hipStream_t);         \
     template hipError_t launch_boxwidth<T>(const BoxArgs&, size_t, hipStream_t);                                  \
-    template hipError_t launch_hermitian<T>(const Geo&, const Item*, int, int, hipStream_t);
+    template hipError_t launch_hermitian<T>(const Geo&, const Item*, int, int, hipStream_t);                      \
+    template hipError_t launch_rsn<T>(const Geo&, const Item*, int, int, int, int, hipStream_t);
 
 // the 1D line kernels, in translation units of their own (they compile in
 // parallel with the others)

@@ -65,7 +65,6 @@ setd_status validate(const setd_desc& d)
     if (d.ic_kind != 0 && d.ic_kind != 1) return fail(SETD_E_INVAL, "ic_kind must be 0 or 1");
     if (d.complex_field != 0 && d.complex_field != 1) return fail(SETD_E_INVAL, "complex_field must be 0 or 1");
     if (d.noise_space != 0 && d.noise_space != 1) return fail(SETD_E_INVAL, "noise_space must be 0 or 1");
-    if (d.noise_space == 1 && d.ndim != 1) return fail(SETD_E_UNSUPPORTED, "real-space noise is built for 1D lines");
     const bool cimag = d.c0[1] != 0.0 || d.c2[1] != 0.0 || d.c4[1] != 0.0;
     if (cimag && !d.complex_field) return fail(SETD_E_INVAL, "complex c(k) needs a complex field");
     if (d.nl < 0 || d.nl > 4) return fail(SETD_E_INVAL, "unknown nonlinearity %d", d.nl);
@@ -192,7 +191,10 @@ setd_status Plan::init(const setd_desc& desc)
     Pb = real_stride(P * elt);
     Bb = B ? real_stride(B * elt) : 0;
     // SETD2 keeps only the carry unless F_{n-1} must stay readable
-    lean = d.ndim >= 2 && d.order == 2 && !d.history_readback && d.nl != NL_NONE && axis0_register_ok(g, elt / 2);
+    // (real-space noise on 2D/3D lattices is transformed for the step it is
+    // used in, so those plans keep phi and F_{n-1})
+    lean = d.ndim >= 2 && d.order == 2 && !d.history_readback && d.nl != NL_NONE && !d.noise_space &&
+           axis0_register_ok(g, elt / 2);
 
     // workspace layout, every buffer 256-byte aligned
     size_t off = 0;
@@ -224,6 +226,10 @@ setd_status Plan::init(const setd_desc& desc)
     lay.pre1 = (d.nl == NL_KPZ) ? take((size_t)R * Pb) : 0;
     lay.big = B ? take((size_t)R * Bb) : 0;
     lay.snap = take((size_t)R * Sb);
+    if (rsn_grid()) {
+        lay.npre = take((size_t)R * Pb);
+        lay.noise = take((size_t)R * Sb);
+    }
     if (iso) {
         lay.boxn = 0;
         for (int l = 2; l <= d.n[0]; l *= 2) {
@@ -287,7 +293,18 @@ double Plan::alg_bytes_per_step() const
 {
     double b[4];
     pass_bytes(b);
-    return b[0] + b[1] + b[2] + b[3];
+    double noise = 0.0;
+    if (rsn_grid()) {
+        // the noise transform: the last-axis pass writes its intermediate
+        // (3D: the line buffer, which the axis-1 pass reads and turns into
+        // the small intermediate), the axis-0 pass reads that and writes eta_a,
+        // and the step reads eta_a
+        const double e = (double)elt * R, kl = (double)g.kept[g.ndim - 1];
+        const double small = (double)g.n[0] * (g.ndim == 3 ? g.kept[1] : 1) * kl;
+        const double bigv = (g.ndim == 3) ? (double)g.n[0] * g.n[1] * kl : 0.0;
+        noise = (2.0 * bigv + 2.0 * small + 2.0 * (double)kept_modes) * e;
+    }
+    return b[0] + b[1] + b[2] + b[3] + noise;
 }
 
 template <typename T>
@@ -322,8 +339,18 @@ setd_status Plan::launch_pass(int i, const Item* items_dev, int nitems, int sub,
                              : launch_pass_t<double>(*this, i, items_dev, nitems, sub, s);
 }
 
+setd_status Plan::launch_noise(const Item* items_dev, int nitems, int sub, hipStream_t s) const
+{
+    if (!rsn_grid()) return SETD_OK;
+    if (d.precision == 32) SETD_HIP((launch_rsn<float>(g, items_dev, nitems, sub, tune.ax1, tune.ax0, s)));
+    else SETD_HIP((launch_rsn<double>(g, items_dev, nitems, sub, tune.ax1, tune.ax0, s)));
+    return SETD_OK;
+}
+
 setd_status Plan::launch_step(const Item* items_dev, int nitems, int sub, hipStream_t s) const
 {
+    setd_status st0 = launch_noise(items_dev, nitems, sub, s);
+    if (st0 != SETD_OK) return st0;
     for (int i = 0; i < passes_per_step(); i++) {
         setd_status st = launch_pass(i, items_dev, nitems, sub, s);
         if (st != SETD_OK) return st;
@@ -403,6 +430,8 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
         it.pre1 = (d.nl == NL_KPZ) ? ws + lay.pre1 + (size_t)r * Pb : nullptr;
         it.big = B ? ws + lay.big + (size_t)r * Bb : nullptr;
         it.snap = ws + lay.snap + (size_t)r * Sb;
+        it.npre = rsn_grid() ? ws + lay.npre + (size_t)r * Pb : nullptr;
+        it.noise = rsn_grid() ? ws + lay.noise + (size_t)r * Sb : nullptr;
         it.coef = ws + ((d.precision == 32) ? lay.coef32 : lay.coef64);
         const size_t* tw = (d.precision == 32) ? lay.tw32 : lay.tw64;
         it.tw0 = ws + tw[0];
@@ -779,6 +808,9 @@ setd_status Plan::step(int64_t n)
         return SETD_OK;
     }
     for (int64_t i = 0; i < n; i++) {
+        // the real-space noise transform of the step is not timed as a pass
+        setd_status stn = launch_noise(items_dev, R, 0, stream);
+        if (stn != SETD_OK) return stn;
         for (int k = 0; k < passes_per_step(); k++) {
             // timing-only events: no system-scope fence (an L2 writeback)
             // between the passes they bracket

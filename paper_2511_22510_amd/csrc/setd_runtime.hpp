@@ -29,6 +29,7 @@ struct Layout {
     size_t phi = 0, prev = 0, pre0 = 0, pre1 = 0, big = 0, snap = 0;
     size_t twm64 = 0, twm32 = 0, specacc = 0, series = 0, fdtacc = 0;   // time series (series_len > 0)
     size_t boxcls = 0, boxn = 0;  // box-width class sums and their count (equal n[i])
+    size_t npre = 0, noise = 0;   // real-space noise on 2D/3D lattices: intermediate, eta_a
     size_t total = 0;
 };
 
@@ -97,7 +98,11 @@ struct Plan {
     setd_status init(const setd_desc& desc);
     setd_status bind(void* dev, size_t bytes, hipStream_t s);
     // queue the passes of one step for nitems items starting at items_dev
+    // (after the transform of the step's real-space noise, if the plan draws it)
     setd_status launch_step(const Item* items_dev, int nitems, int sub, hipStream_t s) const;
+    // 2D/3D plans with real-space noise: its transform for the current step
+    setd_status launch_noise(const Item* items_dev, int nitems, int sub, hipStream_t s) const;
+    bool rsn_grid() const { return d.noise_space == 1 && d.ndim >= 2; }
     // queue pass i (launch order) of one step
     setd_status launch_pass(int i, const Item* items_dev, int nitems, int sub, hipStream_t s) const;
     setd_status profile_read(double* out, size_t cap, size_t* len);

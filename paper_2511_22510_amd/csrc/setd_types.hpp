@@ -19,7 +19,7 @@ struct Geo {
     int kp[3];        // largest stored FFT index on the low side of each axis
     int pitch;        // padded length of the stored last axis (elements)
     int nh_last;      // unpruned spectral length of the last axis (n/2+1 or n)
-    int rsn;          // noise drawn in real space and transformed (1D lines)
+    int rsn;          // noise drawn in real space and transformed
 };
 
 // stored rows of a realization: [kept0][kept1] lines of the last axis (3D),
@@ -46,6 +46,8 @@ struct Item {
     void* pre1;       // KPZ: axis-0 inverse of i k0 phi (2D), else null
     void* big;        // 3D: [n0][n1][pitch] line buffer of the last-axis pass
     void* snap;       // snapshot of phi for two-time correlations
+    void* npre;       // real-space noise (2D/3D): its transform over the last axes, laid out as pre0
+    void* noise;      // real-space noise (2D/3D): eta_a of the step in the stored layout of phi
     const void* coef; // coefficient table in the state precision
     const void* tw0;  // twiddles exp(-2 pi i k / n_axis), state precision
     const void* tw1;
@@ -84,8 +86,9 @@ enum { NL_PHI3 = 0, NL_PHI3_CONS = 1, NL_KPZ = 2, NL_CGL = 3, NL_NONE = 4 };
 // per stored mode of a 2D lattice in the state layout
 enum { COEF_SEPARABLE = 0, COEF_ISO = 1, COEF_PER_MODE = 2 };
 
-// modes of the passes
-enum { MODE_STEP = 0, MODE_IC = 1, MODE_SYNC = 2, MODE_RECOVER = 3 };
+// modes of the passes (MODE_RSN: the axis-0 forward transform of the
+// real-space noise, npre -> noise)
+enum { MODE_STEP = 0, MODE_IC = 1, MODE_SYNC = 2, MODE_RECOVER = 3, MODE_RSN = 4 };
 // k_linear: a step of F = 0 in place; the SETD2 carry Y = E phi + G eta_n;
 // re-drawing the carry's noise for another step index
 enum { LIN_STEP = 0, LIN_CARRY = 1, LIN_RENOISE = 2 };

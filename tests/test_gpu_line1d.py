@@ -227,15 +227,16 @@ def test_line_real_space_noise_parity(p):
 
 
 def test_real_space_noise_limits():
+    """The kick estimators regenerate Fourier-space draws: plans drawing the
+    noise in real space refuse them, on lines and on 2D lattices."""
     S = _setd()
-    with pytest.raises(S.SetdError) as e:
-        S.Plan(W.model_a([32, 32], precision=32, noise_space=1))
-    assert e.value.status == S.SETD_E_UNSUPPORTED
-    g = S.Plan(W.model_a([64], precision=32, realizations=2, noise_space=1))
-    with pytest.raises(S.SetdError) as e:
-        g.observe(S.OBS_KICK)
-    assert e.value.status == S.SETD_E_UNSUPPORTED
-    g.close()
+    for p in (W.model_a([64], precision=32, realizations=2, noise_space=1),
+              W.model_a([32, 32], precision=32, realizations=2, noise_space=1)):
+        g = S.Plan(p)
+        with pytest.raises(S.SetdError) as e:
+            g.observe(S.OBS_KICK)
+        assert e.value.status == S.SETD_E_UNSUPPORTED
+        g.close()
 
 
 PS_CASES = [

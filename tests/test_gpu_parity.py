@@ -133,6 +133,46 @@ def test_config_cgl_full_size_100_steps():
     assert err <= 2e-4
 
 
+# noise drawn per site in real space and transformed (Sec. 4 step 2's
+# alternative) on 2D and 3D lattices: real and complex fields, SETD1/SETD2,
+# both precisions, anisotropic lattices, the register and tile-sweep axis-0
+# kernels (2/3 rule on / off) and the linear kernel
+RSN_CASES = [
+    W.model_a([64, 64], precision=64, order=2, realizations=2, noise_space=1),
+    W.model_b([128, 64], precision=32, realizations=3, noise_space=1),
+    W.kpz([128, 128], precision=32, realizations=2, noise_space=1),
+    W.kpz([64, 64], precision=64, order=1, realizations=1, ic_kind=1, ic_sigma=0.2, noise_space=1),
+    W.cgl([32, 32, 32], precision=64, realizations=2, noise_space=1),
+    W.cgl([16, 32, 64], precision=32, realizations=1, noise_space=1),
+    W.cgl([64, 64], precision=32, order=1, realizations=2, dx=0.5, noise_space=1),
+    W.model_a([16, 16, 32], precision=64, order=2, realizations=2, noise_space=1),
+    W.model_a([8, 8, 8], precision=32, order=1, realizations=3, noise_space=1),
+    W.model_b([32, 32], precision=64, dealias=0, realizations=2, noise_space=1),
+    W.cgl([16, 16], precision=64, dealias=0, realizations=1, noise_space=1),
+    W.model_a([32, 32], precision=64, nl="none", u=0.0, r=0.5, realizations=2, noise_space=1),
+]
+
+
+@pytest.mark.parametrize("p", RSN_CASES, ids=lambda p: "rs-%s-%s-f%d-o%d-d%d" % (
+    p["nl"], "x".join(map(str, p["n"])), p["precision"], p["order"], p["dealias"]))
+def test_real_space_noise_parity(p):
+    """The GPU draws the site noise of each step (Philox blocks (x mod Q, n,
+    r, 3)), transforms it over every axis and scales by 1/sqrt(prod n); the
+    oracle draws the same sites and transforms them with its own FFT."""
+    err = run_pair(p, steps=100, every=1)
+    say("max rel err", err)
+    assert err <= TOL[p["precision"]]
+
+
+def test_real_space_noise_full_size_model_b():
+    """Real-space noise at the Model B workload's size (512^2 x 64, FP32): the
+    first and last realizations against the oracle over 30 steps."""
+    p = W.problem(W.CONFIG_B, noise_space=1)
+    err = run_pair(p, steps=30, every=1, r_sample=[0, 63])
+    say("model B real-space noise max rel err", err)
+    assert err <= 2e-4
+
+
 @pytest.mark.parametrize("history", [0, 1])
 @pytest.mark.parametrize("prec", [32, 64])
 def test_long_model_a_stays_on_the_oracle(prec, history):

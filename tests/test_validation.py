@@ -39,7 +39,6 @@ def _status(p):
     (dict(c2=(-1.0, 0.5)), "SETD_E_INVAL"),          # complex c(k) on a real field
     (dict(noise_space=2), "SETD_E_INVAL"),
     (dict(dealias=2), "SETD_E_UNSUPPORTED"),         # phase shift off lines
-    (dict(noise_space=1), "SETD_E_UNSUPPORTED"),     # real-space noise off lines
     (dict(nl="cgl"), "SETD_E_UNSUPPORTED"),          # CGL needs a complex field
 ])
 def test_invalid_descriptors_are_refused(bad, code):
