@@ -32,7 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_axis0_model_b_512.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_model_b_512.txt")
 # VALU issue peak: 256 CUs x 4 SIMDs, a wave64 FP32 instruction (packed FP32
 # off) occupies a 16-lane SIMD for 4 cycles, at 2.4 GHz: 614.4e9
@@ -50,13 +50,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when it is missing or the kernel sources changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
+    summary of `workload` (profiles/traffic_<workload>.txt), or None when it is
+    missing, names another kernel, or the kernel sources changed since."""
+    path = os.path.join(PROFILES, "traffic_%s.txt" % workload)
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
@@ -91,47 +93,167 @@ def measured_valu():
     return out
 
 
-def time_plan(setd, p, steps, warmup, profile):
+def survey_pass_bytes(p):
+    """Bytes each kernel launch of one step must move under the pass model of
+    the workload definitions (2/3-pruned spectral arrays, real-space fields in
+    LDS only): the state and, for SETD2, the previous nonlinear term read and
+    written once, and each transform intermediate that LDS cannot hold read
+    and written once.  2D real fields: rows (intermediate in/out; KPZ reads a
+    second one), then axis 0 (intermediate(s) in and out, state and history in
+    and out).  3D: axis-1 inverse, rows, axis-1 forward, axis 0.  All
+    realizations of the plan; per step the list sums to the bytes per
+    site-update times the sites."""
+    d, n = p["ndim"], list(p["n"])
+    e = 8 if p.get("precision", 64) == 32 else 16
+    R = int(p.get("realizations", 1))
+    cplx = bool(p.get("complex_field", 0))
+    da = int(p.get("dealias", 1)) == 1
+
+    def kept(i):
+        last = i == d - 1
+        K = (n[i] - 1) // 3 if da else (n[i] // 2 if (last and not cplx) else n[i] - 1)
+        if last and not cplx:
+            return K + 1
+        return 2 * K + 1 if da else n[i]
+
+    st = 1
+    for i in range(d):
+        st *= kept(i)
+    arrays = 4 if int(p.get("order", 1)) == 2 else 2   # phi (and F_{n-1}) in and out
+    kl = kept(d - 1)
+    if p.get("nl") == "none":
+        return [2.0 * st * e * R]
+    if d == 2:
+        pre = n[0] * kl
+        npre = 2 if p.get("nl") == "kpz" else 1
+        return [float((npre + 1) * pre * e * R), float(((1 + npre) * pre + arrays * st) * e * R)]
+    small = n[0] * kept(1) * kl
+    big = n[0] * n[1] * kl
+    return [float((small + big) * e * R), float(2 * big * e * R), float((big + small) * e * R),
+            float((2 * small + arrays * st) * e * R)]
+
+
+def time_plan(setd, p, steps, warmup, profile, prof_steps=None):
     """Time `steps` steps of plan `p` after `warmup` untimed ones, with no
-    instrumentation; with `profile`, then time a second segment of `steps`
-    steps with HIP events around every pass on the library's stream (per-pass
-    durations; the events add a little time per pass, so that segment does not
-    give the step rate).  Returns (seconds of the first segment, per-pass
-    [total ms, launches] of the second or None, plan info, clean finish,
-    seconds of the second segment or None)."""
+    instrumentation (wall clock, and HIP events on the plan's stream around the
+    segment); with `profile`, then time a second segment of `prof_steps` steps
+    with HIP events around every pass on the library's stream (per-pass
+    durations; each pair of events adds a dispatch gap inside its bracket, so
+    that segment does not give the step rate).  Returns a dict: seconds of the
+    first segment (wall, events), per-pass [total ms, launches] of the second
+    or None, plan info, clean finish, seconds of the second segment or None,
+    the plan's workspace bytes."""
     import torch
     plan = setd.Plan(p)
     plan.step(warmup)
     torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record()
     plan.step(steps)
+    ev1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof, t_prof = None, None
+    ps = prof_steps or steps
     if profile:
         setd.setd_profile(plan.h, 1, plan.lib)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        plan.step(steps)
+        plan.step(ps)
         torch.cuda.synchronize()
         t_prof = time.perf_counter() - t2
         prof = setd.setd_profile_read(plan.h, plan.lib)
     out, st = setd.setd_observe(plan.h, setd.OBS_STEP, 4, plan.lib, allow_nonfinite=True)
-    ok = (st == setd.SETD_OK) and out[0] == warmup + steps * (2 if profile else 1)
+    ok = (st == setd.SETD_OK) and out[0] == warmup + steps + (ps if profile else 0)
     info = plan.info
+    nbytes = plan.nbytes
     plan.close()
-    return t1 - t0, prof, info, ok, t_prof
+    return dict(wall=t1 - t0, ev=ev0.elapsed_time(ev1) * 1e-3, prof=prof, info=info, ok=ok, t_prof=t_prof,
+                steps=steps, prof_steps=ps, workspace=nbytes)
 
 
-def serving_run(setd, W, n_jobs, seed, audit=True):
-    """A Poisson stream of mixed SETD2 FP32 jobs through the continuous-batching
-    server; returns latency percentiles and throughput, the same jobs' rate as
-    plain per-job FP64 runs (each job alone, 100 steps), and an audit of the two
-    cheapest jobs (5% of 40): the served state against a solo run of the same
-    job (bitwise) and against the FP64 oracle (realization 0, all steps)."""
+def pass_roofline(r, p, names, traffic_workload=None):
+    """Roofline record of the passes of one timed plan.  Per-pass launch
+    durations come from the HIP events around every launch, less the dispatch
+    gap those events add inside each bracket: (sum of the bracketed averages -
+    the uninstrumented step time) / passes per step, measured in the same run.
+    achieved = the pass model's bytes (survey_pass_bytes) / duration; the bytes
+    this build's storage moves (the plan's own pass bytes: a dealiased SETD2
+    plan keeps one carry array instead of phi and F_{n-1}) are given beside."""
     import numpy as np
-    import torch
-    trace = W.serving_trace(n_jobs=n_jobs, rate=20.0, seed=seed, steps_range=(1000, 10000))
+    info = r["info"]
+    steps_ev = r["ev"] / max(1, r["steps"])
+    tot_ms, cnt = r["prof"][:, 0], r["prof"][:, 1]
+    ev_avg = tot_ms / cnt * 1e-3
+    npass = len(ev_avg)
+    gap = max(0.0, (float(ev_avg.sum()) - steps_ev) / npass)
+    avg = ev_avg - gap
+    model = survey_pass_bytes(p)
+    moved = [float(info.pass_bytes[i]) for i in range(npass)]
+    dom = int(np.argmax(avg))
+    passes = [{"kernel": names[i], "avg_us": float(avg[i] * 1e6), "avg_us_events": float(ev_avg[i] * 1e6),
+               "alg_bytes": model[i], "moved_bytes": moved[i], "gbs": model[i] / avg[i] / 1e9,
+               "gbs_moved": moved[i] / avg[i] / 1e9} for i in range(npass)]
+    achieved = model[dom] / avg[dom] / 1e9
+    traffic = measured_traffic(names[dom], traffic_workload) if traffic_workload else None
+    return {
+        "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": names[dom],
+        "avg_launch_us": float(avg[dom] * 1e6), "avg_launch_us_events": float(ev_avg[dom] * 1e6),
+        "event_gap_us": gap * 1e6, "alg_bytes_per_launch": model[dom], "moved_bytes_per_launch": moved[dom],
+        "frac_moved": moved[dom] / avg[dom] / 1e9 / PEAK_HBM_GBS,
+        "passes": passes,
+        "step_alg_bytes": float(sum(model)), "step_moved_bytes": float(sum(moved)),
+        "step_frac": float(sum(model) / steps_ev / 1e9 / PEAK_HBM_GBS),
+        "step_frac_moved": float(sum(moved) / steps_ev / 1e9 / PEAK_HBM_GBS),
+    }, dom, avg
+
+
+def pass_names_2d(info, N):
+    rv = int(info.variants[0])
+    return ["k_row_real<float,%d,pad=%d,block=%d,pair_groups=%d>" % (N, 3 if rv & 1 else 0, 256 if rv & 2 else 64,
+                                                                     1 << ((rv >> 2) & 3)),
+            ("k_axis0r<float,%d,tile=%d>" % (N, info.axis_tile[0])) if int(info.variants[1]) >= 4 else
+            "k_axis0<float,%d,tile=%d,cols_per_thread=%d>" % (N, info.axis_tile[0], info.axis_tile[1])]
+
+
+def pass_names_3d(info, N):
+    return ["k_axis1<inverse,%d>" % N, "k_row_cplx<%d>" % N, "k_axis1<forward,%d>" % N,
+            "k_axis0r<float,%d,tile=%d>" % (N, info.axis_tile[0])]
+
+
+def log(*a):
+    print("bench:", *a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- serving
+SERVING_MAKERS = ("A", "B", "KPZ", "CGL")
+
+
+def serving_calibration(setd, W, steps=30):
+    """GPU seconds per step of every (model, lattice, realizations) the serving
+    trace draws, each timed alone (SETD2 FP32, the trace's physics)."""
+    makers = {"A": W.model_a, "B": W.model_b, "KPZ": W.kpz, "CGL": W.cgl}
+    costs = {}
+    for name, n in W.SERVING_TYPES:
+        for R in (1, 4, 16):
+            p = makers[name](n, order=2, precision=32, realizations=R, seed=11)
+            r = time_plan(setd, p, steps, 3, profile=False)
+            costs[(name, tuple(n), R)] = r["ev"] / steps
+    return costs
+
+
+def job_cost(costs, job):
+    p = job["problem"]
+    return costs[(job["model"], tuple(p["n"]), int(p["realizations"]))] * job["steps"]
+
+
+def serve_trace(setd, W, trace):
+    """Run a trace through the server in real time; per-job latencies.  The
+    server keeps every finished job's final state on the host (the audit reads
+    them), so its host budget is raised above the trace's total."""
+    os.environ["SETD_SERVER_KEEP_BYTES"] = str(32 << 30)
     srv = setd.Server(arena_bytes=int(64 * 2**30))
     t_start = setd.setd_clock(srv.lib)
     ids = []
@@ -141,53 +263,98 @@ def serving_run(setd, W, n_jobs, seed, audit=True):
         ids.append((srv.submit(job["problem"], job["steps"]), job))
     srv.drain()
     t_end = setd.setd_clock(srv.lib)
-    lat, su = [], 0
+    rows = []
     for jid, job in ids:
-        times = srv.times(jid)
-        lat.append(times[2] - times[0])
-        su += W.site_updates(job["problem"], job["steps"])
-    out = {"jobs": len(ids), "arrival_rate_per_s": 20.0}
-    lat = np.array(lat)
-    out.update({
-        "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
-        "makespan_s": float(t_end - t_start), "site_updates_per_s": float(su / (t_end - t_start)),
-    })
+        t = srv.times(jid)
+        st = srv.poll(jid)
+        rows.append(dict(job=job, jid=jid, latency=t[2] - t[0], wait=t[1] - t[0], ok=st == (True, setd.SETD_OK)))
+    return srv, rows, t_end - t_start
+
+
+def latency_summary(W, rows, makespan):
+    import numpy as np
+    lat = np.array([r["latency"] for r in rows])
+    su = sum(W.site_updates(r["job"]["problem"], r["job"]["steps"]) for r in rows)
+    return {"jobs": len(rows), "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "makespan_s": float(makespan),
+            "site_updates_per_s": float(su / makespan), "all_ok": all(r["ok"] for r in rows)}
+
+
+def serving_run(setd, W, n_jobs, seed, audit=True, n_sustained=100):
+    """The mixed SETD2 FP32 job stream through the continuous-batching server:
+    the fixed trace (Poisson arrivals at 20 jobs/s, which offers several times
+    what one GPU can serve, so its latencies include queueing) and the same job
+    mix at a sustainable rate chosen from the measured per-type costs so that
+    the offered utilisation is 0.7; per-type breakdown; the same jobs as plain
+    per-job FP64 runs; and an audit of every 20th job in arrival order: its
+    served state equals a solo run (bitwise) and the solo run's first 100
+    steps match the FP64 oracle (realization 0)."""
+    import numpy as np
+    import torch
+    costs = serving_calibration(setd, W)
+    log("serving: per-type costs measured")
+    trace = W.serving_trace(n_jobs=n_jobs, rate=20.0, seed=seed, steps_range=(1000, 10000))
+    mean_cost = float(np.mean([job_cost(costs, j) for j in trace]))
+    srv, rows, makespan = serve_trace(setd, W, trace)
+    log("serving: %d-job trace at 20 jobs/s done in %.1f s" % (n_jobs, makespan))
+    out = {"arrival_rate_per_s": 20.0, "offered_utilisation": 20.0 * mean_cost,
+           "mean_job_gpu_s_alone": mean_cost}
+    out.update(latency_summary(W, rows, makespan))
+    by = {}
+    for r in rows:
+        j = r["job"]
+        b = by.setdefault(j["model"], {"jobs": 0, "site_updates": 0, "gpu_s_alone": 0.0, "lat": []})
+        b["jobs"] += 1
+        b["site_updates"] += W.site_updates(j["problem"], j["steps"])
+        b["gpu_s_alone"] += job_cost(costs, j)
+        b["lat"].append(r["latency"])
+    tot = sum(b["gpu_s_alone"] for b in by.values())
+    out["per_type"] = {k: {"jobs": b["jobs"], "site_updates": b["site_updates"],
+                           "gpu_s_alone": b["gpu_s_alone"], "share_of_gpu_time": b["gpu_s_alone"] / tot,
+                           "p50_latency_s": float(np.percentile(b["lat"], 50)),
+                           "p99_latency_s": float(np.percentile(b["lat"], 99))} for k, b in sorted(by.items())}
     if audit:
         from oracle import oracle as O
-        cheap = sorted(ids, key=lambda x: W.site_updates(x[1]["problem"], x[1]["steps"]))[:max(1, n_jobs // 20)]
-        rows = []
-        for jid, job in cheap:
+        arows = []
+        for r in rows[::20]:
+            job, jid = r["job"], r["jid"]
             p, n = job["problem"], job["steps"]
-            served = srv.get(jid, 0)
             solo = setd.Plan(p)
-            solo.step(n)
-            same = bool(np.array_equal(served, solo.get(0)))
+            solo.step(100)
+            s100 = solo.get(0)
+            solo.step(n - 100)
+            R = int(p["realizations"])
+            same = all(np.array_equal(srv.get(jid, q), solo.get(q)) for q in sorted({0, R - 1}))
             solo.close()
             o = O.Sim(p, r_first=0, r_count=1)
-            o.step(n)
+            o.step(100)
             ref = o.get(0)
-            err = float(np.linalg.norm(served - ref) / max(np.linalg.norm(ref), 1e-300))
-            rows.append({"job": int(job["id"]), "model": job["model"], "n": list(p["n"]),
-                         "realizations": int(p["realizations"]), "steps": int(n),
-                         "served_equals_solo": same, "fp32_rel_err_vs_oracle": err})
-        out["audit"] = rows
+            err = float(np.linalg.norm(s100 - ref) / max(np.linalg.norm(ref), 1e-300))
+            arows.append({"job": int(job["id"]), "model": job["model"], "n": list(p["n"]), "realizations": R,
+                          "steps": int(n), "served_equals_solo": bool(same), "fp32_rel_err_vs_oracle_100_steps": err})
+        out["audit"] = arows
+        log("serving: audit of %d jobs done" % len(arows))
     srv.close()
     torch.cuda.synchronize()
     # plain per-job FP64: every job alone, 100 timed steps after 5 untimed
     su64, t64 = 0, 0.0
-    for _, job in ids:
-        p = dict(job["problem"], precision=64)
-        plan = setd.Plan(p)
-        plan.step(5)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.step(100)
-        torch.cuda.synchronize()
-        t64 += time.perf_counter() - t0
+    for r in rows:
+        p = dict(r["job"]["problem"], precision=64)
+        tp = time_plan(setd, p, 100, 5, profile=False)
+        t64 += tp["wall"]
         su64 += W.site_updates(p, 100)
-        plan.close()
     out["fp64_per_job_site_updates_per_s"] = su64 / t64
     out["served_fp32_over_fp64_per_job"] = out["site_updates_per_s"] / (su64 / t64)
+    log("serving: FP64 per-job rate measured")
+    if n_sustained > 0:
+        lam = 0.7 / mean_cost
+        trace2 = W.serving_trace(n_jobs=n_sustained, rate=lam, seed=seed, steps_range=(1000, 10000))
+        srv2, rows2, mk2 = serve_trace(setd, W, trace2)
+        srv2.close()
+        sus = {"arrival_rate_per_s": lam, "offered_utilisation": lam * mean_cost}
+        sus.update(latency_summary(W, rows2, mk2))
+        out["sustainable"] = sus
+        log("serving: sustainable-rate run (%.2f jobs/s) done in %.1f s" % (lam, mk2))
     return out
 
 
@@ -195,17 +362,27 @@ LINE_STEPS_PER_LAUNCH = 256
 
 
 def other_workloads(setd, W, steps):
-    """Step rate of the KPZ (1024^2 x 16) and CGL (256^3 x 4) workloads and of
-    the 1D lines of the paper's Model A and KPZ figures."""
+    """Step rate and pass roofline of the KPZ (1024^2 x 16) and CGL (256^3 x 4)
+    workloads, and the 1D lines of the paper's Model A and KPZ figures."""
     res = []
-    for name, cfg in (("KPZ 1024x1024, SETD2, FP32, 16 realizations", W.CONFIG_KPZ),
-                      ("CGL 256x256x256, SETD2, complex64, 4 realizations", W.CONFIG_CGL)):
+    for name, cfg, nm in (("KPZ 1024x1024, SETD2, FP32, 16 realizations", W.CONFIG_KPZ, "kpz_1024"),
+                          ("CGL 256x256x256, SETD2, complex64, 4 realizations", W.CONFIG_CGL, "cgl_256")):
         p = W.problem(cfg)
-        el, _, info, ok, _ = time_plan(setd, p, steps, 5, profile=False)
-        sec = el / steps
+        r = time_plan(setd, p, steps, 5, profile=True)
+        info = r["info"]
+        N = int(p["n"][0])
+        names = pass_names_2d(info, N) if p["ndim"] == 2 else pass_names_3d(info, N)
+        if p["nl"] == "kpz":
+            names[0] = names[0].replace("k_row_real", "k_row_real<kpz>")
+        rl, dom, _ = pass_roofline(r, p, names, traffic_workload=nm)
+        sec = r["wall"] / steps
         res.append({"workload": name, "site_updates_per_s": float(info.site_updates_per_step) / sec,
-                    "ms_per_step": 1e3 * sec, "alg_bytes_per_step": float(info.alg_bytes_per_step),
-                    "step_frac": float(info.alg_bytes_per_step / sec / 1e9 / PEAK_HBM_GBS), "ok": bool(ok)})
+                    "ms_per_step": 1e3 * sec, "working_set_bytes": r["workspace"],
+                    "alg_bytes_per_step": rl["step_alg_bytes"], "moved_bytes_per_step": rl["step_moved_bytes"],
+                    "step_frac": rl["step_alg_bytes"] / sec / 1e9 / PEAK_HBM_GBS,
+                    "step_frac_moved": rl["step_moved_bytes"] / sec / 1e9 / PEAK_HBM_GBS,
+                    "roofline": rl, "ok": bool(r["ok"])})
+        log("%s: %.4f ms/step" % (name, 1e3 * sec))
     return res + line_workloads(setd, W, "ak")
 
 
@@ -221,11 +398,12 @@ def line_workloads(setd, W, which):
         name, cfg = LINES[key]
         p = W.problem(getattr(W, cfg))
         k = 8 * LINE_STEPS_PER_LAUNCH
-        el, _, info, ok, _ = time_plan(setd, p, k, LINE_STEPS_PER_LAUNCH, profile=False)
-        sec = el / k
+        r = time_plan(setd, p, k, LINE_STEPS_PER_LAUNCH, profile=False)
+        info = r["info"]
+        sec = r["wall"] / k
         res.append({"workload": name, "site_updates_per_s": float(info.site_updates_per_step) / sec,
                     "ms_per_step": 1e3 * sec, "steps_per_launch": LINE_STEPS_PER_LAUNCH,
-                    "hbm_bytes_per_launch": float(info.alg_bytes_per_step), "ok": bool(ok)})
+                    "hbm_bytes_per_launch": float(info.alg_bytes_per_step), "ok": bool(r["ok"])})
     return res
 
 
@@ -281,10 +459,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the host oracle baseline and the serving audit")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
-    ap.add_argument("--serving-jobs", type=int, default=40, help="0 skips the serving run")
-    ap.add_argument("--no-other", action="store_true", help="skip the KPZ and CGL step rates")
+    ap.add_argument("--serving-jobs", type=int, default=200, help="0 skips the serving run")
+    ap.add_argument("--sustained-jobs", type=int, default=100,
+                    help="jobs of the serving run at the sustainable rate (0 skips it)")
+    ap.add_argument("--no-other", action="store_true", help="skip the other workloads")
     ap.add_argument("--lines", choices=["a", "k", "ak"], default=None,
                     help="time only the 1D line workloads (a: Model A, k: KPZ) and print them")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -295,7 +475,6 @@ def main():
               "(realizations would shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_2511_22510_amd import setd, workloads as W
 
@@ -311,39 +490,21 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     p = W.problem(W.CONFIG_B)
-    elapsed, prof, info, ok, t_prof = time_plan(setd, p, args.steps, args.warmup, profile=True)
-    if not ok:
+    # the per-pass segment is at least 200 steps, so that the event-gap
+    # correction (a difference of two timings) is well resolved
+    r = time_plan(setd, p, args.steps, args.warmup, profile=True, prof_steps=max(args.steps, 200))
+    if not r["ok"]:
         print("bench: the batched run did not complete cleanly", file=sys.stderr)
         sys.exit(1)
+    info = r["info"]
     sites = float(info.site_updates_per_step)
+    elapsed = r["wall"]
     value = sites * args.steps / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
-
-    rv = int(info.variants[0])
-    pass_names = ["k_row_real<float,512,pad=%d,block=%d,pair_groups=%d>" % (3 if rv & 1 else 0, 256 if rv & 2 else 64,
-                                                                           1 << ((rv >> 2) & 3)),
-                  ("k_axis0r<float,512,tile=%d>" % info.axis_tile[0]) if int(info.variants[1]) >= 4 else
-                  "k_axis0<float,512,tile=%d,cols_per_thread=%d>" % (info.axis_tile[0], info.axis_tile[1])]
-    tot_ms = prof[:, 0]
-    cnt = prof[:, 1]
-    dom = int(np.argmax(tot_ms))
-    avg_s = tot_ms[dom] / cnt[dom] * 1e-3
-    alg = float(info.pass_bytes[dom])
-    achieved = alg / avg_s / 1e9
-    traffic = measured_traffic(pass_names[dom])
-    roofline = {
-        "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-        "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-        "kernel": pass_names[dom], "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": alg,
-        "passes": [{"kernel": pass_names[i], "avg_us": float(tot_ms[i] / cnt[i] * 1e3),
-                    "alg_bytes": float(info.pass_bytes[i]),
-                    "gbs": float(info.pass_bytes[i] / (tot_ms[i] / cnt[i] * 1e-3) / 1e9)}
-                   for i in range(len(tot_ms))],
-        "timed_with_events_ms_per_step": 1e3 * t_prof / args.steps,
-        "valu": valu_roofline(pass_names, tot_ms / cnt * 1e-3, dom),
-        "step_alg_bytes": float(info.alg_bytes_per_step),
-        "step_frac": float(info.alg_bytes_per_step / (elapsed / args.steps) / 1e9 / PEAK_HBM_GBS),
-    }
+    names = pass_names_2d(info, 512)
+    roofline, dom, avg = pass_roofline(r, p, names, traffic_workload="model_b_512")
+    roofline["valu"] = valu_roofline(names, avg, dom)
+    log("Model B 512^2 x 64: %.4f ms/step" % ms_per_step)
 
     line = {
         "metric": "site-updates/s per SETD step, batched FP32 vs plain FP64; p99 job latency",
@@ -355,27 +516,49 @@ def main():
                    "lattice": [512, 512], "realizations": 64, "scheme": "SETD2", "h": 0.005,
                    "global_batch": 64, "parallelism": "single GPU"},
         "roofline": roofline,
+        "working_set_bytes": r["workspace"],
     }
+
+    # the same model with a working set beyond the 256 MB Infinity Cache
+    p256 = W.problem(W.CONFIG_B, realizations=256)
+    r2 = time_plan(setd, p256, max(args.steps // 4, 50), 5, profile=True, prof_steps=100)
+    rl2, _, _ = pass_roofline(r2, p256, pass_names_2d(r2["info"], 512), traffic_workload="model_b_512_r256")
+    sec2 = r2["wall"] / max(args.steps // 4, 50)
+    line["beyond_infinity_cache"] = {
+        "workload": "Model B 512x512, SETD2, complex64, 256 realizations", "working_set_bytes": r2["workspace"],
+        "ms_per_step": 1e3 * sec2, "site_updates_per_s": float(r2["info"].site_updates_per_step) / sec2,
+        "roofline": rl2, "ok": bool(r2["ok"])}
+    log("Model B 512^2 x 256: %.4f ms/step" % (1e3 * sec2))
 
     if not args.no_fp64:
         p64 = W.problem(W.CONFIG_B, precision=64, realizations=1)
         k64 = max(args.steps, 200)
-        e64, _, info64, ok64, _ = time_plan(setd, p64, k64, args.warmup, profile=False)
-        v64 = float(info64.site_updates_per_step) * k64 / e64
+        r64 = time_plan(setd, p64, k64, args.warmup, profile=False)
+        v64 = float(r64["info"].site_updates_per_step) * k64 / r64["wall"]
         line["fp64_plain"] = {"workload": "Model B 512x512, SETD2, complex128, 1 realization",
-                              "value": v64, "ms_per_step": 1e3 * e64 / k64, "ok": bool(ok64)}
+                              "value": v64, "ms_per_step": 1e3 * r64["wall"] / k64, "ok": bool(r64["ok"])}
         line["fp32_batched_over_fp64_plain"] = value / v64
+        # the first workload as specified: Model A 64^2, plain SETD1, FP64, one
+        # realization, all 1000 steps
+        pa = W.problem(W.CONFIG_A)
+        ra = time_plan(setd, pa, W.CONFIG_A["steps"], args.warmup, profile=False)
+        line["config_a"] = {"workload": "Model A 64x64, SETD1, FP64, 1 realization, 1000 steps",
+                            "seconds": ra["wall"], "ms_per_step": 1e3 * ra["wall"] / W.CONFIG_A["steps"],
+                            "steps_per_s": W.CONFIG_A["steps"] / ra["wall"],
+                            "site_updates_per_s": 64 * 64 * W.CONFIG_A["steps"] / ra["wall"], "ok": bool(ra["ok"])}
+        log("FP64 plain and Model A 64^2 timed")
 
     if not args.no_other:
         line["other_workloads"] = other_workloads(setd, W, 50)
         line["sde"] = sde_rate(setd)
 
-    if args.serving_jobs > 0 and hasattr(setd, "Server"):
-        line["serving"] = serving_run(setd, W, args.serving_jobs, seed=2024, audit=not args.no_cpu)
+    if args.serving_jobs > 0:
+        line["serving"] = serving_run(setd, W, args.serving_jobs, seed=2024, audit=not args.no_cpu,
+                                      n_sustained=args.sustained_jobs)
 
     if not args.no_cpu:
         from oracle import oracle as O
-        R_cpu, steps_cpu = 8, 300
+        R_cpu, steps_cpu = 24, 100
         o = O.Sim(p, r_first=0, r_count=R_cpu)
         t0 = time.perf_counter()
         o.step(steps_cpu)
@@ -384,8 +567,10 @@ def main():
         line["cpu_baseline"] = {
             "value": 512 * 512 * R_cpu * steps_cpu / dt, "unit": "site-updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": "Model B 512x512 SETD2 FP64 oracle, %d realizations x %d steps (%.1f s)" % (R_cpu, steps_cpu, dt),
+            "sample": "Model B 512x512 SETD2 FP64 oracle, realizations 0..%d over the 100-step parity window "
+                      "(%.1f s)" % (R_cpu - 1, dt),
         }
+        log("CPU oracle timed")
 
     print(json.dumps(line), flush=True)
 

@@ -27,14 +27,35 @@ def test_valu_summary_is_read_by_label_and_gated_by_hash(tmp_path, monkeypatch):
 
 
 def test_traffic_summary_is_gated_by_kernel_and_hash(tmp_path, monkeypatch):
-    f = tmp_path / "traffic.txt"
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    f = tmp_path / "traffic_wl.txt"
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
     h = bench.kernel_source_hash()
     _write(f, "kernel = k_axis0r<float,512,tile=8>\nsource_hash = %s\nhbm_bytes_per_launch = 5.5e8\n" % h)
-    assert bench.measured_traffic("k_axis0r<float,512,tile=8>") == 5.5e8
-    assert bench.measured_traffic("k_axis0r<float,512,tile=16>") is None
+    assert bench.measured_traffic("k_axis0r<float,512,tile=8>", "wl") == 5.5e8
+    assert bench.measured_traffic("k_axis0r<float,512,tile=16>", "wl") is None
+    assert bench.measured_traffic("k_axis0r<float,512,tile=8>", "other") is None
     _write(f, "kernel = k_axis0r<float,512,tile=8>\nsource_hash = x\nhbm_bytes_per_launch = 5.5e8\n")
-    assert bench.measured_traffic("k_axis0r<float,512,tile=8>") is None
+    assert bench.measured_traffic("k_axis0r<float,512,tile=8>", "wl") is None
+
+
+def test_pass_model_bytes_match_the_workload_table():
+    """The pass model's bytes per step of each workload: Model A 64^2 FP64 SETD1
+    0.12 MB (29.4 B per site-update), Model B 512^2 x 64 298.7 MB (17.8 B), the
+    plain FP64 Model B 35.6 B, KPZ 1024^2 x 16 388.6 MB (23.2 B), CGL 256^3 x 4
+    3.03 GB (45.2 B)."""
+    from paper_2511_22510_amd import workloads as W
+    cases = [(W.problem(W.CONFIG_A), 0.12e6, 29.4), (W.problem(W.CONFIG_B), 298.7e6, 17.8),
+             (W.problem(W.CONFIG_B, precision=64, realizations=1), 9.3e6, 35.6),
+             (W.problem(W.CONFIG_KPZ), 388.6e6, 23.2), (W.problem(W.CONFIG_CGL), 3.03e9, 45.2)]
+    for p, step_bytes, per_site in cases:
+        b = bench.survey_pass_bytes(p)
+        assert len(b) == (4 if p["ndim"] == 3 else 2)
+        tot = sum(b)
+        sites = W.site_updates(p, 1)
+        assert abs(tot / step_bytes - 1) < 0.01, (p["nl"], tot)
+        assert abs(tot / sites - per_site) < 0.05, (p["nl"], tot / sites)
+    # the dominant (axis-0) pass of Model B: 209.07 MB
+    assert abs(bench.survey_pass_bytes(W.problem(W.CONFIG_B))[1] - 209.07e6) < 0.01e6
 
 
 def test_valu_roofline_uses_the_issue_peak():
