@@ -210,17 +210,23 @@ def pass_roofline(r, p, names, traffic_workload=None):
     }, dom, avg
 
 
+def axis0_name(info, N):
+    v = int(info.variants[1])
+    if v >= 4:
+        # register kernel: variants 4 + 2j / 5 + 2j interleave items in groups of 2^j
+        return "k_axis0r<float,%d,tile=%d,group=%d>" % (N, info.axis_tile[0], 1 << ((v - 4) // 2))
+    return "k_axis0<float,%d,tile=%d,cols_per_thread=%d>" % (N, info.axis_tile[0], info.axis_tile[1])
+
+
 def pass_names_2d(info, N):
     rv = int(info.variants[0])
     return ["k_row_real<float,%d,pad=%d,block=%d,pair_groups=%d>" % (N, 3 if rv & 1 else 0, 256 if rv & 2 else 64,
                                                                      1 << ((rv >> 2) & 3)),
-            ("k_axis0r<float,%d,tile=%d>" % (N, info.axis_tile[0])) if int(info.variants[1]) >= 4 else
-            "k_axis0<float,%d,tile=%d,cols_per_thread=%d>" % (N, info.axis_tile[0], info.axis_tile[1])]
+            axis0_name(info, N)]
 
 
 def pass_names_3d(info, N):
-    return ["k_axis1<inverse,%d>" % N, "k_row_cplx<%d>" % N, "k_axis1<forward,%d>" % N,
-            "k_axis0r<float,%d,tile=%d>" % (N, info.axis_tile[0])]
+    return ["k_axis1<inverse,%d>" % N, "k_row_cplx<%d>" % N, "k_axis1<forward,%d>" % N, axis0_name(info, N)]
 
 
 def log(*a):

@@ -208,7 +208,9 @@ typedef struct {
                                  variant bits: 0 LDS padding, 1 256-thread
                                  workgroups, 2-3 log2 of the row-pair groups a
                                  workgroup takes in turn (real fields); axis-0
-                                 variants 4 and 5 update in registers           */
+                                 variants 4 and up update in registers: 4 + 2j
+                                 and 5 + 2j at two tile widths, the items
+                                 interleaved per column tile in groups of 2^j   */
     int axis_tile[2];         /* axis-0 pass: column tile width, columns per thread */
     int streams;              /* 2 when setd_step runs the two halves of the
                                  realizations on the bound stream and an
@@ -337,6 +339,15 @@ setd_status setd_job_get_field(setd_server* server, setd_job job, int realizatio
 /* Host timestamps of a job in seconds on a monotonic clock:
    out[0] submit, out[1] admit, out[2] finish; out[3] steps done. */
 setd_status setd_job_times(setd_server* server, setd_job job, double* out4);
+
+/* Counters of the server since its creation: out[0] scheduler ticks that ran
+   steps, out[1] pass launches those ticks queued (per launch unit and
+   sub-step), out[2] the launches among them that several lattice classes
+   shared (2D real fields of square lattices N = 64..512, complex64, 2/3 rule,
+   SETD2, phi^3 nonlinearities: one launch per pass for all of them;
+   environment SETD_SERVER_MULTI=0 at creation keeps one launch per class).
+   cap >= 3; *len receives 3. */
+setd_status setd_server_stats(setd_server* server, double* out, size_t cap, size_t* len);
 
 /* Stop the scheduler thread and release the server (jobs still queued are
    dropped; the arena itself is the caller's). */

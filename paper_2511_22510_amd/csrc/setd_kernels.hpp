@@ -238,6 +238,7 @@ struct AxisArgs {
     int sub;
     int ctab;      // register axis-0 kernel, keyed coefficients: stage them in LDS (the launch sized it)
     int alt;       // axis-1 pass: the noise intermediate npre in place of pre0
+    int group;     // register axis-0 kernel: items interleaved per column tile (1: item after item)
 };
 
 struct LinArgs {
@@ -279,16 +280,18 @@ __device__ __forceinline__ unsigned xcd_logical(unsigned L, unsigned G)
 // DA: the 2/3 rule is on; then bins q = 0, 1 (k < N/4) always hold a stored
 // mode, q = 6, 7 (k >= 3N/4) always its mirror, q = 3, 4 never any, and only
 // q = 0..2 are written back, all decided at compile time.
+// The body takes the block's grid position (bx, by) and thread: the kernel
+// below passes its own, the shared launch of several lattice classes its
+// position within the class.
 template <typename T, int N, int PAD, int KIND, bool DA, bool PF>
-__global__ void __launch_bounds__(256) k_row_real(RowArgs a)
+__device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, const int by, const int tid)
 {
-    const Item it = a.items[blockIdx.y];
+    const Item it = a.items[by];
     if (a.sub >= it.steps) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     constexpr int TPL = N / 8;
     constexpr uint32_t ES = sizeof(cx<T>);
-    const int tid = threadIdx.x;
     const int l = tid / TPL, t = tid - l * TPL;
     // KPZ steps hold two lines per row pair in LDS
     cx<T>* L = lds + l * (KIND == 1 ? 2 : 1) * lds_len<N, PAD>();
@@ -301,10 +304,10 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
     line_tw_expand(twp, tw);
     const int pitch = g.pitch;
     const int K = g.kp[last];
-    // pair groups blockIdx.x iter + i, i < niter (the same count in every lane)
+    // pair groups bx iter + i, i < niter (the same count in every lane)
     const int npair = (a.nrows + 1) / 2;
     const int ngrp = (npair + a.lpw - 1) / a.lpw;
-    const int grp0 = blockIdx.x * a.iter;
+    const int grp0 = bx * a.iter;
     // without prefetch the launch gives every workgroup one group
     const int niter = PF ? min(a.iter, ngrp - grp0) : 1;
     // rows of this block, clipped to the array
@@ -388,7 +391,7 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
             // barriers, twice the independent work per exchange), interleaved in LDS
             // read from the item in global memory: indexing the private copy
             // with the run-time axis would keep all of it in scratch memory
-            const T dkl = (T)a.items[blockIdx.y].dk[last];
+            const T dkl = (T)a.items[by].dk[last];
             cx<T> w[2][8];
 #pragma unroll
             for (int s = 0; s < 2; s++) {
@@ -473,6 +476,12 @@ __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
             bstore<T>(rb, c + o1, 0, {T(0.5) * (Zk.y + Zm.y), T(0.5) * (Zm.x - Zk.x)});
         }
     }
+}
+
+template <typename T, int N, int PAD, int KIND, bool DA, bool PF>
+__global__ void __launch_bounds__(256) k_row_real(RowArgs a)
+{
+    row_real_body<T, N, PAD, KIND, DA, PF>(a, blockIdx.x, blockIdx.y, threadIdx.x);
 }
 
 // ---------------------------------------------------------------- row pass, complex field
@@ -912,24 +921,25 @@ constexpr int axis0r_waves()
     return blocks * w / 4 > 1 ? blocks * w / 4 : 1;
 }
 
+// The body runs one column tile (blk) of one item with TILE * N0 / 8 threads
+// (tid) and the LDS at byte lds_off; herm_sync says whether the block holding
+// these threads also holds tile 0 of a 2D lattice (its Hermitian column needs
+// a barrier of the whole block).  The kernel below runs one tile per block,
+// the shared launch of several lattice classes one or more.
 template <typename T, int N0, int TILE, int PAD, int KIND, bool LEAN>
-__global__ void __launch_bounds__(TILE * N0 / 8)
-__attribute__((amdgpu_waves_per_eu(axis0r_waves<T, TILE * N0 / 8>())))
-k_axis0r(AxisArgs a)
+__device__ __forceinline__ void axis0r_body(const AxisArgs& a, const int item, const int blk, const int tid,
+                                            const unsigned lds_off, const bool herm_sync)
 {
     constexpr bool KPZ = KIND == 1, CC = KIND == 2;
-    const unsigned lg = xcd_logical(blockIdx.x, gridDim.x);
-    const int item = (int)(lg / (unsigned)a.per_item);
-    const int blk = (int)(lg % (unsigned)a.per_item);
     const Item it = a.items[item];
     if (a.sub >= it.steps) return;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+    extern __shared__ __align__(16) unsigned char smem_base[];
+    unsigned char* const smem_raw = smem_base + lds_off;
     cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
     const Geo& g = a.g;
     constexpr int TPL = N0 / 8;
     constexpr uint32_t ES = sizeof(cx<T>);
     constexpr uint32_t CS = (CC ? 8 : 4) * sizeof(T);   // bytes of a coefficient entry
-    const int tid = threadIdx.x;
     const int c0 = tid % TILE, t = tid / TILE;
     const int tile = blk % a.ntiles, i1 = blk / a.ntiles;
     const int last = g.ndim - 1;
@@ -1064,7 +1074,7 @@ k_axis0r(AxisArgs a)
     if (staged) {
         __syncthreads();   // every lane has read its last transform values
         const int nent = (kp0 + 1) * TILE;
-        for (int e = tid; e < nent; e += (int)blockDim.x) {
+        for (int e = tid; e < nent; e += TILE * N0 / 8) {
             const int m = e / TILE, c = e - m * TILE;
             const int col = tile * TILE + c;
             int alc = col;
@@ -1211,8 +1221,8 @@ k_axis0r(AxisArgs a)
     // (q <= 2) independent; row 0 is self-conjugate.  LDS is free between the
     // barrier above and the one that opens the inverse transform.
     if constexpr (!CC) {
-        if (g.ndim == 2 && tile == 0) {
-            if (c0 == 0) {
+        if (g.ndim == 2 && herm_sync) {
+            if (tile == 0 && c0 == 0) {
 #pragma unroll
                 for (int q = 0; q < 3; q++) {
                     if (!stored(q)) continue;
@@ -1222,7 +1232,7 @@ k_axis0r(AxisArgs a)
                 }
             }
             __syncthreads();
-            if (c0 == 0) {
+            if (tile == 0 && c0 == 0) {
 #pragma unroll
                 for (int q = 5; q < 8; q++) {
                     if (!stored(q)) continue;
@@ -1266,6 +1276,115 @@ k_axis0r(AxisArgs a)
     // the last block of this realization advances its step counter
     __syncthreads();
     if (tid == 0) advance_step(it.ctrl, (unsigned)a.per_item, nstep);
+}
+
+template <typename T, int N0, int TILE, int PAD, int KIND, bool LEAN>
+__global__ void __launch_bounds__(TILE * N0 / 8)
+__attribute__((amdgpu_waves_per_eu(axis0r_waves<T, TILE * N0 / 8>())))
+k_axis0r(AxisArgs a)
+{
+    // Logical blocks in groups of `group` items: within a group, consecutive
+    // blocks take one block position (column tile) of each of the group's
+    // items in turn, so the coefficient rows of a tile, which every item
+    // reads, are used group times while in L2; an XCD's contiguous range of
+    // logical blocks covers whole groups.  group 1: one item after the other.
+    const unsigned lg = xcd_logical(blockIdx.x, gridDim.x);
+    const unsigned P = (unsigned)a.per_item, G = (unsigned)a.group;
+    const unsigned nit = gridDim.x / P;
+    const unsigned grp = lg / (G * P), w = lg % (G * P);
+    const unsigned gsz = min(G, nit - grp * G);   // items in this group (the last may hold fewer)
+    const int item = (int)(grp * G + w % gsz);
+    const int blk = (int)(w / gsz);
+    axis0r_body<T, N0, TILE, PAD, KIND, LEAN>(a, item, blk, threadIdx.x, 0u, blk % a.ntiles == 0);
+}
+
+// ---------------------------------------------------------------- launches shared by lattice classes
+// The 2D real-field classes of a serving tick that differ only in the lattice
+// size (square N = 64, 128, 256 or 512; complex64; 2/3 rule; SETD2 carry;
+// the phi^3 nonlinearities) advance in one launch per pass.  The arguments
+// hold one slot per size; a block finds its slot from the slots' first blocks
+// and runs that size's body, so every slot's body is compiled once and its
+// arguments are read at fixed offsets.  Row pass: 256-thread blocks at every
+// size (the same LDS, 18 KiB).  Axis-0 pass: 512-thread blocks; tile 8 for
+// N = 512 and 16 otherwise, and for N <= 128 a block holds SUB = 2 or 4
+// sub-blocks of one item (sub-block k runs tile SUB b + k of the item's
+// b-th block; those past its last tile read and store nothing), so that all
+// threads of a block meet the same barriers; every size uses 36 KiB of LDS.
+constexpr int MULTI_SLOTS = 4;   // N = 64 << slot
+
+__host__ __device__ constexpr int multi_tile(int slot) { return slot == 3 ? 8 : 16; }
+__host__ __device__ constexpr int multi_sub(int slot) { return 512 / (multi_tile(slot) * ((64 << slot) / 8)); }
+
+struct MultiRowArgs {
+    RowArgs a[MULTI_SLOTS];
+    int first[MULTI_SLOTS + 1];   // first block of each slot; first[MULTI_SLOTS] = the grid
+    int gx[MULTI_SLOTS];          // blocks per item
+};
+
+struct MultiAxArgs {
+    AxisArgs a[MULTI_SLOTS];      // a[s].per_item counts sub-blocks; a[s].ntiles covers them
+    int first[MULTI_SLOTS + 1];
+    int bpi[MULTI_SLOTS];         // blocks per item
+};
+
+// the slot of block b: the last one whose first block is <= b (empty slots
+// share their successor's first block)
+__device__ __forceinline__ int multi_slot(const int (&first)[MULTI_SLOTS + 1], int b)
+{
+    int s = 0;
+#pragma unroll
+    for (int i = 1; i < MULTI_SLOTS; i++)
+        if (b >= first[i]) s = i;
+    return s;
+}
+
+template <typename T, int SLOT>
+__device__ __forceinline__ void row_multi_slot(const MultiRowArgs& m, int b)
+{
+    constexpr int N = 64 << SLOT;
+    const int local = b - m.first[SLOT];
+    row_real_body<T, N, 3, 0, true, false>(m.a[SLOT], local % m.gx[SLOT], local / m.gx[SLOT], threadIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_row_multi(MultiRowArgs m)
+{
+    const int b = blockIdx.x;
+    switch (multi_slot(m.first, b)) {
+    case 0: row_multi_slot<T, 0>(m, b); break;
+    case 1: row_multi_slot<T, 1>(m, b); break;
+    case 2: row_multi_slot<T, 2>(m, b); break;
+    default: row_multi_slot<T, 3>(m, b); break;
+    }
+}
+
+template <typename T, int SLOT>
+__device__ __forceinline__ void axis0_multi_slot(const MultiAxArgs& m, int lg)
+{
+    constexpr int N0 = 64 << SLOT, TILE = multi_tile(SLOT), SUB = multi_sub(SLOT);
+    constexpr int SUBT = TILE * N0 / 8;   // threads of a sub-block
+    constexpr int PAD = 3;
+    constexpr unsigned SUBLDS = (unsigned)(TILE * lds_len<N0, PAD>() * 2 * sizeof(T));
+    const int local = lg - m.first[SLOT];
+    const int item = local / m.bpi[SLOT], blk = local % m.bpi[SLOT];
+    const int k = (int)threadIdx.x / SUBT;
+    axis0r_body<T, N0, TILE, PAD, 0, true>(m.a[SLOT], item, blk * SUB + k, (int)threadIdx.x - k * SUBT,
+                                           (unsigned)k * SUBLDS, blk == 0);
+}
+
+// (the four bodies in one function need more registers than any of them
+// alone: at the three waves per SIMD targeted here they fit without spills)
+template <typename T>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
+k_axis0_multi(MultiAxArgs m)
+{
+    const int lg = (int)xcd_logical(blockIdx.x, gridDim.x);
+    switch (multi_slot(m.first, lg)) {
+    case 0: axis0_multi_slot<T, 0>(m, lg); break;
+    case 1: axis0_multi_slot<T, 1>(m, lg); break;
+    case 2: axis0_multi_slot<T, 2>(m, lg); break;
+    default: axis0_multi_slot<T, 3>(m, lg); break;
+    }
 }
 
 // ---------------------------------------------------------------- axis-1 pass (3D)

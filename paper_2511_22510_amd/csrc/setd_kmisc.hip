@@ -213,7 +213,8 @@ void axis_shape(int precision, int n, int var, int* tile, int* lpt)
     const int tm = (precision == 32) ? (n <= 512 ? 16 : 8) : (n <= 512 ? 8 : 4);
     static const int tl[6] = {1, 1, 1, 2, 2, 1};
     static const int lp[6] = {2, 1, 4, 1, 1, 1};
-    const int v = (var >= 0 && var < 6) ? var : 0;
+    // register-kernel variants 4 + 2j / 5 + 2j share the tiles of 4 / 5
+    const int v = (var >= 0 && var < 6) ? var : (var >= 6 && var < 12 ? 4 + (var - 4) % 2 : 0);
     *tile = tm / tl[v] > 0 ? tm / tl[v] : 1;
     *lpt = lp[v];
 }

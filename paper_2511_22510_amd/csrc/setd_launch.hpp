@@ -54,7 +54,26 @@ hipError_t launch_fdt_reduce(const Geo& g, const double* dacc, int total, int M,
 // axis-1 and axis-0 pass variants)
 template <typename T>
 hipError_t launch_rsn(const Geo& g, const Item* items, int nitems, int sub, int var1, int var0, hipStream_t s);
-// 1D lattices: nsteps steps per launch (MODE_STEP) or the initial condition (MODE_IC)
+// Lattice classes that share one launch per pass (k_row_multi, k_axis0_multi):
+// 2D real fields on square lattices of N = 64, 128, 256 or 512 points, complex64,
+// 2/3 rule, SETD2 with the carry storage, a phi^3 nonlinearity, Fourier-space
+// noise.  Slot s of launch_multi2d takes the class of N = 64 << s (nitems 0:
+// none); pass 0 is the row pass, 1 the axis-0 pass with the update.
+struct MultiClass {
+    Geo g;
+    const Item* items;
+    int nitems;
+};
+inline bool multi2d_ok(const Geo& g, bool lean, int nl)
+{
+    const int n = g.n[0];
+    return g.ndim == 2 && !g.cplx && g.prec == 32 && g.dealias == 1 && !g.rsn && lean && n == g.n[1] &&
+           (n == 64 || n == 128 || n == 256 || n == 512) && (nl == NL_PHI3 || nl == NL_PHI3_CONS);
+}
+inline int multi2d_slot(int n) { return n == 64 ? 0 : n == 128 ? 1 : n == 256 ? 2 : 3; }
+template <typename T>
+hipError_t launch_multi2d(const MultiClass (&cls)[4], int pass, int sub, hipStream_t s);
+// 1D lattices: nsteps steps per launch// 1D lattices: nsteps steps per launch (MODE_STEP) or the initial condition (MODE_IC)
 template <typename T>
 hipError_t launch_line1d(const Geo& g, const Item* items, int nitems, int mode, int sub, int nsteps, int nl,
                          hipStream_t s);

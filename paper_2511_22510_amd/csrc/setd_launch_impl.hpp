@@ -7,7 +7,8 @@
 //              {(tm, 2), (tm, 1), (tm, 4), (tm/2, 1)}, tm = tile_max, with LDS
 //              padding whenever the padded tile still fits 64 KiB; the axis-0
 //              time step also has the register-update kernel k_axis0r with
-//              tile tm/2 (variant 4) or tm (variant 5)
+//              tile tm/2 (variants 4, 6, 8, 10) or tm (5, 7, 9, 11), its items
+//              interleaved per column tile in groups of 1, 2, 4 or 8
 #pragma once
 
 #include <cmath>
@@ -149,7 +150,7 @@ static hipError_t launch_hermitian_t(const Geo& g, const Item* items, int nitems
 // axis-0 pass with the update in registers (k_axis0r), one column per thread group
 template <typename T, int N, int TILE>
 static hipError_t launch_axis0r(const Geo& g, const Item* items, int nitems, int mode, int sub, bool kpz,
-                                bool lean, hipStream_t s)
+                                bool lean, int group, hipStream_t s)
 {
     constexpr int PAD = tile_pad<T, N, TILE>();
     AxisArgs a{};
@@ -167,6 +168,7 @@ static hipError_t launch_axis0r(const Geo& g, const Item* items, int nitems, int
     const size_t tab = (size_t)(g.kp[0] + 1) * TILE * (g.cplx ? 8 : 4) * sizeof(T);
     a.ctab = (g.ndim == 3 && tab <= 65536) ? 1 : 0;
     if (a.ctab && tab > lds) lds = tab;
+    a.group = group < 1 ? 1 : (group > nitems ? nitems : group);
     if (lean) {
         if (g.cplx) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 2, true>), grid, block, lds, s, a);
         else if (kpz) hipLaunchKernelGGL((k_axis0r<T, N, TILE, PAD, 1, true>), grid, block, lds, s, a);
@@ -190,18 +192,21 @@ static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int
         // (axis0_register_ok); other modes and plans take the tile-sweep
         // kernel.  A plan keeping the SETD2 carry steps with the register
         // kernel only.
+        // variants 4 + 2j (tile TM/2) and 5 + 2j (tile TM): items interleaved in
+        // groups of 2^j per column tile
         const bool reg = mode == MODE_STEP && axis0_register_ok(g, sizeof(T));
         if (reg && lean && var < 4) var = 4;
-        if (reg && (var == 4 || var == 5)) {
-            hipError_t e = (var == 4) ? launch_axis0r<T, N, (TM >= 2 ? TM / 2 : 1)>(g, items, nitems, mode, sub, kpz, lean, s)
-                                      : launch_axis0r<T, N, TM>(g, items, nitems, mode, sub, kpz, lean, s);
+        if (reg && var >= 4) {
+            const int group = 1 << ((var - 4) / 2);
+            hipError_t e = ((var - 4) % 2 == 0)
+                               ? launch_axis0r<T, N, (TM >= 2 ? TM / 2 : 1)>(g, items, nitems, mode, sub, kpz, lean, group, s)
+                               : launch_axis0r<T, N, TM>(g, items, nitems, mode, sub, kpz, lean, group, s);
             // the register kernel keeps a 2D real field's column a_last = 0
             // Hermitian itself; 3D planes span several blocks
             if (e == hipSuccess && g.ndim == 3) e = launch_hermitian_t<T>(g, items, nitems, lean ? 1 : 0, sub, s);
             return e;
         }
-        if (var == 4) var = 3;
-        else if (var == 5) var = 0;
+        if (var >= 4) var = ((var - 4) % 2 == 0) ? 3 : 0;
     }
     hipError_t e;
     switch (var) {
@@ -282,6 +287,56 @@ hipError_t launch_rsn(const Geo& g, const Item* items, int nitems, int sub, int 
     // field's Hermitian planes
     SETD_DISPATCH_N(g.n[0], e = (launch_axis_n<T, NN, true>(g, items, nitems, MODE_RSN, sub, var0, false, false, s)));
     return e;
+}
+
+template <typename T>
+hipError_t launch_multi2d(const MultiClass (&cls)[4], int pass, int sub, hipStream_t s)
+{
+    static_assert(MULTI_SLOTS == 4, "one class slot per lattice size 64..512");
+    int total = 0;
+    if (pass == 0) {
+        MultiRowArgs m{};
+        for (int k = 0; k < MULTI_SLOTS; k++) {
+            const int N = 64 << k, lpw = 256 / (N / 8);
+            m.first[k] = total;
+            RowArgs& a = m.a[k];
+            a.g = cls[k].g;
+            a.items = cls[k].items;
+            a.nrows = N;
+            a.lpw = lpw;
+            a.iter = 1;
+            a.mode = MODE_STEP;
+            a.sub = sub;
+            m.gx[k] = (N / 2 + lpw - 1) / lpw;
+            if (cls[k].nitems > 0 && (cls[k].g.n[0] != N || cls[k].g.n[1] != N)) return hipErrorInvalidValue;
+            total += cls[k].nitems * m.gx[k];
+        }
+        m.first[MULTI_SLOTS] = total;
+        if (total == 0) return hipSuccess;
+        // lpw lines of N + N/8 elements: 2048/N x 9N/8 = 2304 at every size
+        hipLaunchKernelGGL((k_row_multi<T>), dim3(total), dim3(256), (size_t)2304 * sizeof(cx<T>), s, m);
+    } else {
+        MultiAxArgs m{};
+        for (int k = 0; k < MULTI_SLOTS; k++) {
+            const int tile = multi_tile(k), subs = multi_sub(k);
+            m.first[k] = total;
+            AxisArgs& a = m.a[k];
+            a.g = cls[k].g;
+            a.items = cls[k].items;
+            m.bpi[k] = cls[k].nitems > 0 ? (cls[k].g.pitch / tile + subs - 1) / subs : 0;
+            a.ntiles = m.bpi[k] * subs;
+            a.per_item = m.bpi[k] * subs;
+            a.mode = MODE_STEP;
+            a.sub = sub;
+            if (cls[k].nitems > 0 && cls[k].g.pitch % tile != 0) return hipErrorInvalidValue;
+            total += cls[k].nitems * m.bpi[k];
+        }
+        m.first[MULTI_SLOTS] = total;
+        if (total == 0) return hipSuccess;
+        // 36 KiB at every size: tile x (N + N/8) elements x 2 reals
+        hipLaunchKernelGGL((k_axis0_multi<T>), dim3(total), dim3(512), (size_t)8 * 576 * 2 * sizeof(T), s, m);
+    }
+    return hipGetLastError();
 }
 
 template <typename T>

@@ -575,7 +575,7 @@ setd_status Plan::autotune()
     // SETD_VARIANT="row,axis0,axis1" pins the variants (tests, reproducible timing)
     if (const char* pin = std::getenv("SETD_VARIANT")) {
         int r = 0, a0 = 0, a1 = 0;
-        if (sscanf(pin, "%d,%d,%d", &r, &a0, &a1) == 3 && r >= 0 && r < 16 && a0 >= 0 && a0 < 6 && a1 >= 0 && a1 < 4) {
+        if (sscanf(pin, "%d,%d,%d", &r, &a0, &a1) == 3 && r >= 0 && r < 16 && a0 >= 0 && a0 < 12 && a1 >= 0 && a1 < 4) {
             tune.row = r;
             tune.ax0 = (lean && a0 < 4) ? 4 : a0;   // a lean plan steps with the register kernel
             tune.ax1 = a1;
@@ -584,7 +584,7 @@ setd_status Plan::autotune()
             tune.split = (sp && sp[0] == '2') ? 2 : 1;
             return SETD_OK;
         }
-        return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row in 0..15, axis0 in 0..5, axis1 in 0..3");
+        return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row in 0..15, axis0 in 0..11, axis1 in 0..3");
     }
     const char* env = std::getenv("SETD_AUTOTUNE");
     if ((env && env[0] == '0') || no_alloc) return SETD_OK;
@@ -608,10 +608,12 @@ setd_status Plan::autotune()
     const int ax0_pass = (d.ndim == 2) ? 1 : 3;
     struct Knob { int* var; int first; int nvar; int pass; int pass2; };
     // row variants 4..15 (several pair groups per workgroup) exist for real
-    // fields; axis-0 variants 4 and 5 (register update) for dealiased plans,
-    // and are the only ones a plan keeping the SETD2 carry can step with
+    // fields; axis-0 variants 4 and up (register update) for dealiased plans,
+    // and are the only ones a plan keeping the SETD2 carry can step with;
+    // the item groups of variants 6..11 need 2, 4 or 8 items
+    const int ax0_top = !g.dealias ? 4 : (R >= 8 ? 12 : (R >= 4 ? 10 : (R >= 2 ? 8 : 6)));
     Knob knobs[3] = {{&tune.row, 0, d.complex_field ? 4 : 16, row_pass, -1},
-                     {&tune.ax0, lean ? 4 : 0, g.dealias ? 6 : 4, ax0_pass, -1},
+                     {&tune.ax0, lean ? 4 : 0, ax0_top, ax0_pass, -1},
                      {&tune.ax1, 0, 4, 0, 2}};
     const int nknobs = (d.ndim == 3) ? 3 : 2;
     setd_status st = SETD_OK;

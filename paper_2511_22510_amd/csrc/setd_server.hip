@@ -31,6 +31,7 @@
 #include <thread>
 #include <vector>
 
+#include "setd_launch.hpp"
 #include "setd_runtime.hpp"
 
 namespace setd {
@@ -147,6 +148,11 @@ struct setd_server {
     size_t kept_bytes = 0;
     std::deque<setd_job> kept_order;
     double est_step_s = 0.0;              // measured wall time of one batched step
+    // 2D real-field classes of different lattice sizes share one launch per
+    // pass (SETD_SERVER_MULTI=0 keeps a launch per class)
+    bool multi = true;
+    // counters: ticks that ran steps, pass launches queued, shared ones among them
+    double n_ticks = 0, n_launches = 0, n_shared = 0;
 
     void run();
     void admit_locked(std::vector<Job*>& admitted);
@@ -281,18 +287,53 @@ setd_status setd_server::tick(std::vector<Job*>& act, int* steps_taken)
     }
     Item* items_dev = reinterpret_cast<Item*>(arena + items_off);
     SETD_HIP(hipMemcpyAsync(items_dev, items_host, nitems * sizeof(Item), hipMemcpyHostToDevice, stream));
+    // launch units: the classes that can share launches (one per lattice
+    // size, multi2d_ok) form one unit when there are two or more of them;
+    // every other class is a unit of its own (-1 marks the shared unit)
+    MultiClass mc[4] = {};
+    int nshare = 0;
+    if (multi)
+        for (const Launch& L : launches)
+            if (multi2d_ok(L.rep->g, L.rep->lean, L.rep->d.nl)) nshare++;
+    std::vector<int> units;
+    if (nshare >= 2) units.push_back(-1);
+    for (size_t c = 0; c < launches.size(); c++) {
+        const Launch& L = launches[c];
+        if (nshare >= 2 && multi2d_ok(L.rep->g, L.rep->lean, L.rep->d.nl))
+            mc[multi2d_slot(L.rep->g.n[0])] = MultiClass{L.rep->g, items_dev + L.first, L.n};
+        else
+            units.push_back((int)c);
+    }
     const double t0 = now_s();
-    const int nl = std::min<int>(nlanes, (int)launches.size());
+    const int nl = std::min<int>(nlanes, (int)units.size());
     if (nl >= 2) {
         SETD_HIP(hipEventRecord(ev_fork, stream));
         for (int i = 0; i < nl; i++) SETD_HIP(hipStreamWaitEvent(lanes[i], ev_fork, 0));
     }
     setd_status lst = SETD_OK;
+    double q_launches = 0, q_shared = 0;
     for (int sub = 0; sub < maxk && lst == SETD_OK; sub++) {
-        for (size_t c = 0; c < launches.size() && lst == SETD_OK; c++) {
-            const Launch& L = launches[c];
-            lst = L.rep->launch_step(items_dev + L.first, L.n, sub, nl >= 2 ? lanes[c % nl] : stream);
+        for (size_t u = 0; u < units.size() && lst == SETD_OK; u++) {
+            const hipStream_t ls = nl >= 2 ? lanes[u % nl] : stream;
+            if (units[u] < 0) {
+                for (int pass = 0; pass < 2 && lst == SETD_OK; pass++) {
+                    const hipError_t e = launch_multi2d<float>(mc, pass, sub, ls);
+                    if (e != hipSuccess) lst = fail(SETD_E_DEVICE, "shared launch failed: %s", hipGetErrorString(e));
+                }
+                q_launches += 2;
+                q_shared += 2;
+            } else {
+                const Launch& L = launches[units[u]];
+                lst = L.rep->launch_step(items_dev + L.first, L.n, sub, ls);
+                q_launches += L.rep->passes_per_step();
+            }
         }
+    }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        n_launches += q_launches;
+        n_shared += q_shared;
+        if (maxk > 0) n_ticks += 1;
     }
     if (nl >= 2) {
         // join even after a failed launch
@@ -383,6 +424,7 @@ setd_status setd_server_create(void* dev_arena, size_t bytes, void* hip_stream, 
     s->aging_s = env_double("SETD_SERVER_AGING", 1.0);
     s->tick_target_s = env_double("SETD_SERVER_TICK", 0.005);
     s->keep_budget = (size_t)env_double("SETD_SERVER_KEEP_BYTES", (double)((size_t)2 << 30));
+    s->multi = env_double("SETD_SERVER_MULTI", 1) != 0;
     // SETD_SERVER_LANES (0..4, default 4) streams for the launch classes of a tick
     const int want = std::max(0, std::min(setd_server::NLANE, (int)env_double("SETD_SERVER_LANES", 4)));
     if (want >= 2 && hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess) {
@@ -498,6 +540,18 @@ setd_status setd_job_times(setd_server* s, setd_job job, double* out4)
     out4[1] = j->t_admit;
     out4[2] = j->t_done;
     out4[3] = (double)j->done_steps;
+    return SETD_OK;
+}
+
+setd_status setd_server_stats(setd_server* s, double* out, size_t cap, size_t* len)
+{
+    if (!s || !out || !len) return fail(SETD_E_INVAL, "null argument");
+    if (cap < 3) return fail(SETD_E_INVAL, "output needs 3 doubles");
+    std::lock_guard<std::mutex> lk(s->mu);
+    out[0] = s->n_ticks;
+    out[1] = s->n_launches;
+    out[2] = s->n_shared;
+    *len = 3;
     return SETD_OK;
 }
 

@@ -101,6 +101,7 @@ SIGNATURES = {
     "setd_job_observe": (ctypes.c_int, [_P, _I64, ctypes.c_int, _D, _SZ, ctypes.POINTER(_SZ)]),
     "setd_job_get_field": (ctypes.c_int, [_P, _I64, ctypes.c_int, _D, _SZ]),
     "setd_job_times": (ctypes.c_int, [_P, _I64, _D]),
+    "setd_server_stats": (ctypes.c_int, [_P, _D, _SZ, ctypes.POINTER(_SZ)]),
     "setd_server_destroy": (ctypes.c_int, [_P]),
     "setd_sde_run": (ctypes.c_int, [ctypes.POINTER(setd_sde_desc), _P, _P, _P]),
     "setd_run_noalloc": (ctypes.c_int, [ctypes.POINTER(setd_desc), _I64, _P, _SZ, _P]),
@@ -318,6 +319,14 @@ def setd_job_times(server, job, lib=None):
     return out
 
 
+def setd_server_stats(server, lib=None):
+    lib = lib or load()
+    out = np.zeros(3, dtype=np.float64)
+    ln = _SZ()
+    _check(lib, lib.setd_server_stats(server, out.ctypes.data_as(_D), out.size, ctypes.byref(ln)))
+    return out[: ln.value].copy()
+
+
 def setd_server_destroy(server, lib=None):
     lib = lib or load()
     lib.setd_server_destroy(server)
@@ -384,6 +393,10 @@ class Server:
     def get(self, jid, r=0):
         shp, n = self._shape[jid]
         return setd_job_get_field(self.h, jid, r, n, self.lib).reshape(shp)
+
+    def stats(self):
+        """[ticks, pass launches, shared launches] (setd_server_stats)."""
+        return setd_server_stats(self.h, self.lib)
 
     def close(self):
         if getattr(self, "h", None):

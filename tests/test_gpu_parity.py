@@ -564,18 +564,21 @@ VARIANT_CASES = [
     W.cgl([16, 32, 32], precision=64, realizations=1),
     W.model_a([8, 16], precision=32, order=2, realizations=3),
     W.kpz([128, 64], precision=32, realizations=2, ic_kind=1, ic_sigma=0.2),
+    # five items: groups of 2, 4 and 8 end in a partial group
+    W.model_b([64, 64], precision=32, realizations=5),
 ]
 
 
 @pytest.mark.parametrize("variant", ["0,0,0", "1,1,1", "2,2,2", "3,3,3", "1,2,3", "3,0,1", "0,4,0", "2,5,3",
-                                     "5,4,0", "14,1,1", "11,5,2", "15,0,3"])
+                                     "5,4,0", "14,1,1", "11,5,2", "15,0,3", "1,6,1", "0,9,2", "3,11,0"])
 @pytest.mark.parametrize("history", [0, 1])
 def test_every_kernel_variant_matches_oracle(variant, history, monkeypatch):
     """Each autotuner choice (row: LDS padding x block size x row-pair groups
     per workgroup; axis passes: tile width x columns per thread; axis-0
-    variants 4 and 5: the register-update kernel at two tile widths) gives
-    the same trajectory, with either SETD2 storage (the carry-only storage
-    always steps with variants 4 or 5)."""
+    variants 4 and up: the register-update kernel at two tile widths, items
+    interleaved per tile in groups of 1, 2, 4 or 8) gives the same
+    trajectory, with either SETD2 storage (the carry-only storage always
+    steps with the register kernel)."""
     monkeypatch.setenv("SETD_VARIANT", variant)
     for p in VARIANT_CASES:
         p = dict(p, history_readback=history)
@@ -624,4 +627,25 @@ def test_full_configurations_run_to_completion():
     a2 = float(np.sum(np.abs(spec) ** 2)) / n3 ** 2
     say("CGL 256^3 mean |A|^2 after 2e4 steps", a2)
     assert 0.3 < a2 < 1.2
+    g.close()
+
+
+@pytest.mark.parametrize("variant", ["1,4,1", "1,6,1", "1,9,1", "1,11,1"])
+def test_item_groups_are_bitwise_the_same(variant, monkeypatch):
+    """The item interleaving of the register axis-0 kernel changes only which
+    block runs when: every realization's trajectory is bitwise that of the
+    item-after-item order (variant 4 / 5 at the same tile width)."""
+    S = _setd()
+    p = W.model_b([128, 128], precision=32, realizations=7)
+    base = "1,%d,1" % (4 + (int(variant.split(",")[1]) - 4) % 2)
+    monkeypatch.setenv("SETD_VARIANT", base)
+    ref = S.Plan(p)
+    monkeypatch.setenv("SETD_VARIANT", variant)
+    g = S.Plan(p)
+    for _ in range(3):
+        ref.step(5)
+        g.step(5)
+        for r in range(p["realizations"]):
+            assert np.array_equal(ref.get(r), g.get(r))
+    ref.close()
     g.close()

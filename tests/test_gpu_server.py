@@ -187,3 +187,46 @@ def test_admission_keeps_item_entries_within_the_table(monkeypatch):
             assert np.array_equal(srv.get(jid, r), solo.get(r)), (jid, r)
         solo.close()
     srv.close()
+
+
+SHARED = [
+    (W.model_a([64, 64], precision=32, order=2, realizations=3, seed=301), 37),
+    (W.model_a([128, 128], precision=32, order=2, realizations=2, seed=302), 41),
+    (W.model_b([256, 256], precision=32, realizations=4, seed=303), 29),
+    (W.model_a([512, 512], precision=32, order=2, realizations=1, seed=304), 33),
+    # the same class as the 128^2 Model A job: both fill one slot
+    (W.model_b([128, 128], precision=32, realizations=1, seed=305), 45),
+    # classes that keep launches of their own
+    (W.kpz([128, 128], precision=32, realizations=2, seed=306), 23),
+    (W.cgl([32, 32, 32], precision=32, realizations=1, seed=307), 19),
+]
+
+
+@pytest.mark.parametrize("multi", ["1", "0"])
+def test_uneven_lattices_share_launches(multi, monkeypatch):
+    """2D real-field jobs on 64^2 to 512^2 lattices advance in one launch per
+    pass per tick (each lattice size a slot of the shared kernels); every job
+    equals its solo run bitwise and the oracle within the bar.  With
+    SETD_SERVER_MULTI=0 the same jobs run one launch per class."""
+    monkeypatch.setenv("SETD_SERVER_MULTI", multi)
+    S = _setd()
+    srv = S.Server(512 << 20)
+    ids = [srv.submit(p, n) for p, n in SHARED]
+    srv.drain()
+    ticks, launches, shared = srv.stats()
+    say("multi", multi, "ticks", ticks, "pass launches", launches, "shared", shared)
+    assert ticks > 0 and launches > 0
+    assert (shared > 0) if multi == "1" else (shared == 0)
+    for jid, (p, n) in zip(ids, SHARED):
+        assert srv.poll(jid) == (True, S.SETD_OK)
+        solo = S.Plan(p)
+        solo.step(n)
+        for r in range(p["realizations"]):
+            assert np.array_equal(srv.get(jid, r), solo.get(r)), (jid, r)
+        solo.close()
+        o = O.Sim(p, r_first=0, r_count=1)
+        o.step(n)
+        err = relerr(srv.get(jid, 0), o.get(0))
+        say("job", jid, p["nl"], p["n"], "oracle err", err)
+        assert err <= 2e-4
+    srv.close()
