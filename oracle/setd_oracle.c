@@ -72,7 +72,7 @@ typedef struct {
     int order;             /* 1 SETD1, 2 SETD2                              */
     int realizations;
     uint64_t seed;
-    int dealias;           /* 0 none, 1 the 2/3 rule, 2 phase shift (1D)    */
+    int dealias;           /* 0 none, 1 the 2/3 rule, 2 phase shift         */
     int ic_kind;           /* 0 zero, 1 Gaussian per site                   */
     double ic_sigma;
     int noise_space;       /* 0 Fourier-space draws (App. B), 1 real space  */
@@ -419,7 +419,7 @@ orc_sim* orc_create_subset(const orc_desc* d, int r_first, int r_count)
     if (d->ndim < 1 || d->ndim > 3) return NULL;
     for (int i = 0; i < d->ndim; i++) if (!is_pow2(d->n[i]) || d->n[i] < 4) return NULL;
     if (d->order != 1 && d->order != 2) return NULL;
-    if (d->dealias < 0 || d->dealias > 2 || (d->dealias == 2 && d->ndim != 1)) return NULL;
+    if (d->dealias < 0 || d->dealias > 2) return NULL;
     if (!(d->h > 0) || !(d->dx > 0)) return NULL;
     if (d->realizations < 1 || r_first < 0 || r_count < 1 || r_first + r_count > d->realizations) return NULL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
@@ -556,13 +556,15 @@ int orc_threads(void) { return omp_get_max_threads(); }
 /* ------------------------------------------------------------------------ */
 static void nonlinear_raw(orc_sim* s, const cplx* ph, cplx* F);
 
-/* Phase-shift dealiasing on a line (Sec. 4; the paper names the method, the
-   rule here is this implementation's reading): the nonlinearity is also
-   evaluated on the grid shifted by dx/2, i.e. from e^{i k dx/2} phi_a, and
-   transformed back with e^{-i k dx/2}; the mean of the two transforms has the
-   single aliases a +- N with opposite signs, so they cancel.  With the
-   Nyquist mode dropped, the quadratic and cubic products of modes |a| < N/2
-   alias at most once, so F is alias-free. */
+/* Phase-shift dealiasing (Sec. 4; the paper names the method, the rule here
+   is this implementation's reading): the nonlinearity is evaluated on the grid
+   and on the grids moved by dx/2 along every nonempty set of axes, i.e. from
+   e^{i k.s} phi_a with s_i in {0, dx/2}, and each transform is moved back with
+   e^{-i k.s}.  In the mean of the 2^d transforms an alias a + m N (m_i in
+   {-1, 0, 1} per axis) carries the factor prod_i (1 + (-1)^{m_i}) / 2, which
+   vanishes unless m = 0.  With the Nyquist modes dropped, the quadratic and
+   cubic products of modes |a_i| < N_i/2 alias at most once per axis, so F is
+   alias-free.  On a line: the grid and the grid moved by dx/2. */
 static void nonlinear_term(orc_sim* s, const cplx* ph, cplx* F)
 {
     const orc_desc* d = &s->d;
@@ -570,11 +572,25 @@ static void nonlinear_term(orc_sim* s, const cplx* ph, cplx* F)
     if (d->nl == NL_NONE) { for (size_t e = 0; e < ns; e++) F[e] = 0; return; }
     nonlinear_raw(s, ph, F);
     if (d->dealias == 2) {
+        const int nsh = 1 << d->ndim;
         cplx* shifted = (cplx*)malloc(sizeof(cplx) * ns);
         cplx* Fs = (cplx*)malloc(sizeof(cplx) * ns);
-        for (size_t e = 0; e < ns; e++) shifted[e] = cexp(I * M_PI * s->kidx[3 * e] / d->n[0]) * ph[e];
-        nonlinear_raw(s, shifted, Fs);
-        for (size_t e = 0; e < ns; e++) F[e] = 0.5 * (F[e] + cexp(-I * M_PI * s->kidx[3 * e] / d->n[0]) * Fs[e]);
+        for (int m = 1; m < nsh; m++) {   /* m = 0 is the unshifted grid, F already */
+            for (size_t e = 0; e < ns; e++) {
+                double th = 0.0;
+                for (int i = 0; i < d->ndim; i++)
+                    if ((m >> i) & 1) th += M_PI * s->kidx[3 * e + i] / d->n[i];
+                shifted[e] = cexp(I * th) * ph[e];
+            }
+            nonlinear_raw(s, shifted, Fs);
+            for (size_t e = 0; e < ns; e++) {
+                double th = 0.0;
+                for (int i = 0; i < d->ndim; i++)
+                    if ((m >> i) & 1) th += M_PI * s->kidx[3 * e + i] / d->n[i];
+                F[e] += cexp(-I * th) * Fs[e];
+            }
+        }
+        for (size_t e = 0; e < ns; e++) F[e] = F[e] / (double)nsh;
         free(shifted);
         free(Fs);
     }
