@@ -153,11 +153,17 @@ typedef struct {
                                  evaluated in FP64 and rounded; 64: complex128     */
     int realizations;         /* independent noise realizations in one plan (>= 1) */
     uint64_t seed;            /* Philox4x32-10 key                                 */
-    int dealias;              /* 0: none; 1: 2/3 rule, keep 3|a_i| < n[i]; 2 (1D
-                                 lines, Fourier-space noise): phase shift, the
-                                 nonlinearity averaged over the grid and the grid
-                                 moved by dx/2, keeping 2|a| < n (alias-free for
-                                 the quadratic and cubic terms)                */
+    int dealias;              /* 0: none; 1: 2/3 rule, keep 3|a_i| < n[i]; 2
+                                 (Fourier-space noise): phase shift, the
+                                 nonlinearity averaged over the grid and the
+                                 2^d - 1 grids moved by dx/2 along each
+                                 nonempty set of axes, keeping 2|a_i| < n[i]
+                                 (alias-free for the quadratic and cubic terms).
+                                 2D/3D plans with dealias 2 keep phi and
+                                 F_{n-1} (no carry) and take 2^(d-1) times the
+                                 transforms of a 2/3 step (3D: four copies of
+                                 the n0 n1 (n2/2+1) line buffer); not with KPZ
+                                 on 2D/3D lattices                           */
     int ic_kind;              /* 0: phi = 0; 1: i.i.d. N(0, ic_sigma^2) per site
                                  (complex fields: ic_sigma (z1 + i z2))             */
     double ic_sigma;

@@ -46,6 +46,16 @@ __device__ __forceinline__ int ceil_isqrt(int m)
     return s * s == m ? s : s + 1;
 }
 
+// e^{i pi x}
+template <typename T>
+__device__ __forceinline__ cx<T> cispi(T x)
+{
+    T s, c;
+    if constexpr (sizeof(T) == 4) sincospif(x, &s, &c);
+    else sincospi(x, &s, &c);
+    return {c, s};
+}
+
 // ---------------------------------------------------------------- coefficients
 template <typename T>
 struct Coef {
@@ -276,7 +286,12 @@ __device__ __forceinline__ unsigned xcd_logical(unsigned L, unsigned G)
 // row (the resource covers the block's rows that exist); a lane whose bin has
 // no stored mode uses BUF_OOB, reads zero and writes nothing, so the loads are
 // unconditional and all in flight together.
-// KIND: 0 = phi^3 (Model A/B) step, 1 = KPZ step, 2 = initial condition.
+// KIND: 0 = phi^3 (Model A/B) step, 1 = KPZ step, 2 = initial condition,
+// 3 = phi^3 step with phase shifts (dealias 2): the packed line and its copy
+// moved by dx/2 along the row (e^{i pi a/N} per bin) go through the stages
+// together and their transforms are averaged, the second moved back; 2D: rows
+// of pre (sel 0) or of its axis-0-shifted copy preb (sel 1); 3D: rows of grid
+// sel of the four grids in big.
 // DA: the 2/3 rule is on; then bins q = 0, 1 (k < N/4) always hold a stored
 // mode, q = 6, 7 (k >= 3N/4) always its mirror, q = 3, 4 never any, and only
 // q = 0..2 are written back, all decided at compile time.
@@ -284,7 +299,8 @@ __device__ __forceinline__ unsigned xcd_logical(unsigned L, unsigned G)
 // below passes its own, the shared launch of several lattice classes its
 // position within the class.
 template <typename T, int N, int PAD, int KIND, bool DA, bool PF>
-__device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, const int by, const int tid)
+__device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, const int by, const int tid,
+                                              const int sel = 0)
 {
     const Item it = a.items[by];
     if (a.sub >= it.steps) return;
@@ -293,8 +309,8 @@ __device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, co
     constexpr int TPL = N / 8;
     constexpr uint32_t ES = sizeof(cx<T>);
     const int l = tid / TPL, t = tid - l * TPL;
-    // KPZ steps hold two lines per row pair in LDS
-    cx<T>* L = lds + l * (KIND == 1 ? 2 : 1) * lds_len<N, PAD>();
+    // KPZ and phase-shift steps hold two lines per row pair in LDS
+    cx<T>* L = lds + l * ((KIND == 1 || KIND == 3) ? 2 : 1) * lds_len<N, PAD>();
     const Geo& g = a.g;
     const int last = g.ndim - 1;
     LineTw<T, N> tw;
@@ -314,7 +330,10 @@ __device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, co
     const int row0 = 2 * grp0 * a.lpw;
     const int nrow = min(2 * a.lpw * niter, a.nrows - row0);
     const size_t boff = (size_t)row0 * pitch;
-    cx<T>* const bufp = reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big) + boff;
+    cx<T>* const bufp =
+        (g.ndim == 2 ? reinterpret_cast<cx<T>*>((KIND == 3 && sel) ? it.preb : it.pre0)
+                     : reinterpret_cast<cx<T>*>(it.big) + (KIND == 3 ? (size_t)sel * g.n[0] * g.n[1] * pitch : 0)) +
+        boff;
     const rsrc_t rb = make_rsrc(bufp, (uint32_t)nrow * (uint32_t)pitch * ES);
     const uint32_t RS = (uint32_t)pitch * ES;   // bytes per row
     // the pair of lane group l in group i, whether it exists, and the byte
@@ -447,16 +466,41 @@ __device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, co
                 v[q] = z;
             }
             if (PF && i + 1 < niter) load_rows(i + 1);
-            fft_line<T, N, +1, PAD>(v, t, L, 1, twp);
-            // phi^3 in real space (Model A and B)
+            if constexpr (KIND == 3) {
+                // phi^3 on the rows and on the rows moved by dx/2, through the
+                // stages together; the mean of the transforms, the second
+                // moved back, cancels the aliases along the row
+                cx<T> w[2][8], phs[8];
 #pragma unroll
-            for (int q = 0; q < 8; q++) {
-                const T x = v[q].x * inv, y = v[q].y * inv;
-                v[q] = {x * x * x, y * y * y};
+                for (int q = 0; q < 8; q++) {
+                    phs[q] = cispi<T>((T)sgn_idx(t + q * TPL, N) / (T)N);
+                    w[0][q] = v[q];
+                    w[1][q] = cmul(phs[q], v[q]);
+                }
+                fft_lines<T, N, +1, PAD, 2>(w, t, L, 2, 1, twp);
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        const T x = w[u][q].x * inv, y = w[u][q].y * inv;
+                        w[u][q] = {x * x * x, y * y * y};
+                    }
+                }
+                fft_lines<T, N, -1, PAD, 2>(w, t, L, 2, 1, twp);
+#pragma unroll
+                for (int q = 0; q < 8; q++) v[q] = T(0.5) * (w[0][q] + cmulc(w[1][q], phs[q]));
+            } else {
+                fft_line<T, N, +1, PAD>(v, t, L, 1, twp);
+                // phi^3 in real space (Model A and B)
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const T x = v[q].x * inv, y = v[q].y * inv;
+                    v[q] = {x * x * x, y * y * y};
+                }
             }
         }
 
-        fft_line<T, N, -1, PAD>(v, t, L, 1, twp);
+        if constexpr (KIND != 3) fft_line<T, N, -1, PAD>(v, t, L, 1, twp);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 8; q++) {
@@ -481,11 +525,15 @@ __device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, co
 template <typename T, int N, int PAD, int KIND, bool DA, bool PF>
 __global__ void __launch_bounds__(256) k_row_real(RowArgs a)
 {
-    row_real_body<T, N, PAD, KIND, DA, PF>(a, blockIdx.x, blockIdx.y, threadIdx.x);
+    row_real_body<T, N, PAD, KIND, DA, PF>(a, blockIdx.x, blockIdx.y, threadIdx.x, blockIdx.z);
 }
 
 // ---------------------------------------------------------------- row pass, complex field
-template <typename T, int N, int PAD, bool IC>
+// PS (dealias 2): the line and its copy moved by dx/2 (e^{i pi a/N} per bin)
+// through the stages together, their transforms averaged with the second
+// moved back; 2D: rows of pre (blockIdx.z 0) or of its axis-0-shifted copy
+// preb (1); 3D: rows of grid blockIdx.z of the four grids in big.
+template <typename T, int N, int PAD, bool IC, bool PS = false>
 __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
 {
     const Item it = a.items[blockIdx.y];
@@ -497,7 +545,7 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
     const int l = tid / TPL, t = tid - l * TPL;
     const int line = blockIdx.x * a.lpw + l;
     const bool valid = line < a.nrows;
-    cx<T>* L = lds + l * lds_len<N, PAD>();
+    cx<T>* L = lds + l * (PS ? 2 : 1) * lds_len<N, PAD>();
     const Geo& g = a.g;
     const int last = g.ndim - 1;
     LineTw<T, N> tw;
@@ -508,7 +556,11 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
     // this lane's line, BUF_OOB for bins without a stored mode
     const int line0 = blockIdx.x * a.lpw;
     const int nline = min(a.lpw, a.nrows - line0);
-    const rsrc_t rb = make_rsrc(reinterpret_cast<cx<T>*>(g.ndim == 2 ? it.pre0 : it.big) + (size_t)line0 * g.pitch,
+    // phase shifts: 2D rows of pre or preb, 3D rows of grid blockIdx.z of big
+    cx<T>* const buf = g.ndim == 2 ? reinterpret_cast<cx<T>*>((PS && blockIdx.z) ? it.preb : it.pre0)
+                                   : reinterpret_cast<cx<T>*>(it.big) +
+                                         (PS ? (size_t)blockIdx.z * g.n[0] * g.n[1] * g.pitch : 0);
+    const rsrc_t rb = make_rsrc(buf + (size_t)line0 * g.pitch,
                                 (uint32_t)nline * (uint32_t)g.pitch * ES);
     const uint32_t lo = (uint32_t)l * (uint32_t)g.pitch * ES;
     auto col_off = [&](int q) -> uint32_t {
@@ -532,16 +584,39 @@ __global__ void __launch_bounds__(256) k_row_cplx(RowArgs a)
     } else {
 #pragma unroll
         for (int q = 0; q < 8; q++) v[q] = bload<T>(rb, col_off(q), 0);
-        fft_line<T, N, +1, PAD>(v, t, L, 1, tw);
-        // |A|^2 A in real space (CGL)
+        if constexpr (PS) {
+            cx<T> w[2][8], phs[8];
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const T x = v[q].x * inv, y = v[q].y * inv;
-            const T m = x * x + y * y;
-            v[q] = {m * x, m * y};
+            for (int q = 0; q < 8; q++) {
+                phs[q] = cispi<T>((T)sgn_idx(t + q * TPL, N) / (T)N);
+                w[0][q] = v[q];
+                w[1][q] = cmul(phs[q], v[q]);
+            }
+            fft_lines<T, N, +1, PAD, 2>(w, t, L, 2, 1, tw);
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const T x = w[u][q].x * inv, y = w[u][q].y * inv;
+                    const T m = x * x + y * y;
+                    w[u][q] = {m * x, m * y};
+                }
+            }
+            fft_lines<T, N, -1, PAD, 2>(w, t, L, 2, 1, tw);
+#pragma unroll
+            for (int q = 0; q < 8; q++) v[q] = T(0.5) * (w[0][q] + cmulc(w[1][q], phs[q]));
+        } else {
+            fft_line<T, N, +1, PAD>(v, t, L, 1, tw);
+            // |A|^2 A in real space (CGL)
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const T x = v[q].x * inv, y = v[q].y * inv;
+                const T m = x * x + y * y;
+                v[q] = {m * x, m * y};
+            }
         }
     }
-    fft_line<T, N, -1, PAD>(v, t, L, 1, tw);
+    if (!PS || IC) fft_line<T, N, -1, PAD>(v, t, L, 1, tw);
 #pragma unroll
     for (int q = 0; q < 8; q++) bstore<T>(rb, col_off(q), 0, v[q]);
 }
@@ -667,7 +742,14 @@ __global__ void __launch_bounds__(256) k_rsn_rows(RsnArgs a)
 // MODE_RECOVER: pre -> forward FFT / N0 -> phi, pre left as it is (the state
 //            of a plan that keeps the SETD2 carry instead of phi; pre holds
 //            the unscaled axis-0 inverse of phi, N0 a power of two).
-template <typename T, int N0, int TILE, int PAD, bool KPZ, int LPT>
+// PS (phase-shift dealiasing, 2D and 3D): beside pre the pass keeps preb,
+// the axis-0 inverse of e^{i pi a0/N0} phi.  A step transforms both forward
+// (the passes before have already averaged each over the grids moved along
+// the other axes), takes X = (X_pre + e^{-i pi a0/N0} X_preb) / 2 as the
+// nonlinear term (the mean over the 2^d grids), and after the update transforms phi and
+// e^{i pi a0/N0} phi back into pre and preb; the second half of the LDS holds
+// the shifted lines.
+template <typename T, int N0, int TILE, int PAD, bool KPZ, int LPT, bool PS>
 __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
 {
     const unsigned lg = xcd_logical(blockIdx.x, gridDim.x);
@@ -701,10 +783,16 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
     cx<T>* __restrict__ phi = reinterpret_cast<cx<T>*>(rsn_mode ? it.noise : it.phi);
     cx<T>* __restrict__ prev = reinterpret_cast<cx<T>*>(it.prev);
     const cx<T>* __restrict__ rnoise = reinterpret_cast<const cx<T>*>(it.noise);
+    cx<T>* __restrict__ preb = reinterpret_cast<cx<T>*>(it.preb);
+    // the shifted lines' LDS: the second half
+    cx<T>* const ldsb = lds + (PS ? TILE * lds_len<N0, PAD>() : 0);
     LineTw<T, N0> tw;
     line_tw_load(tw, t, twid<T>(it.tw0));
     cx<T>* L = lds + c0;   // line k at L + k * CW, element stride TILE
+    cx<T>* LB = ldsb + c0;
     const int kept0 = g.kept[0], kp0 = g.kp[0];
+    // e^{i pi a0/N0} of axis-0 position j (signed a0)
+    auto shift0 = [&](int j) { return cispi<T>((T)sgn_idx(j, N0) / (T)N0); };
 
     int j1 = 0, a1 = 0;
     if (g.ndim == 3) {
@@ -714,6 +802,7 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
     const T dk0 = (T)it.dk[0], dk1 = (T)it.dk[1], dk2 = (T)it.dk[2];
 
     cx<T> v[LPT][8];
+    cx<T> vb[PS ? LPT : 1][8];
     int64_t nstep = 0;
     int hp = 0;
     if (a.mode == MODE_STEP) {
@@ -727,6 +816,7 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
             for (int q = 0; q < 8; q++) {
                 const int i0 = stored_idx(t + q * TPL, N0, kept0, kp0);
                 v[k][q] = (cv[k] && i0 >= 0) ? phi[(size_t)i0 * lstride + plane + col[k]] : czero<T>();
+                if constexpr (PS) vb[k][q] = cmul(shift0(t + q * TPL), v[k][q]);
             }
         }
     } else {
@@ -737,6 +827,22 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
                 v[k][q] = cv[k] ? pre0[(size_t)(t + q * TPL) * lstride + plane + col[k]] : czero<T>();
         }
         fft_lines<T, N0, -1, PAD, LPT>(v, t, L, TILE, CW, tw);
+        if constexpr (PS) {
+            // the shifted copy (a step only: the initial condition has none)
+#pragma unroll
+            for (int k = 0; k < LPT; k++) {
+#pragma unroll
+                for (int q = 0; q < 8; q++)
+                    vb[k][q] = (cv[k] && a.mode == MODE_STEP) ? preb[(size_t)(t + q * TPL) * lstride + plane + col[k]]
+                                                              : czero<T>();
+            }
+            fft_lines<T, N0, -1, PAD, LPT>(vb, t, LB, TILE, CW, tw);
+#pragma unroll
+            for (int k = 0; k < LPT; k++) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) LB[k * CW + lds_slot<PAD>(t + q * TPL) * TILE] = vb[k][q];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < LPT; k++) {
 #pragma unroll
@@ -794,6 +900,13 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
             const int colm = tile * TILE + cc;
             const int j0 = fft_pos(i0, N0, kept0, kp0);
             cx<T>* slot = lds + lds_slot<PAD>(j0) * TILE + cc;
+            cx<T>* slotb = ldsb + lds_slot<PAD>(j0) * TILE + cc;
+            // phase shifts: the mean over the four grids, and e^{i pi a0/N0}
+            cx<T> sh = {T(1), T(0)};
+            if constexpr (PS) {
+                sh = shift0(j0);
+                if (a.mode == MODE_STEP) *slot = T(0.5) * (*slot + cmulc(*slotb, sh));
+            }
             if (colm < keptl) {
                 const size_t si = (size_t)i0 * lstride + plane + cc;
                 if (a.mode == MODE_IC || rsn_mode) {
@@ -820,8 +933,10 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
                     phi[si] = nw;
                     *slot = nw;
                 }
+                if constexpr (PS) *slotb = cmul(sh, *slot);
             } else {
                 *slot = czero<T>();
+                if constexpr (PS) *slotb = czero<T>();
             }
             cur = nxt;
         }
@@ -829,6 +944,7 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
         for (int m = tid; m < (N0 - kept0) * TILE; m += NTHR) {
             const int row = kp0 + 1 + m / TILE;
             lds[lds_slot<PAD>(row) * TILE + (m % TILE)] = czero<T>();
+            if constexpr (PS) ldsb[lds_slot<PAD>(row) * TILE + (m % TILE)] = czero<T>();
         }
         // one flag update per block
         if (__syncthreads_or(bad) && tid == 0) atomicOr(&it.ctrl->nonfinite, 1);
@@ -837,7 +953,10 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
 #pragma unroll
         for (int k = 0; k < LPT; k++) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) v[k][q] = L[k * CW + lds_slot<PAD>(t + q * TPL) * TILE];
+            for (int q = 0; q < 8; q++) {
+                v[k][q] = L[k * CW + lds_slot<PAD>(t + q * TPL) * TILE];
+                if constexpr (PS) vb[k][q] = LB[k * CW + lds_slot<PAD>(t + q * TPL) * TILE];
+            }
         }
     }
     cx<T> v2[KPZ ? LPT : 1][8];
@@ -858,6 +977,16 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
         if (cv[k]) {
 #pragma unroll
             for (int q = 0; q < 8; q++) pre0[(size_t)(t + q * TPL) * lstride + plane + col[k]] = v[k][q];
+        }
+    }
+    if constexpr (PS) {
+        fft_lines<T, N0, +1, PAD, LPT>(vb, t, LB, TILE, CW, tw);
+#pragma unroll
+        for (int k = 0; k < LPT; k++) {
+            if (cv[k]) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) preb[(size_t)(t + q * TPL) * lstride + plane + col[k]] = vb[k][q];
+            }
         }
     }
     if constexpr (KPZ) {
@@ -1390,7 +1519,13 @@ k_axis0_multi(MultiAxArgs m)
 // ---------------------------------------------------------------- axis-1 pass (3D)
 // mode +1: stored axis-1 entries of pre -> inverse FFT -> big
 // mode -1: big -> forward FFT -> stored axis-1 entries of pre
-template <typename T, int N1, int TILE, int PAD, int LPT>
+// PS (phase-shift dealiasing, 3D): big holds four grids, 2 s0 + s1, s0 = 1 for
+// the grid moved by dx/2 along axis 0 (the source preb instead of pre), s1 = 1
+// for the grid moved along axis 1 (e^{i pi a1/N1} per mode).  blockIdx.z picks
+// s0; mode +1 writes both grids of that source, mode -1 transforms both
+// forward and keeps their mean, the second moved back, in pre or preb.  One
+// column per thread; the two lines sit side by side in LDS (stride 2 TILE).
+template <typename T, int N1, int TILE, int PAD, int LPT, bool PS = false>
 __global__ void __launch_bounds__(TILE / LPT * N1 / 8) k_axis1(AxisArgs a)
 {
     const unsigned lg = xcd_logical(blockIdx.x, gridDim.x);
@@ -1414,10 +1549,50 @@ __global__ void __launch_bounds__(TILE / LPT * N1 / 8) k_axis1(AxisArgs a)
         col[k] = tile * TILE + c0 + k * CW;
         cv[k] = col[k] < g.kept[2];
     }
-    cx<T>* __restrict__ small = reinterpret_cast<cx<T>*>(a.alt ? it.npre : it.pre0) + (size_t)n0 * kept1 * pitch;
-    cx<T>* __restrict__ big = reinterpret_cast<cx<T>*>(it.big) + (size_t)n0 * N1 * pitch;
     LineTw<T, N1> tw;
     line_tw_load(tw, t, twid<T>(it.tw1));
+    if constexpr (PS) {
+        static_assert(LPT == 1, "one column per thread");
+        const int s0 = (int)blockIdx.z;
+        const size_t gsz = (size_t)g.n[0] * N1 * pitch;   // elements of one grid of big
+        cx<T>* __restrict__ src = reinterpret_cast<cx<T>*>(s0 ? it.preb : it.pre0) + (size_t)n0 * kept1 * pitch;
+        cx<T>* __restrict__ b0 = reinterpret_cast<cx<T>*>(it.big) + (size_t)(2 * s0) * gsz + (size_t)n0 * N1 * pitch;
+        cx<T>* __restrict__ b1 = b0 + gsz;
+        cx<T> w[2][8], sh[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) sh[q] = cispi<T>((T)sgn_idx(t + q * TPL, N1) / (T)N1);
+        if (a.mode > 0) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int i = stored_idx(t + q * TPL, N1, kept1, kp1);
+                w[0][q] = (cv[0] && i >= 0) ? src[(size_t)i * pitch + col[0]] : czero<T>();
+                w[1][q] = cmul(sh[q], w[0][q]);
+            }
+            fft_lines<T, N1, +1, PAD, 2>(w, t, lds + c0, 2 * TILE, TILE, tw);
+            if (cv[0]) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    b0[(size_t)(t + q * TPL) * pitch + col[0]] = w[0][q];
+                    b1[(size_t)(t + q * TPL) * pitch + col[0]] = w[1][q];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                w[0][q] = cv[0] ? b0[(size_t)(t + q * TPL) * pitch + col[0]] : czero<T>();
+                w[1][q] = cv[0] ? b1[(size_t)(t + q * TPL) * pitch + col[0]] : czero<T>();
+            }
+            fft_lines<T, N1, -1, PAD, 2>(w, t, lds + c0, 2 * TILE, TILE, tw);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int i = stored_idx(t + q * TPL, N1, kept1, kp1);
+                if (cv[0] && i >= 0) src[(size_t)i * pitch + col[0]] = T(0.5) * (w[0][q] + cmulc(w[1][q], sh[q]));
+            }
+        }
+        return;
+    }
+    cx<T>* __restrict__ small = reinterpret_cast<cx<T>*>(a.alt ? it.npre : it.pre0) + (size_t)n0 * kept1 * pitch;
+    cx<T>* __restrict__ big = reinterpret_cast<cx<T>*>(it.big) + (size_t)n0 * N1 * pitch;
     cx<T>* L = lds + c0;
     cx<T> v[LPT][8];
     if (a.mode > 0) {
@@ -1676,16 +1851,6 @@ struct Line1dArgs {
     int sub;      // sub-step of the scheduler tick
     int nsteps;   // MODE_STEP: steps of this launch
 };
-
-// e^{i pi x}
-template <typename T>
-__device__ __forceinline__ cx<T> cispi(T x)
-{
-    T s, c;
-    if constexpr (sizeof(T) == 4) sincospif(x, &s, &c);
-    else sincospi(x, &s, &c);
-    return {c, s};
-}
 
 // Twiddles of a line kernel: every power in registers (FP32) or the stage
 // bases only (FP64, whose registers are twice as wide).

@@ -22,7 +22,7 @@ hipError_t launch_row(const Geo& g, const Item* items, int nitems, int mode, int
 inline bool axis0_register_ok(const Geo& g, size_t real_bytes)
 {
     const size_t pre_bytes = (size_t)g.n[0] * (g.ndim == 3 ? g.kept[1] : 1) * g.pitch * 2 * real_bytes;
-    return g.dealias && pre_bytes < ((size_t)1 << 31);
+    return g.dealias == 1 && pre_bytes < ((size_t)1 << 31);
 }
 
 // lean: the plan keeps the SETD2 carry instead of phi and F_{n-1} (needs

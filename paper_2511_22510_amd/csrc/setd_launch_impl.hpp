@@ -37,7 +37,13 @@ static hipError_t launch_row_np(const Geo& g, const Item* items, int nitems, int
                                 int iter, bool kpz, hipStream_t s)
 {
     constexpr int tpl = N / 8;
-    const int lpw = big_block ? (tpl >= 256 ? 1 : 256 / tpl) : (tpl >= 64 ? 1 : 64 / tpl);
+    // KPZ and phase-shift steps hold two lines per row (pair); 256-thread
+    // blocks fall back to one wavefront's groups where they would pass 64 KiB
+    const bool ps = g.dealias == 2 && g.ndim >= 2 && mode == MODE_STEP;
+    const bool two = (kpz && !g.cplx) || ps;
+    const int small = tpl >= 64 ? 1 : 64 / tpl;
+    int lpw = big_block ? (tpl >= 256 ? 1 : 256 / tpl) : small;
+    if ((size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T) * (two ? 2 : 1) > 65536) lpw = small;
     RowArgs a;
     a.g = g;
     a.items = items;
@@ -48,6 +54,17 @@ static hipError_t launch_row_np(const Geo& g, const Item* items, int nitems, int
     a.sub = sub;
     const int lines = g.cplx ? a.nrows : (a.nrows + 1) / 2;
     const int groups = (lines + lpw - 1) / lpw;
+    if (ps) {
+        // phase shifts: the rows of pre and of its shifted copy (2D) or of the
+        // four grids in big (3D), grid z; two lines per row group in LDS, one
+        // group at a time
+        a.iter = 1;
+        dim3 gps(groups, nitems, g.ndim == 3 ? 4 : 2);
+        const size_t lps = (size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T) * 2;
+        if (g.cplx) hipLaunchKernelGGL((k_row_cplx<T, N, PAD, false, true>), gps, dim3(lpw * tpl), lps, s, a);
+        else hipLaunchKernelGGL((k_row_real<T, N, PAD, 3, false, false>), gps, dim3(lpw * tpl), lps, s, a);
+        return hipGetLastError();
+    }
     dim3 grid((groups + a.iter - 1) / a.iter, nitems);
     dim3 block(lpw * tpl);
     // KPZ steps hold two lines per row pair
@@ -56,21 +73,21 @@ static hipError_t launch_row_np(const Geo& g, const Item* items, int nitems, int
         if (mode == MODE_IC) hipLaunchKernelGGL((k_row_cplx<T, N, PAD, true>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((k_row_cplx<T, N, PAD, false>), grid, block, lds, s, a);
     } else if (mode == MODE_IC) {
-        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 2, true, false>), grid, block, lds, s, a);
+        if (g.dealias == 1) hipLaunchKernelGGL((k_row_real<T, N, PAD, 2, true, false>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((k_row_real<T, N, PAD, 2, false, false>), grid, block, lds, s, a);
     } else if (kpz) {
         if (a.iter > 1) {
-            if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, true, true>), grid, block, lds, s, a);
+            if (g.dealias == 1) hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, true, true>), grid, block, lds, s, a);
             else hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, false, true>), grid, block, lds, s, a);
         } else {
-            if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, true, false>), grid, block, lds, s, a);
+            if (g.dealias == 1) hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, true, false>), grid, block, lds, s, a);
             else hipLaunchKernelGGL((k_row_real<T, N, PAD, 1, false, false>), grid, block, lds, s, a);
         }
     } else if (a.iter > 1) {
-        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, true, true>), grid, block, lds, s, a);
+        if (g.dealias == 1) hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, true, true>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, false, true>), grid, block, lds, s, a);
     } else {
-        if (g.dealias) hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, true, false>), grid, block, lds, s, a);
+        if (g.dealias == 1) hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, true, false>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((k_row_real<T, N, PAD, 0, false, false>), grid, block, lds, s, a);
     }
     return hipGetLastError();
@@ -123,9 +140,53 @@ static hipError_t launch_axis_nt(const Geo& g, const Item* items, int nitems, in
     dim3 grid(a.per_item * nitems);
     dim3 block(TILE / LPT * (N / 8));
     const size_t lds = (size_t)TILE * lds_len<N, PAD>() * 2 * sizeof(T);
-    if (AX0 && kpz) hipLaunchKernelGGL((k_axis0<T, N, TILE, PAD, true, LPT>), grid, block, lds, s, a);
-    else if (AX0) hipLaunchKernelGGL((k_axis0<T, N, TILE, PAD, false, LPT>), grid, block, lds, s, a);
+    if (AX0 && kpz) hipLaunchKernelGGL((k_axis0<T, N, TILE, PAD, true, LPT, false>), grid, block, lds, s, a);
+    else if (AX0) hipLaunchKernelGGL((k_axis0<T, N, TILE, PAD, false, LPT, false>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((k_axis1<T, N, TILE, PAD, LPT>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+// axis-0 pass of a plan with phase-shift dealiasing (k_axis0 with PS): the
+// half-width tile, one column per thread, LDS for the lines and their shifted
+// copies (padded only where both halves fit 64 KiB)
+template <typename T, int N>
+static hipError_t launch_axis0_ps(const Geo& g, const Item* items, int nitems, int mode, int sub, hipStream_t s)
+{
+    constexpr int TILE = tile_max<T>(N) / 2;
+    constexpr int PAD = ((size_t)2 * TILE * lds_len<N, 3>() * 2 * sizeof(T) <= 65536) ? 3 : 0;
+    constexpr size_t lds = (size_t)2 * TILE * lds_len<N, PAD>() * 2 * sizeof(T);
+    static_assert(lds <= 65536, "phase-shift axis-0 tile exceeds 64 KiB of LDS");
+    AxisArgs a{};
+    a.g = g;
+    a.items = items;
+    a.ntiles = g.pitch / TILE;
+    a.per_item = a.ntiles * ((g.ndim == 3) ? g.kept[1] : 1);
+    a.mode = mode;
+    a.sub = sub;
+    hipLaunchKernelGGL((k_axis0<T, N, TILE, PAD, false, 1, true>), dim3(a.per_item * nitems), dim3(TILE * (N / 8)), lds,
+                       s, a);
+    return hipGetLastError();
+}
+
+// axis-1 passes of a 3D step with phase shifts (k_axis1 with PS): dir +1 takes
+// pre and preb (grid z) to the four grids of big, -1 back; the half-width tile,
+// one column per thread, two lines side by side in LDS
+template <typename T, int N>
+static hipError_t launch_axis1_ps(const Geo& g, const Item* items, int nitems, int dir, int sub, hipStream_t s)
+{
+    constexpr int TILE = tile_max<T>(N) / 2;
+    constexpr int PAD = ((size_t)2 * TILE * lds_len<N, 3>() * 2 * sizeof(T) <= 65536) ? 3 : 0;
+    constexpr size_t lds = (size_t)2 * TILE * lds_len<N, PAD>() * 2 * sizeof(T);
+    static_assert(lds <= 65536, "phase-shift axis-1 tile exceeds 64 KiB of LDS");
+    AxisArgs a{};
+    a.g = g;
+    a.items = items;
+    a.ntiles = g.pitch / TILE;
+    a.per_item = a.ntiles * g.n[0];
+    a.mode = dir;
+    a.sub = sub;
+    hipLaunchKernelGGL((k_axis1<T, N, TILE, PAD, 1, true>), dim3(a.per_item * nitems, 1, 2), dim3(TILE * (N / 8)),
+                       lds, s, a);
     return hipGetLastError();
 }
 
@@ -207,6 +268,12 @@ static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int
             return e;
         }
         if (var >= 4) var = ((var - 4) % 2 == 0) ? 3 : 0;
+        if (g.dealias == 2) {
+            hipError_t e = launch_axis0_ps<T, N>(g, items, nitems, mode, sub, s);
+            if (e == hipSuccess && (mode == MODE_STEP || mode == MODE_IC))
+                e = launch_hermitian_t<T>(g, items, nitems, 0, sub, s);
+            return e;
+        }
     }
     hipError_t e;
     switch (var) {
@@ -240,6 +307,11 @@ hipError_t launch_hermitian(const Geo& g, const Item* items, int nitems, int whi
 template <typename T>
 hipError_t launch_axis1(const Geo& g, const Item* items, int nitems, int dir, int sub, int var, hipStream_t s)
 {
+    // dir +3 / -3: the phase-shift passes of a step (pre, preb <-> four grids)
+    if (dir == 3 || dir == -3) {
+        if (g.ndim != 3 || g.dealias != 2) return hipErrorInvalidValue;
+        SETD_DISPATCH_N(g.n[1], return (launch_axis1_ps<T, NN>(g, items, nitems, dir / 3, sub, s)));
+    }
     SETD_DISPATCH_N(g.n[1], return (launch_axis_n<T, NN, false>(g, items, nitems, dir, sub, var, false, false, s)));
     return hipSuccess;
 }

@@ -57,7 +57,9 @@ setd_status validate(const setd_desc& d)
     if (d.precision != 32 && d.precision != 64) return fail(SETD_E_INVAL, "precision must be 32 or 64");
     if (d.realizations < 1) return fail(SETD_E_INVAL, "realizations must be >= 1");
     if (d.dealias < 0 || d.dealias > 2) return fail(SETD_E_INVAL, "dealias must be 0, 1 or 2");
-    if (d.dealias == 2 && d.ndim != 1) return fail(SETD_E_UNSUPPORTED, "phase-shift dealiasing is built for 1D lines");
+    if (d.dealias == 2 && d.ndim >= 2 && d.nl == NL_KPZ)
+        return fail(SETD_E_UNSUPPORTED, "phase-shift dealiasing on 2D/3D lattices is built for the phi^3 and CGL "
+                                        "terms (the 2/3 rule is already exact for the quadratic KPZ term)");
     if (d.dealias == 2 && d.noise_space == 1)
         return fail(SETD_E_UNSUPPORTED, "phase-shift dealiasing is not combined with real-space noise");
     if (d.series_len != 0 && !pow2_in(d.series_len, 8, 1024))
@@ -177,7 +179,8 @@ setd_status Plan::init(const setd_desc& desc)
     const size_t k1 = (d.ndim == 3) ? (size_t)g.kept[1] : 1;
     S = (size_t)geo_rows(g) * g.pitch;
     P = (d.ndim == 1) ? 0 : (size_t)g.n[0] * k1 * g.pitch;   // a line keeps no partial transform
-    B = (d.ndim == 3) ? (size_t)g.n[0] * g.n[1] * g.pitch : 0;
+    // 3D: the line buffer of the last-axis pass, four grids of it with phase shifts
+    B = (d.ndim == 3) ? (size_t)g.n[0] * g.n[1] * g.pitch * (d.dealias == 2 ? 4 : 1) : 0;
     // Realizations of an array lie an odd multiple of 256 bytes apart: blocks
     // that work on the same columns of different realizations at the same
     // time then reach different HBM channels instead of addresses that agree
@@ -230,6 +233,7 @@ setd_status Plan::init(const setd_desc& desc)
         lay.npre = take((size_t)R * Pb);
         lay.noise = take((size_t)R * Sb);
     }
+    if (ps_grid()) lay.preb = take((size_t)R * Pb);
     if (iso) {
         lay.boxn = 0;
         for (int l = 2; l <= d.n[0]; l *= 2) {
@@ -276,6 +280,12 @@ void Plan::pass_bytes(double* out) const
     }
     if (d.ndim == 2) {
         const double pre = (double)g.n[0] * kl;
+        if (ps_grid()) {
+            // phase shifts: pre and its shifted copy in and out of both passes
+            out[0] = 4.0 * pre * e;
+            out[1] = (4.0 * pre + (2.0 + hist) * st) * e;
+            return;
+        }
         const double npre = (d.nl == NL_KPZ) ? 2.0 : 1.0;
         out[0] = (npre + 1.0) * pre * e;                        // row pass: read pre (and pre1), write pre
         out[1] = ((1.0 + npre) * pre + (2.0 + hist) * st) * e;  // axis 0: pre in/out, state, history
@@ -283,6 +293,14 @@ void Plan::pass_bytes(double* out) const
     }
     const double small = (double)g.n[0] * g.kept[1] * kl;
     const double bigv = (double)g.n[0] * g.n[1] * kl;
+    if (ps_grid()) {
+        // phase shifts: pre and preb, four grids of the line buffer
+        out[0] = (2.0 * small + 4.0 * bigv) * e;
+        out[1] = 8.0 * bigv * e;
+        out[2] = (4.0 * bigv + 2.0 * small) * e;
+        out[3] = (4.0 * small + (2.0 + hist) * st) * e;
+        return;
+    }
     out[0] = (small + bigv) * e;                                // axis-1 inverse
     out[1] = 2.0 * bigv * e;                                    // row pass
     out[2] = (bigv + small) * e;                                // axis-1 forward
@@ -324,10 +342,12 @@ static setd_status launch_pass_t(const Plan& p, int i, const Item* items_dev, in
         else SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.ax0, p.d.nl == NL_KPZ, p.lean, s)));
         return SETD_OK;
     }
+    // phase shifts: the axis-1 passes carry pre and preb to and from four grids
+    const int ps = g.dealias == 2 ? 3 : 1;
     switch (i) {
-    case 0: SETD_HIP((launch_axis1<T>(g, items_dev, nitems, +1, sub, p.tune.ax1, s))); break;
+    case 0: SETD_HIP((launch_axis1<T>(g, items_dev, nitems, +ps, sub, p.tune.ax1, s))); break;
     case 1: SETD_HIP((launch_row<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.row, p.d.nl == NL_KPZ, s))); break;
-    case 2: SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -1, sub, p.tune.ax1, s))); break;
+    case 2: SETD_HIP((launch_axis1<T>(g, items_dev, nitems, -ps, sub, p.tune.ax1, s))); break;
     default: SETD_HIP((launch_axis0<T>(g, items_dev, nitems, MODE_STEP, sub, p.tune.ax0, p.d.nl == NL_KPZ, p.lean, s))); break;
     }
     return SETD_OK;
@@ -432,6 +452,7 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
         it.snap = ws + lay.snap + (size_t)r * Sb;
         it.npre = rsn_grid() ? ws + lay.npre + (size_t)r * Pb : nullptr;
         it.noise = rsn_grid() ? ws + lay.noise + (size_t)r * Sb : nullptr;
+        it.preb = ps_grid() ? ws + lay.preb + (size_t)r * Pb : nullptr;
         it.coef = ws + ((d.precision == 32) ? lay.coef32 : lay.coef64);
         const size_t* tw = (d.precision == 32) ? lay.tw32 : lay.tw64;
         it.tw0 = ws + tw[0];
@@ -611,7 +632,7 @@ setd_status Plan::autotune()
     // fields; axis-0 variants 4 and up (register update) for dealiased plans,
     // and are the only ones a plan keeping the SETD2 carry can step with;
     // the item groups of variants 6..11 need 2, 4 or 8 items
-    const int ax0_top = !g.dealias ? 4 : (R >= 8 ? 12 : (R >= 4 ? 10 : (R >= 2 ? 8 : 6)));
+    const int ax0_top = g.dealias != 1 ? 4 : (R >= 8 ? 12 : (R >= 4 ? 10 : (R >= 2 ? 8 : 6)));
     Knob knobs[3] = {{&tune.row, 0, d.complex_field ? 4 : 16, row_pass, -1},
                      {&tune.ax0, lean ? 4 : 0, ax0_top, ax0_pass, -1},
                      {&tune.ax1, 0, 4, 0, 2}};

@@ -30,6 +30,7 @@ struct Layout {
     size_t twm64 = 0, twm32 = 0, specacc = 0, series = 0, fdtacc = 0;   // time series (series_len > 0)
     size_t boxcls = 0, boxn = 0;  // box-width class sums and their count (equal n[i])
     size_t npre = 0, noise = 0;   // real-space noise on 2D/3D lattices: intermediate, eta_a
+    size_t preb = 0;              // phase-shift dealiasing (2D): the shifted intermediate
     size_t total = 0;
 };
 
@@ -103,6 +104,9 @@ struct Plan {
     // 2D/3D plans with real-space noise: its transform for the current step
     setd_status launch_noise(const Item* items_dev, int nitems, int sub, hipStream_t s) const;
     bool rsn_grid() const { return d.noise_space == 1 && d.ndim >= 2; }
+    // 2D/3D plans with phase-shift dealiasing keep a shifted copy of pre
+    // (3D: and four grids in the line buffer)
+    bool ps_grid() const { return d.dealias == 2 && d.ndim >= 2; }
     // queue pass i (launch order) of one step
     setd_status launch_pass(int i, const Item* items_dev, int nitems, int sub, hipStream_t s) const;
     setd_status profile_read(double* out, size_t cap, size_t* len);

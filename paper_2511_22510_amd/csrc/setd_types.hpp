@@ -13,7 +13,7 @@ struct Geo {
     int ndim;         // 2 or 3
     int cplx;         // 0 real field (last axis R2C), 1 complex field
     int prec;         // 32 or 64
-    int dealias;      // 0 or 1
+    int dealias;      // 0 none, 1 the 2/3 rule, 2 phase shift
     int n[3];         // lattice points per axis (n[ndim..2] = 1)
     int kept[3];      // stored spectral entries per axis
     int kp[3];        // largest stored FFT index on the low side of each axis
@@ -48,6 +48,7 @@ struct Item {
     void* snap;       // snapshot of phi for two-time correlations
     void* npre;       // real-space noise (2D/3D): its transform over the last axes, laid out as pre0
     void* noise;      // real-space noise (2D/3D): eta_a of the step in the stored layout of phi
+    void* preb;       // phase-shift dealiasing (2D): axis-0 inverse of e^{i pi a0/N0} phi, laid out as pre0
     const void* coef; // coefficient table in the state precision
     const void* tw0;  // twiddles exp(-2 pi i k / n_axis), state precision
     const void* tw1;

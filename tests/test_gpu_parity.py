@@ -173,6 +173,45 @@ def test_real_space_noise_full_size_model_b():
     assert err <= 2e-4
 
 
+# phase-shift dealiasing on 2D lattices (reading 25: the mean over the four
+# grids moved by dx/2 along no axis, either axis or both): real and complex
+# fields, both precisions and orders, anisotropic lattices, the largest axis-0
+# tile (64 KiB of LDS at N0 = 1024 in FP32 and N0 = 512 in FP64)
+PS_CASES = [
+    W.model_a([64, 64], precision=64, order=2, realizations=2, dealias=2),
+    W.model_a([32, 64], precision=32, order=1, realizations=3, dealias=2),
+    W.model_b([64, 64], precision=32, realizations=2, dealias=2),
+    W.cgl([32, 32], precision=64, realizations=2, dealias=2),
+    W.cgl([64, 32], precision=32, order=1, realizations=1, dx=0.5, dealias=2),
+    W.model_a([16, 16], precision=64, order=2, realizations=1, ic_sigma=0.4, dealias=2),
+    W.model_a([8, 8], precision=32, order=2, realizations=2, dealias=2),
+    W.model_a([1024, 32], precision=32, order=2, realizations=1, dealias=2),
+    W.model_b([512, 16], precision=64, realizations=1, dealias=2),
+    W.model_a([32, 32], precision=64, nl="none", u=0.0, r=0.5, realizations=1, dealias=2),
+    # 3D: eight grids
+    W.model_a([16, 16, 16], precision=64, order=2, realizations=2, dealias=2),
+    W.model_a([32, 16, 16], precision=32, order=1, realizations=2, dealias=2),
+    W.model_b([16, 32, 16], precision=32, realizations=1, dealias=2),
+    W.model_b([16, 16, 16], precision=64, realizations=1, ic_kind=1, ic_sigma=0.3, dealias=2),
+    W.cgl([16, 16, 16], precision=64, realizations=2, dealias=2),
+    W.cgl([32, 16, 32], precision=32, order=1, realizations=1, dealias=2),
+    W.model_a([8, 8, 8], precision=32, order=2, realizations=3, dealias=2),
+]
+
+
+@pytest.mark.parametrize("p", PS_CASES, ids=lambda p: "ps-%s-%s-f%d-o%d" % (
+    p["nl"], "x".join(map(str, p["n"])), p["precision"], p["order"]))
+def test_phase_shift_lattice_parity(p):
+    """The row pass evaluates the nonlinearity on the rows and on the rows
+    moved by dx/2, for pre and for its axis-0-shifted copy (3D: for the four
+    grids the axis-1 pass makes of them, moved or not along axis 1); the
+    passes after it fold the grids back, and the axis-0 pass combines the last
+    two; the oracle averages its 2^d shifted evaluations directly."""
+    err = run_pair(p, steps=100, every=1)
+    say("max rel err", err)
+    assert err <= TOL[p["precision"]]
+
+
 @pytest.mark.parametrize("history", [0, 1])
 @pytest.mark.parametrize("prec", [32, 64])
 def test_long_model_a_stays_on_the_oracle(prec, history):

@@ -49,6 +49,10 @@ MIX = [
     # line options: their own launch classes
     (W.model_a([256], precision=32, realizations=2, seed=113, dx=0.25, dealias=2), 17),
     (W.model_a([256], precision=32, realizations=1, seed=114, dx=0.25, noise_space=1), 23),
+    # 2D options: phase shifts, real-space noise
+    (W.model_a([64, 64], precision=32, order=2, realizations=2, seed=115, dealias=2), 21),
+    (W.model_b([64, 64], precision=32, realizations=2, seed=116, noise_space=1), 17),
+    (W.cgl([16, 16, 16], precision=32, realizations=1, seed=117, dealias=2), 15),
 ]
 
 

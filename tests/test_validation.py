@@ -38,7 +38,6 @@ def _status(p):
     (dict(series_len=12), "SETD_E_INVAL"),
     (dict(c2=(-1.0, 0.5)), "SETD_E_INVAL"),          # complex c(k) on a real field
     (dict(noise_space=2), "SETD_E_INVAL"),
-    (dict(dealias=2), "SETD_E_UNSUPPORTED"),         # phase shift off lines
     (dict(nl="cgl"), "SETD_E_UNSUPPORTED"),          # CGL needs a complex field
 ])
 def test_invalid_descriptors_are_refused(bad, code):
@@ -53,6 +52,12 @@ def test_invalid_descriptors_are_refused(bad, code):
 def test_unsupported_combinations():
     from paper_2511_22510_amd import setd
     assert _status(W.kpz([32, 32, 32]))[0] == setd.SETD_E_UNSUPPORTED
+    assert _status(W.kpz([32, 32], dealias=2))[0] == setd.SETD_E_UNSUPPORTED
+    assert _status(W.model_a([32, 32], dealias=2))[0] == setd.SETD_OK
+    assert _status(W.cgl([32, 32], dealias=2))[0] == setd.SETD_OK
+    assert _status(W.model_b([16, 16, 16], dealias=2))[0] == setd.SETD_OK
+    assert _status(W.cgl([16, 16, 16], dealias=2))[0] == setd.SETD_OK
+    assert _status(W.model_a([16, 16, 16], dealias=2, noise_space=1))[0] == setd.SETD_E_UNSUPPORTED
     assert _status(W.model_a([64], dealias=2, noise_space=1))[0] == setd.SETD_E_UNSUPPORTED
     assert _status(dict(W.cgl([32, 32]), nl="phi3"))[0] == setd.SETD_E_UNSUPPORTED
 
@@ -64,6 +69,9 @@ def test_unsupported_combinations():
     (W.model_a([256]), 86, 129, 1),                      # a line: K + 1
     (W.model_a([256], dealias=2), 128, 129, 1),          # phase shift: |a| < N/2
     (W.cgl([64], dealias=0), 64, 33, 1),
+    (W.model_a([64, 64], dealias=2), 63 * 32, 47, 2),  # phase shifts: |a_i| < N_i/2
+    (W.cgl([16, 16, 16], dealias=2), 15 ** 3, 15, 4),
+    (W.model_a([16, 32, 16], dealias=2), 15 * 31 * 8, 21, 4),
 ])
 def test_plan_sizes(p, kept, nb, passes):
     from paper_2511_22510_amd import setd
