@@ -214,9 +214,10 @@ typedef struct {
                                  variant bits: 0 LDS padding, 1 256-thread
                                  workgroups, 2-3 log2 of the row-pair groups a
                                  workgroup takes in turn (real fields); axis-0
-                                 variants 4 and up update in registers: 4 + 2j
-                                 and 5 + 2j at two tile widths, the items
-                                 interleaved per column tile in groups of 2^j   */
+                                 variants 4 and up update in registers: 4 + 2j,
+                                 5 + 2j and 12 + j at three tile widths, the
+                                 items interleaved per column tile in groups of
+                                 2^j                                             */
     int axis_tile[2];         /* axis-0 pass: column tile width, columns per thread */
     int streams;              /* 2 when setd_step runs the two halves of the
                                  realizations on the bound stream and an

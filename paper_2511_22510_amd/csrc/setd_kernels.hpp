@@ -109,6 +109,13 @@ __device__ __forceinline__ Coef<T> load_coef_t(const void* coef, int key)
 
 // key of a mode in a shell-indexed table: |a|^2 (equal dk on every axis) or
 // the separable (|a0|, |a1|, |a2|) index
+// entry of a 2D lattice's per-mode table: row |a0| (c(k) and D(k) depend on
+// k0 through k0^2 only, so a0 and -a0 share a row), column of the stored last axis
+__device__ __forceinline__ int per_mode_key(const Geo& g, int a0, int col)
+{
+    return (a0 < 0 ? -a0 : a0) * g.pitch + col;
+}
+
 __device__ __forceinline__ int coef_key(const Item& it, int a0, int a1, int a2)
 {
     if (it.coef_mode == COEF_ISO) return a0 * a0 + a1 * a1 + a2 * a2;
@@ -879,12 +886,12 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
                     f.ph = phi[si];
                     if (use_prev) f.pv = prev[si];
                     int key;
+                    const int a0 = sgn_idx(fft_pos(i0, N0, kept0, kp0), N0);
                     if (it.coef_mode == COEF_PER_MODE) {
-                        key = i0 * g.pitch + colm;
+                        key = per_mode_key(g, a0, colm);
                     } else {
                         int jlm, alm;
                         last_pos(colm, jlm, alm);
-                        const int a0 = sgn_idx(fft_pos(i0, N0, kept0, kp0), N0);
                         key = (g.ndim == 3) ? coef_key(it, a0, a1, alm) : coef_key(it, a0, alm, 0);
                     }
                     f.cf = load_coef<T>(it, key);
@@ -1193,7 +1200,11 @@ __device__ __forceinline__ void axis0r_body(const AxisArgs& a, const int item, c
 
     fft_lines<T, N0, -1, PAD, 1>(v, t, L, TILE, 0, tw);
     const bool per_mode = it.coef_mode == COEF_PER_MODE;
+    // per-mode table rows |a0|: bins q <= 2 (a0 = t + q N0/8) read row
+    // t + q N0/8, bins q >= 5 (a0 = t + q N0/8 - N0) row
+    // (N0/8 - 1 - t) + N0 - (q + 1) N0/8 + 1: a lane part and a uniform part each
     const uint32_t vcoef = ((uint32_t)t * g.pitch + colm) * CS;
+    const uint32_t vcoefn = ((uint32_t)(TPL - 1 - t) * g.pitch + colm) * CS;
     // Keyed coefficients (3D): the block needs the entries of |a0| = 0..K0 for
     // its TILE columns only, and a0 and -a0 share one.  Each is gathered once
     // into LDS, which the transform leaves free until the inverse starts.
@@ -1240,9 +1251,9 @@ __device__ __forceinline__ void axis0r_body(const AxisArgs& a, const int item, c
         }
         uint32_t vo, so;
         if (per_mode) {
-            // entry (row, column) of the table in the state layout
-            vo = st ? vcoef : BUF_OOB;
-            so = (uint32_t)(q * TPL + dq(q)) * g.pitch * CS;
+            // entry (|a0|, column) of the table
+            vo = st ? (q >= 5 ? vcoefn : vcoef) : BUF_OOB;
+            so = (uint32_t)(q >= 5 ? N0 - (q + 1) * TPL + 1 : q * TPL) * g.pitch * CS;
         } else {
             const int a0 = sgn_idx(t + q * TPL, N0);
             const int key = (g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0);
@@ -1659,7 +1670,7 @@ __global__ void __launch_bounds__(256) k_linear(LinArgs a)
                 jl = fft_pos(col, g.n[last], g.kept[last], g.kp[last]);
                 al = sgn_idx(jl, g.n[last]);
             }
-            const int key = (it.coef_mode == COEF_PER_MODE) ? i0 * g.pitch + col
+            const int key = (it.coef_mode == COEF_PER_MODE) ? per_mode_key(g, a0, col)
                             : (g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0);
             const Coef<T> cf = load_coef<T>(it, key);
             // Fourier-space draws, or the transformed real-space noise (separate
@@ -1794,7 +1805,7 @@ __global__ void __launch_bounds__(256) k_observe(ObsArgs a)
             // conj eta_a(n') / G_a with the step's own unit noise, regenerated
             // in the state precision, and G_a of the coefficient table
             const int ew = it.coef_cplx ? 8 : 4;   // table words per entry
-            const int entry = (it.coef_mode == COEF_PER_MODE) ? i0 * g.pitch + col
+            const int entry = (it.coef_mode == COEF_PER_MODE) ? per_mode_key(g, a0, col)
                               : ((g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0));
             const double G = (double)reinterpret_cast<const T*>(it.coef)[(size_t)entry * ew + (it.coef_cplx ? 6 : 3)];
             if (!(G > 0.0)) continue;
@@ -2615,7 +2626,7 @@ __global__ void __launch_bounds__(256) k_spectrum(SpecArgs a)
     double G = 0.0, Da = 0.0;
     if (use) {
         const int ew = it.coef_cplx ? 8 : 4;
-        const int entry = (it.coef_mode == COEF_PER_MODE) ? i0 * g.pitch + col
+        const int entry = (it.coef_mode == COEF_PER_MODE) ? per_mode_key(g, a0, col)
                           : ((g.ndim == 3) ? coef_key(it, a0, a1, al) : coef_key(it, a0, al, 0));
         G = (double)reinterpret_cast<const T*>(it.coef)[(size_t)entry * ew + (it.coef_cplx ? 6 : 3)];
         const double k0 = it.dk[0] * a0;

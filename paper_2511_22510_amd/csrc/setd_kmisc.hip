@@ -15,9 +15,10 @@ __global__ void __launch_bounds__(256) k_coef(CoefArgs a)
     if (key >= a.nkeys) return;
     double k2;
     if (a.mode == COEF_PER_MODE) {
-        // one entry per stored mode of a 2D lattice, in the state layout
+        // a 2D lattice: one entry per |a0| (row) and stored column of the last
+        // axis, in the padded row layout of the state
         const Geo& g = a.g;
-        const int i0 = key / g.pitch, col = key % g.pitch;
+        const int a0 = key / g.pitch, col = key % g.pitch;
         if (col >= g.kept[1]) {
             const int w = a.cplx_table ? 8 : 4;
             for (int i = 0; i < w; i++) {
@@ -26,8 +27,6 @@ __global__ void __launch_bounds__(256) k_coef(CoefArgs a)
             }
             return;
         }
-        const int j0 = (i0 <= g.kp[0]) ? i0 : i0 + g.n[0] - g.kept[0];
-        const int a0 = (j0 < g.n[0] / 2) ? j0 : j0 - g.n[0];
         int a1 = col;
         if (g.cplx) {
             const int j1 = (col <= g.kp[1]) ? col : col + g.n[1] - g.kept[1];
@@ -211,10 +210,11 @@ __global__ void k_obs_mean(int nb, const double* skacc, double* out)
 void axis_shape(int precision, int n, int var, int* tile, int* lpt)
 {
     const int tm = (precision == 32) ? (n <= 512 ? 16 : 8) : (n <= 512 ? 8 : 4);
-    static const int tl[6] = {1, 1, 1, 2, 2, 1};
-    static const int lp[6] = {2, 1, 4, 1, 1, 1};
-    // register-kernel variants 4 + 2j / 5 + 2j share the tiles of 4 / 5
-    const int v = (var >= 0 && var < 6) ? var : (var >= 6 && var < 12 ? 4 + (var - 4) % 2 : 0);
+    static const int tl[7] = {1, 1, 1, 2, 2, 1, 4};
+    static const int lp[7] = {2, 1, 4, 1, 1, 1, 1};
+    // register-kernel variants 4 + 2j / 5 + 2j share the tiles of 4 / 5, and
+    // 12 + j take a quarter of tm
+    const int v = (var >= 0 && var < 6) ? var : (var >= 6 && var < 12 ? 4 + (var - 4) % 2 : (var >= 12 && var < 16 ? 6 : 0));
     *tile = tm / tl[v] > 0 ? tm / tl[v] : 1;
     *lpt = lp[v];
 }

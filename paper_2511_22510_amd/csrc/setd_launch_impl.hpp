@@ -7,8 +7,9 @@
 //              {(tm, 2), (tm, 1), (tm, 4), (tm/2, 1)}, tm = tile_max, with LDS
 //              padding whenever the padded tile still fits 64 KiB; the axis-0
 //              time step also has the register-update kernel k_axis0r with
-//              tile tm/2 (variants 4, 6, 8, 10) or tm (5, 7, 9, 11), its items
-//              interleaved per column tile in groups of 1, 2, 4 or 8
+//              tile tm/2 (variants 4, 6, 8, 10), tm (5, 7, 9, 11) or tm/4
+//              (12 to 15), its items interleaved per column tile in groups of
+//              1, 2, 4 or 8
 #pragma once
 
 #include <cmath>
@@ -253,13 +254,14 @@ static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int
         // (axis0_register_ok); other modes and plans take the tile-sweep
         // kernel.  A plan keeping the SETD2 carry steps with the register
         // kernel only.
-        // variants 4 + 2j (tile TM/2) and 5 + 2j (tile TM): items interleaved in
-        // groups of 2^j per column tile
+        // variants 4 + 2j (tile TM/2), 5 + 2j (tile TM) and 12 + j (tile TM/4),
+        // j = 0..3: items interleaved in groups of 2^j per column tile
         const bool reg = mode == MODE_STEP && axis0_register_ok(g, sizeof(T));
         if (reg && lean && var < 4) var = 4;
         if (reg && var >= 4) {
-            const int group = 1 << ((var - 4) / 2);
-            hipError_t e = ((var - 4) % 2 == 0)
+            const int group = 1 << (var >= 12 ? var - 12 : (var - 4) / 2);
+            hipError_t e = (var >= 12) ? launch_axis0r<T, N, (TM >= 4 ? TM / 4 : 1)>(g, items, nitems, mode, sub, kpz, lean, group, s)
+                           : ((var - 4) % 2 == 0)
                                ? launch_axis0r<T, N, (TM >= 2 ? TM / 2 : 1)>(g, items, nitems, mode, sub, kpz, lean, group, s)
                                : launch_axis0r<T, N, TM>(g, items, nitems, mode, sub, kpz, lean, group, s);
             // the register kernel keeps a 2D real field's column a_last = 0
@@ -267,7 +269,7 @@ static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int
             if (e == hipSuccess && g.ndim == 3) e = launch_hermitian_t<T>(g, items, nitems, lean ? 1 : 0, sub, s);
             return e;
         }
-        if (var >= 4) var = ((var - 4) % 2 == 0) ? 3 : 0;
+        if (var >= 4) var = (var >= 12 || (var - 4) % 2 == 0) ? 3 : 0;
         if (g.dealias == 2) {
             hipError_t e = launch_axis0_ps<T, N>(g, items, nitems, mode, sub, s);
             if (e == hipSuccess && (mode == MODE_STEP || mode == MODE_IC))

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <fstream>
+#include <sstream>
 #include <map>
 #include <mutex>
 #include <new>
@@ -154,7 +155,7 @@ setd_status Plan::init(const setd_desc& desc)
         keydim[1] = keydim[2] = 1;
         nkeys = keydim[0];
     } else if (d.ndim == 2) {
-        coef_mode = COEF_PER_MODE;   // the state layout: coalesced, shared by all realizations
+        coef_mode = COEF_PER_MODE;   // rows |a0| in the state's row layout: coalesced, shared by all realizations
         keydim[0] = keydim[1] = keydim[2] = 1;
     } else if (iso) {
         coef_mode = COEF_ISO;
@@ -175,7 +176,8 @@ setd_status Plan::init(const setd_desc& desc)
     nbins = ceil_isqrt_host(msq) + 1;
 
     // sizes
-    if (coef_mode == COEF_PER_MODE) nkeys = g.kept[0] * g.pitch;
+    // per-mode table of a 2D lattice: rows |a0| = 0..max, the stored columns
+    if (coef_mode == COEF_PER_MODE) nkeys = (kmax[0] + 1) * g.pitch;
     const size_t k1 = (d.ndim == 3) ? (size_t)g.kept[1] : 1;
     S = (size_t)geo_rows(g) * g.pitch;
     P = (d.ndim == 1) ? 0 : (size_t)g.n[0] * k1 * g.pitch;   // a line keeps no partial transform
@@ -576,10 +578,16 @@ static void tune_cache_load()
     g_tune_loaded = true;
     const char* path = std::getenv("SETD_TUNE_CACHE");
     if (!path) return;
+    // one "key row axis0 axis1 split" per line; lines starting with '#' are comments
     std::ifstream f(path);
-    std::string key;
-    Tune t;
-    while (f >> key >> t.row >> t.ax0 >> t.ax1 >> t.split) g_tune_cache[key] = t;
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream ls(line);
+        std::string key;
+        Tune t;
+        if (ls >> key >> t.row >> t.ax0 >> t.ax1 >> t.split) g_tune_cache[key] = t;
+    }
 }
 
 static void tune_cache_store(const std::string& key, const Tune& t)
@@ -596,7 +604,7 @@ setd_status Plan::autotune()
     // SETD_VARIANT="row,axis0,axis1" pins the variants (tests, reproducible timing)
     if (const char* pin = std::getenv("SETD_VARIANT")) {
         int r = 0, a0 = 0, a1 = 0;
-        if (sscanf(pin, "%d,%d,%d", &r, &a0, &a1) == 3 && r >= 0 && r < 16 && a0 >= 0 && a0 < 12 && a1 >= 0 && a1 < 4) {
+        if (sscanf(pin, "%d,%d,%d", &r, &a0, &a1) == 3 && r >= 0 && r < 16 && a0 >= 0 && a0 < 16 && a1 >= 0 && a1 < 4) {
             tune.row = r;
             tune.ax0 = (lean && a0 < 4) ? 4 : a0;   // a lean plan steps with the register kernel
             tune.ax1 = a1;
@@ -605,7 +613,7 @@ setd_status Plan::autotune()
             tune.split = (sp && sp[0] == '2') ? 2 : 1;
             return SETD_OK;
         }
-        return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row in 0..15, axis0 in 0..11, axis1 in 0..3");
+        return fail(SETD_E_INVAL, "SETD_VARIANT must be \"row,axis0,axis1\" with row in 0..15, axis0 in 0..15, axis1 in 0..3");
     }
     const char* env = std::getenv("SETD_AUTOTUNE");
     if ((env && env[0] == '0') || no_alloc) return SETD_OK;
@@ -629,10 +637,15 @@ setd_status Plan::autotune()
     const int ax0_pass = (d.ndim == 2) ? 1 : 3;
     struct Knob { int* var; int first; int nvar; int pass; int pass2; };
     // row variants 4..15 (several pair groups per workgroup) exist for real
-    // fields; axis-0 variants 4 and up (register update) for dealiased plans,
-    // and are the only ones a plan keeping the SETD2 carry can step with;
-    // the item groups of variants 6..11 need 2, 4 or 8 items
-    const int ax0_top = g.dealias != 1 ? 4 : (R >= 8 ? 12 : (R >= 4 ? 10 : (R >= 2 ? 8 : 6)));
+    // fields; axis-0 variants 4 and up (register update) for plans under the
+    // 2/3 rule, and are the only ones a plan keeping the SETD2 carry can step
+    // with; the item groups of variants 6..11 and 13..15 need 2, 4 or 8 items
+    const int ax0_top = g.dealias != 1 ? 4 : 16;
+    auto ax0_ok = [&](int v) {
+        if (v < 4 || v >= 16) return true;
+        const int group = 1 << (v >= 12 ? v - 12 : (v - 4) / 2);
+        return group <= R;
+    };
     Knob knobs[3] = {{&tune.row, 0, d.complex_field ? 4 : 16, row_pass, -1},
                      {&tune.ax0, lean ? 4 : 0, ax0_top, ax0_pass, -1},
                      {&tune.ax1, 0, 4, 0, 2}};
@@ -646,6 +659,7 @@ setd_status Plan::autotune()
         // outlier of one timing does not decide the choice
         for (int round = 0; round < 2 && st == SETD_OK; round++)
         for (int v = kb.first; v < kb.nvar && st == SETD_OK; v++) {
+            if (kb.var == &tune.ax0 && !ax0_ok(v)) continue;
             *kb.var = v;
             auto run = [&]() -> setd_status {
                 setd_status s1 = launch_pass(kb.pass, items_dev, R, 0, stream);

@@ -87,3 +87,30 @@ def test_more_than_one_gpu_is_refused_with_a_message():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_shipped_variant_table_parses_and_covers_the_timed_workloads(monkeypatch):
+    """Every entry of the shipped table is a launch-class key and four
+    variant numbers in the ranges the library accepts; the workloads the
+    bench times have an entry; the bench hands the library a private copy."""
+    keys = {}
+    with open(bench.TUNED_TABLE) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            key, row, ax0, ax1, streams = line.split()
+            assert len(key.split("|")) == 12
+            assert 0 <= int(row) < 16 and 0 <= int(ax0) < 16 and 0 <= int(ax1) < 4 and int(streams) in (1, 2)
+            keys[key] = int(ax0)
+    # Model B 512^2 x 64 and x 256, KPZ 1024^2 x 16, CGL 256^3 x 4 (SETD2, 2/3 rule, carry storage)
+    for k in ("2|0|32|1|512|512|1|0|1|0|64|1", "2|0|32|1|512|512|1|0|1|0|256|1",
+              "2|0|32|1|1024|1024|1|2|1|0|16|2", "3|1|32|1|256|256|256|0|1|0|4|3"):
+        assert k in keys and keys[k] >= 4   # carry storage steps with the register kernel
+    monkeypatch.delenv("SETD_TUNE_CACHE", raising=False)
+    path = bench.use_tuned_table()
+    try:
+        assert os.environ["SETD_TUNE_CACHE"] == path and path != bench.TUNED_TABLE
+        assert open(path).read() == open(bench.TUNED_TABLE).read()
+    finally:
+        os.remove(path)
+        monkeypatch.delenv("SETD_TUNE_CACHE", raising=False)

@@ -609,12 +609,13 @@ VARIANT_CASES = [
 
 
 @pytest.mark.parametrize("variant", ["0,0,0", "1,1,1", "2,2,2", "3,3,3", "1,2,3", "3,0,1", "0,4,0", "2,5,3",
-                                     "5,4,0", "14,1,1", "11,5,2", "15,0,3", "1,6,1", "0,9,2", "3,11,0"])
+                                     "5,4,0", "14,1,1", "11,5,2", "15,0,3", "1,6,1", "0,9,2", "3,11,0",
+                                     "1,12,1", "2,15,0"])
 @pytest.mark.parametrize("history", [0, 1])
 def test_every_kernel_variant_matches_oracle(variant, history, monkeypatch):
     """Each autotuner choice (row: LDS padding x block size x row-pair groups
     per workgroup; axis passes: tile width x columns per thread; axis-0
-    variants 4 and up: the register-update kernel at two tile widths, items
+    variants 4 and up: the register-update kernel at three tile widths, items
     interleaved per tile in groups of 1, 2, 4 or 8) gives the same
     trajectory, with either SETD2 storage (the carry-only storage always
     steps with the register kernel)."""
@@ -669,14 +670,15 @@ def test_full_configurations_run_to_completion():
     g.close()
 
 
-@pytest.mark.parametrize("variant", ["1,4,1", "1,6,1", "1,9,1", "1,11,1"])
+@pytest.mark.parametrize("variant", ["1,4,1", "1,6,1", "1,9,1", "1,11,1", "1,13,1", "1,15,1"])
 def test_item_groups_are_bitwise_the_same(variant, monkeypatch):
     """The item interleaving of the register axis-0 kernel changes only which
     block runs when: every realization's trajectory is bitwise that of the
-    item-after-item order (variant 4 / 5 at the same tile width)."""
+    item-after-item order (variant 4 / 5 / 12 at the same tile width)."""
     S = _setd()
     p = W.model_b([128, 128], precision=32, realizations=7)
-    base = "1,%d,1" % (4 + (int(variant.split(",")[1]) - 4) % 2)
+    v = int(variant.split(",")[1])
+    base = "1,%d,1" % (12 if v >= 12 else 4 + (v - 4) % 2)
     monkeypatch.setenv("SETD_VARIANT", base)
     ref = S.Plan(p)
     monkeypatch.setenv("SETD_VARIANT", variant)
