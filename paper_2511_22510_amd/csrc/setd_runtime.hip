@@ -688,13 +688,16 @@ setd_status Plan::autotune()
     // whole steps with the realizations in one launch per pass, or split in
     // halves over two streams
     if (st == SETD_OK && aux && R >= 2) {
-        // each choice timed twice, interleaved, best of the two
+        // each choice timed three times over 24 steps (a split call pays its
+        // fork and join once, and the two halves settle into their overlap
+        // over the first steps), interleaved, best of the three
+        constexpr int NS = 24;
         float ms_split[2] = {1e30f, 1e30f};
-        if ((st = run_steps(2, 1)) == SETD_OK) st = run_steps(2, 2);   // warm-up
-        for (int rep = 0; rep < 4 && st == SETD_OK; rep++) {
-            const int sp = 1 + (rep & 1);
+        for (int sp = 1; sp <= 2 && st == SETD_OK; sp++) st = run_steps(2, sp);   // warm-up
+        for (int rep = 0; rep < 6 && st == SETD_OK; rep++) {
+            const int sp = 1 + rep % 2;
             if (hipEventRecord(e0, stream) != hipSuccess) { st = fail(SETD_E_DEVICE, "event record failed"); break; }
-            if ((st = run_steps(6, sp)) != SETD_OK) break;
+            if ((st = run_steps(NS, sp)) != SETD_OK) break;
             if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                 st = fail(SETD_E_DEVICE, "event wait failed");
                 break;
@@ -703,7 +706,7 @@ setd_status Plan::autotune()
             (void)hipEventElapsedTime(&ms, e0, e1);
             ms_split[sp - 1] = std::min(ms_split[sp - 1], ms);
             if (const char* vb = std::getenv("SETD_TUNE_VERBOSE"))
-                if (vb[0] == '1') fprintf(stderr, "setd tune %s streams %d: %.1f us per step\n", key.c_str(), sp, ms * 1e3f / 6);
+                if (vb[0] == '1') fprintf(stderr, "setd tune %s streams %d: %.1f us per step\n", key.c_str(), sp, ms * 1e3f / NS);
         }
         // keep the split only for a clear gain
         tune.split = (st == SETD_OK && ms_split[1] < 0.98f * ms_split[0]) ? 2 : 1;

@@ -114,3 +114,29 @@ def test_shipped_variant_table_parses_and_covers_the_timed_workloads(monkeypatch
     finally:
         os.remove(path)
         monkeypatch.delenv("SETD_TUNE_CACHE", raising=False)
+
+
+def test_event_gap_is_subtracted_only_for_one_stream():
+    """The dispatch gap the per-pass events add is the bracketed sum less the
+    uninstrumented step time on one stream; a plan stepping on two streams
+    overlaps its halves in the uninstrumented step, so its brackets stand."""
+    import numpy as np
+    from paper_2511_22510_amd import workloads as W
+    p = W.problem(W.CONFIG_B)
+
+    class Info:
+        pass
+
+    def run(streams):
+        info = Info()
+        info.streams = streams
+        info.pass_bytes = [1e8, 2e8, 0.0, 0.0]
+        prof = np.array([[2.5, 100.0], [4.0, 100.0]])   # 25 and 40 us per launch
+        r = dict(info=info, ev=100 * 60e-6, steps=100, prof=prof)   # 60 us per plain step
+        return bench.pass_roofline(r, p, ["row", "axis0"])[0]
+
+    one, two = run(1), run(2)
+    assert one["kernel"] == two["kernel"] == "axis0"
+    assert abs(one["event_gap_us"] - 2.5) < 1e-9 and abs(one["avg_launch_us"] - 37.5) < 1e-9
+    assert two["event_gap_us"] == 0.0 and abs(two["avg_launch_us"] - 40.0) < 1e-9
+    assert one["step_streams"] == 1 and two["step_streams"] == 2
