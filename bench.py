@@ -45,17 +45,20 @@ TUNED_TABLE = os.path.join(ROOT, "paper_2511_22510_amd", "tuned_mi355x.txt")
 
 
 def spin_up(torch, seconds=1.0):
-    """Device work unrelated to the measured plans (an elementwise loop on a
-    64 MiB tensor) for about `seconds`, so that a timed segment starts at the
-    GPU's steady clocks: right after a plan's setup, the first 400 Model B
-    steps were measured 8% slower than the next 400."""
-    a = torch.ones(1 << 24, device="cuda")
+    """Device work unrelated to the measured plans for about `seconds` (8192^2
+    FP32 products and 256 MiB copies: long kernels, so that a profiler's
+    trace stays small), so that a timed segment starts at the GPU's steady
+    clocks: right after a plan's setup, the first 400 Model B steps were
+    measured 8% slower than the next 400."""
+    a = torch.full((8192, 8192), 1.0 / 8192, device="cuda")
+    c = torch.empty_like(a)
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        for _ in range(20):
-            a.mul_(0.999).add_(0.001)
+        torch.mm(a, a, out=c)
+        for _ in range(4):
+            c.copy_(a)
         torch.cuda.synchronize()
-    del a
+    del a, c
 
 
 def use_tuned_table():

@@ -375,7 +375,10 @@ def test_graph_replays_match_eager_launches(p, split, monkeypatch):
                                W.kpz([64, 64], precision=32, realizations=2, ic_kind=1, ic_sigma=0.2),
                                W.cgl([32, 32], precision=32, realizations=2),
                                W.cgl([32, 32, 32], precision=64, realizations=2),
-                               W.model_a([16, 16, 16], precision=32, realizations=2, order=2)])
+                               W.model_a([16, 16, 16], precision=32, realizations=2, order=2),
+                               # phase-shift dealiasing: |a_i| < N_i/2 kept
+                               W.model_b([32, 32], precision=64, realizations=2, dealias=2),
+                               W.cgl([16, 16, 16], precision=64, realizations=2, dealias=2)])
 def test_response_matches_oracle(p):
     """Linear response by the noise correlation (App. C): the device regenerates
     the kick's noise with the step's own generator and precision, divides by the
@@ -403,7 +406,8 @@ def test_response_matches_oracle(p):
 @pytest.mark.parametrize("p,M", [(W.model_a([32, 32], precision=64, realizations=3, order=2), 16),
                                  (W.model_b([32, 32], precision=32, realizations=2), 32),
                                  (W.kpz([32, 32], precision=32, realizations=2, ic_kind=1, ic_sigma=0.2), 16),
-                                 (W.cgl([16, 16, 16], precision=64, realizations=2), 8)])
+                                 (W.cgl([16, 16, 16], precision=64, realizations=2), 8),
+                                 (W.model_a([32, 32], precision=64, realizations=2, order=2, dealias=2), 16)])
 def test_spectrum_matches_oracle(p, M):
     """App. C time-frequency observables of a window of M steps: the device
     records the stored spectrum after every step, transforms each mode's
@@ -472,7 +476,8 @@ def test_fdt_deviation_matches_oracle(p, M):
                                W.kpz([32, 32], precision=32, realizations=2, dealias=0, ic_kind=1, ic_sigma=0.2),
                                W.kpz([64, 64], precision=64, realizations=2, ic_kind=1, ic_sigma=0.3),
                                W.model_a([16, 16, 16], precision=32, realizations=2),
-                               W.cgl([16, 16, 16], precision=64, realizations=2)])
+                               W.cgl([16, 16, 16], precision=64, realizations=2),
+                               W.model_a([32, 32], precision=64, realizations=2, dealias=2)])
 def test_box_width_matches_oracle(p):
     """Box-averaged width w_l (Sec. 5 KPZ): the device sums the spectrum into
     the alias classes of each box size (no transform); the oracle takes box
@@ -523,7 +528,9 @@ def test_box_width_needs_equal_axes():
 def test_observables_match_oracle():
     S = _setd()
     for p in [W.model_a([64, 64], precision=64, realizations=3, order=2),
-              W.cgl([32, 32, 32], precision=64, realizations=2)]:
+              W.cgl([32, 32, 32], precision=64, realizations=2),
+              W.model_b([32, 32], precision=64, realizations=2, dealias=2),
+              W.model_a([16, 16, 16], precision=64, realizations=2, dealias=2)]:
         g = S.Plan(p)
         o = O.Sim(p)
         g.step(5)
