@@ -153,8 +153,8 @@ typedef struct {
                                  evaluated in FP64 and rounded; 64: complex128     */
     int realizations;         /* independent noise realizations in one plan (>= 1) */
     uint64_t seed;            /* Philox4x32-10 key                                 */
-    int dealias;              /* 0: none; 1: 2/3 rule, keep 3|a_i| < n[i]; 2
-                                 (Fourier-space noise): phase shift, the
+    int dealias;              /* 0: none; 1: 2/3 rule, keep 3|a_i| < n[i]; 2:
+                                 phase shift, the
                                  nonlinearity averaged over the grid and the
                                  2^d - 1 grids moved by dx/2 along each
                                  nonempty set of axes, keeping 2|a_i| < n[i]
@@ -190,9 +190,10 @@ typedef struct {
                                  per step).  On 2D/3D lattices each step first
                                  transforms its site noise into a noise array
                                  (more workspace, more bytes per step) and the
-                                 plan keeps phi and F_{n-1} (no carry).  Not with
-                                 dealias 2.  The kick estimators
-                                 (SETD_OBS_KICK / RESPONSE / SPECTRUM) need 0.  */
+                                 plan keeps phi and F_{n-1} (no carry).  A 1D
+                                 line does not take it with dealias 2.  The kick
+                                 estimators (SETD_OBS_KICK / RESPONSE /
+                                 SPECTRUM) need 0.                               */
 } setd_desc;
 
 /* Derived sizes of a plan (filled by setd_plan_info). */

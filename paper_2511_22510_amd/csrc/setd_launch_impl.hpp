@@ -272,8 +272,8 @@ static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int
         if (var >= 4) var = (var >= 12 || (var - 4) % 2 == 0) ? 3 : 0;
         if (g.dealias == 2) {
             hipError_t e = launch_axis0_ps<T, N>(g, items, nitems, mode, sub, s);
-            if (e == hipSuccess && (mode == MODE_STEP || mode == MODE_IC))
-                e = launch_hermitian_t<T>(g, items, nitems, 0, sub, s);
+            if (e == hipSuccess && (mode == MODE_STEP || mode == MODE_IC || mode == MODE_RSN))
+                e = launch_hermitian_t<T>(g, items, nitems, mode == MODE_RSN ? 2 : 0, sub, s);
             return e;
         }
     }

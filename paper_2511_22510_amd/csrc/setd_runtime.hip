@@ -61,8 +61,8 @@ setd_status validate(const setd_desc& d)
     if (d.dealias == 2 && d.ndim >= 2 && d.nl == NL_KPZ)
         return fail(SETD_E_UNSUPPORTED, "phase-shift dealiasing on 2D/3D lattices is built for the phi^3 and CGL "
                                         "terms (the 2/3 rule is already exact for the quadratic KPZ term)");
-    if (d.dealias == 2 && d.noise_space == 1)
-        return fail(SETD_E_UNSUPPORTED, "phase-shift dealiasing is not combined with real-space noise");
+    if (d.dealias == 2 && d.noise_space == 1 && d.ndim == 1)
+        return fail(SETD_E_UNSUPPORTED, "a 1D line does not combine phase-shift dealiasing with real-space noise");
     if (d.series_len != 0 && !pow2_in(d.series_len, 8, 1024))
         return fail(SETD_E_INVAL, "series_len must be 0 or a power of two in [8, 1024]");
     if (d.ic_kind != 0 && d.ic_kind != 1) return fail(SETD_E_INVAL, "ic_kind must be 0 or 1");

@@ -263,7 +263,6 @@ def test_line_phase_shift_parity(p):
 def test_phase_shift_limits():
     S = _setd()
     for bad in (W.kpz([32, 32], precision=32, dealias=2),
-                W.model_a([32, 32], precision=32, dealias=2, noise_space=1),
                 W.model_a([64], precision=32, dealias=2, noise_space=1)):
         with pytest.raises(S.SetdError) as e:
             S.Plan(bad)

@@ -196,11 +196,16 @@ PS_CASES = [
     W.cgl([16, 16, 16], precision=64, realizations=2, dealias=2),
     W.cgl([32, 16, 32], precision=32, order=1, realizations=1, dealias=2),
     W.model_a([8, 8, 8], precision=32, order=2, realizations=3, dealias=2),
+    # with the noise drawn in real space
+    W.model_b([32, 64], precision=64, realizations=2, dealias=2, noise_space=1),
+    W.cgl([32, 32], precision=32, realizations=1, dealias=2, noise_space=1),
+    W.model_a([16, 16, 32], precision=32, order=1, realizations=2, dealias=2, noise_space=1),
+    W.cgl([16, 16, 16], precision=64, realizations=1, dealias=2, noise_space=1),
 ]
 
 
-@pytest.mark.parametrize("p", PS_CASES, ids=lambda p: "ps-%s-%s-f%d-o%d" % (
-    p["nl"], "x".join(map(str, p["n"])), p["precision"], p["order"]))
+@pytest.mark.parametrize("p", PS_CASES, ids=lambda p: "ps-%s-%s-f%d-o%d-n%d" % (
+    p["nl"], "x".join(map(str, p["n"])), p["precision"], p["order"], p.get("noise_space", 0)))
 def test_phase_shift_lattice_parity(p):
     """The row pass evaluates the nonlinearity on the rows and on the rows
     moved by dx/2, for pre and for its axis-0-shifted copy (3D: for the four
