@@ -162,8 +162,7 @@ typedef struct {
                                  2D/3D plans with dealias 2 keep phi and
                                  F_{n-1} (no carry) and take 2^(d-1) times the
                                  transforms of a 2/3 step (3D: four copies of
-                                 the n0 n1 (n2/2+1) line buffer); not with KPZ
-                                 on 2D/3D lattices                           */
+                                 the n0 n1 (n2/2+1) line buffer)             */
     int ic_kind;              /* 0: phi = 0; 1: i.i.d. N(0, ic_sigma^2) per site
                                  (complex fields: ic_sigma (z1 + i z2))             */
     double ic_sigma;

@@ -298,7 +298,11 @@ __device__ __forceinline__ unsigned xcd_logical(unsigned L, unsigned G)
 // moved by dx/2 along the row (e^{i pi a/N} per bin) go through the stages
 // together and their transforms are averaged, the second moved back; 2D: rows
 // of pre (sel 0) or of its axis-0-shifted copy preb (sel 1); 3D: rows of grid
-// sel of the four grids in big.
+// sel of the four grids in big; 4 = KPZ step with phase shifts (2D): the two
+// rows' gradient lines and their copies moved along the row (four lines)
+// through the inverse stages together, the squares of each pair packed, both
+// packed lines forward and averaged, the second moved back; rows of pre and
+// pre1 (sel 0) or of preb and pre1b (sel 1).
 // DA: the 2/3 rule is on; then bins q = 0, 1 (k < N/4) always hold a stored
 // mode, q = 6, 7 (k >= 3N/4) always its mirror, q = 3, 4 never any, and only
 // q = 0..2 are written back, all decided at compile time.
@@ -316,8 +320,10 @@ __device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, co
     constexpr int TPL = N / 8;
     constexpr uint32_t ES = sizeof(cx<T>);
     const int l = tid / TPL, t = tid - l * TPL;
-    // KPZ and phase-shift steps hold two lines per row pair in LDS
-    cx<T>* L = lds + l * ((KIND == 1 || KIND == 3) ? 2 : 1) * lds_len<N, PAD>();
+    // KPZ and phase-shift steps hold two lines per row pair in LDS, KPZ with
+    // phase shifts four
+    constexpr int LINES = KIND == 4 ? 4 : ((KIND == 1 || KIND == 3) ? 2 : 1);
+    cx<T>* L = lds + l * LINES * lds_len<N, PAD>();
     const Geo& g = a.g;
     const int last = g.ndim - 1;
     LineTw<T, N> tw;
@@ -338,7 +344,7 @@ __device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, co
     const int nrow = min(2 * a.lpw * niter, a.nrows - row0);
     const size_t boff = (size_t)row0 * pitch;
     cx<T>* const bufp =
-        (g.ndim == 2 ? reinterpret_cast<cx<T>*>((KIND == 3 && sel) ? it.preb : it.pre0)
+        (g.ndim == 2 ? reinterpret_cast<cx<T>*>(((KIND == 3 || KIND == 4) && sel) ? it.preb : it.pre0)
                      : reinterpret_cast<cx<T>*>(it.big) + (KIND == 3 ? (size_t)sel * g.n[0] * g.n[1] * pitch : 0)) +
         boff;
     const rsrc_t rb = make_rsrc(bufp, (uint32_t)nrow * (uint32_t)pitch * ES);
@@ -377,8 +383,9 @@ __device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, co
                 X[s][q] = czero<T>();
                 if (empty(q)) continue;
                 const uint32_t c = col_off(q, vi) + oa + (s ? RS : 0u);
-                if constexpr (KIND == 1) {
-                    const rsrc_t rb2 = make_rsrc(reinterpret_cast<cx<T>*>(it.pre1) + boff, (uint32_t)nrow * RS);
+                if constexpr (KIND == 1 || KIND == 4) {
+                    const rsrc_t rb2 =
+                        make_rsrc(reinterpret_cast<cx<T>*>((KIND == 4 && sel) ? it.pre1b : it.pre1) + boff, (uint32_t)nrow * RS);
                     A[s][q] = bload<T>(rb2, c, 0);
                     X[s][q] = bload<T>(rb, c, 0);
                 } else {
@@ -411,7 +418,7 @@ __device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, co
                     v[q] = {sig * za, sig * zc};
                 }
             }
-        } else if constexpr (KIND == 1) {
+        } else if constexpr (KIND == 1 || KIND == 4) {
             // |grad h|^2 with d0 h = IFFT[i k0 h] (from pre1) and d1 h = IFFT[i k1 h];
             // the two rows' lines go through the stages together (one set of
             // barriers, twice the independent work per exchange), interleaved in LDS
@@ -445,12 +452,42 @@ __device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, co
                 }
             }
             if (PF && i + 1 < niter) load_rows(i + 1);
-            fft_lines<T, N, +1, PAD, 2>(w, t, L, 2, 1, twp);
+            if constexpr (KIND == 4) {
+                // the lines as they are and moved by dx/2 along the row: the
+                // squares of each pair packed, both transformed forward and
+                // averaged with the second moved back
+                cx<T> w4[4][8], phs[8];
 #pragma unroll
-            for (int q = 0; q < 8; q++) {
-                const T x0 = w[0][q].x * inv, y0 = w[0][q].y * inv;
-                const T x1 = w[1][q].x * inv, y1 = w[1][q].y * inv;
-                v[q] = {x0 * x0 + y0 * y0, x1 * x1 + y1 * y1};
+                for (int q = 0; q < 8; q++) {
+                    phs[q] = cispi<T>((T)sgn_idx(t + q * TPL, N) / (T)N);
+#pragma unroll
+                    for (int s = 0; s < 2; s++) {
+                        w4[s][q] = w[s][q];
+                        w4[2 + s][q] = cmul(phs[q], w[s][q]);
+                    }
+                }
+                fft_lines<T, N, +1, PAD, 4>(w4, t, L, 4, 1, twp);
+                cx<T> sq[2][8];
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        const T x0 = w4[2 * u][q].x * inv, y0 = w4[2 * u][q].y * inv;
+                        const T x1 = w4[2 * u + 1][q].x * inv, y1 = w4[2 * u + 1][q].y * inv;
+                        sq[u][q] = {x0 * x0 + y0 * y0, x1 * x1 + y1 * y1};
+                    }
+                }
+                fft_lines<T, N, -1, PAD, 2>(sq, t, L, 2, 1, twp);
+#pragma unroll
+                for (int q = 0; q < 8; q++) v[q] = T(0.5) * (sq[0][q] + cmulc(sq[1][q], phs[q]));
+            } else {
+                fft_lines<T, N, +1, PAD, 2>(w, t, L, 2, 1, twp);
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const T x0 = w[0][q].x * inv, y0 = w[0][q].y * inv;
+                    const T x1 = w[1][q].x * inv, y1 = w[1][q].y * inv;
+                    v[q] = {x0 * x0 + y0 * y0, x1 * x1 + y1 * y1};
+                }
             }
         } else {
 #pragma unroll
@@ -507,7 +544,7 @@ __device__ __forceinline__ void row_real_body(const RowArgs& a, const int bx, co
             }
         }
 
-        if constexpr (KIND != 3) fft_line<T, N, -1, PAD>(v, t, L, 1, twp);
+        if constexpr (KIND != 3 && KIND != 4) fft_line<T, N, -1, PAD>(v, t, L, 1, twp);
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 8; q++) {
@@ -753,9 +790,10 @@ __global__ void __launch_bounds__(256) k_rsn_rows(RsnArgs a)
 // the axis-0 inverse of e^{i pi a0/N0} phi.  A step transforms both forward
 // (the passes before have already averaged each over the grids moved along
 // the other axes), takes X = (X_pre + e^{-i pi a0/N0} X_preb) / 2 as the
-// nonlinear term (the mean over the 2^d grids), and after the update transforms phi and
-// e^{i pi a0/N0} phi back into pre and preb; the second half of the LDS holds
-// the shifted lines.
+// nonlinear term (the mean over the 2^d grids), and after the update
+// transforms phi and e^{i pi a0/N0} phi back into pre and preb (KPZ: also
+// i k0 of each into pre1 and pre1b); the second half of the LDS holds the
+// shifted lines.
 template <typename T, int N0, int TILE, int PAD, bool KPZ, int LPT, bool PS>
 __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
 {
@@ -966,7 +1004,10 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
             }
         }
     }
+    // KPZ: i k0 phi for the second inverse (with phase shifts also of the
+    // shifted copy)
     cx<T> v2[KPZ ? LPT : 1][8];
+    cx<T> v2b[(KPZ && PS) ? LPT : 1][8];
     if constexpr (KPZ) {
 #pragma unroll
         for (int k = 0; k < LPT; k++) {
@@ -975,6 +1016,7 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
                 const int j0 = t + q * TPL;
                 const T kk = (2 * j0 == N0) ? T(0) : dk0 * (T)sgn_idx(j0, N0);
                 v2[k][q] = {-kk * v[k][q].y, kk * v[k][q].x};
+                if constexpr (PS) v2b[k][q] = {-kk * vb[k][q].y, kk * vb[k][q].x};
             }
         }
     }
@@ -1004,6 +1046,17 @@ __global__ void __launch_bounds__(TILE / LPT * N0 / 8) k_axis0(AxisArgs a)
             if (cv[k]) {
 #pragma unroll
                 for (int q = 0; q < 8; q++) pre1[(size_t)(t + q * TPL) * lstride + plane + col[k]] = v2[k][q];
+            }
+        }
+    }
+    if constexpr (KPZ && PS) {
+        cx<T>* __restrict__ pre1b = reinterpret_cast<cx<T>*>(it.pre1b);
+        fft_lines<T, N0, +1, PAD, LPT>(v2b, t, LB, TILE, CW, tw);
+#pragma unroll
+        for (int k = 0; k < LPT; k++) {
+            if (cv[k]) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) pre1b[(size_t)(t + q * TPL) * lstride + plane + col[k]] = v2b[k][q];
             }
         }
     }

@@ -38,13 +38,19 @@ static hipError_t launch_row_np(const Geo& g, const Item* items, int nitems, int
                                 int iter, bool kpz, hipStream_t s)
 {
     constexpr int tpl = N / 8;
-    // KPZ and phase-shift steps hold two lines per row (pair); 256-thread
-    // blocks fall back to one wavefront's groups where they would pass 64 KiB
+    // KPZ and phase-shift steps hold two lines per row (pair), KPZ with phase
+    // shifts four; 256-thread blocks fall back to one wavefront's groups where
+    // they would pass 64 KiB, and padded LDS to unpadded where even those would
     const bool ps = g.dealias == 2 && g.ndim >= 2 && mode == MODE_STEP;
-    const bool two = (kpz && !g.cplx) || ps;
+    const bool kreal = kpz && !g.cplx;
+    const int nlines = (ps && kreal) ? 4 : ((kreal || ps) ? 2 : 1);
     const int small = tpl >= 64 ? 1 : 64 / tpl;
+    if constexpr (PAD > 0) {
+        if ((size_t)small * lds_len<N, PAD>() * 2 * sizeof(T) * nlines > 65536)
+            return launch_row_np<T, N, 0>(g, items, nitems, mode, sub, big_block, iter, kpz, s);
+    }
     int lpw = big_block ? (tpl >= 256 ? 1 : 256 / tpl) : small;
-    if ((size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T) * (two ? 2 : 1) > 65536) lpw = small;
+    if ((size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T) * nlines > 65536) lpw = small;
     RowArgs a;
     a.g = g;
     a.items = items;
@@ -57,19 +63,20 @@ static hipError_t launch_row_np(const Geo& g, const Item* items, int nitems, int
     const int groups = (lines + lpw - 1) / lpw;
     if (ps) {
         // phase shifts: the rows of pre and of its shifted copy (2D) or of the
-        // four grids in big (3D), grid z; two lines per row group in LDS, one
-        // group at a time
+        // four grids in big (3D), grid z; two (KPZ: four) lines per row group
+        // in LDS, one group at a time
         a.iter = 1;
         dim3 gps(groups, nitems, g.ndim == 3 ? 4 : 2);
-        const size_t lps = (size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T) * 2;
+        const size_t lps = (size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T) * nlines;
         if (g.cplx) hipLaunchKernelGGL((k_row_cplx<T, N, PAD, false, true>), gps, dim3(lpw * tpl), lps, s, a);
+        else if (kreal) hipLaunchKernelGGL((k_row_real<T, N, PAD, 4, false, false>), gps, dim3(lpw * tpl), lps, s, a);
         else hipLaunchKernelGGL((k_row_real<T, N, PAD, 3, false, false>), gps, dim3(lpw * tpl), lps, s, a);
         return hipGetLastError();
     }
     dim3 grid((groups + a.iter - 1) / a.iter, nitems);
     dim3 block(lpw * tpl);
     // KPZ steps hold two lines per row pair
-    const size_t lds = (size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T) * ((kpz && !g.cplx) ? 2 : 1);
+    const size_t lds = (size_t)lpw * lds_len<N, PAD>() * 2 * sizeof(T) * nlines;
     if (g.cplx) {
         if (mode == MODE_IC) hipLaunchKernelGGL((k_row_cplx<T, N, PAD, true>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((k_row_cplx<T, N, PAD, false>), grid, block, lds, s, a);
@@ -151,7 +158,8 @@ static hipError_t launch_axis_nt(const Geo& g, const Item* items, int nitems, in
 // half-width tile, one column per thread, LDS for the lines and their shifted
 // copies (padded only where both halves fit 64 KiB)
 template <typename T, int N>
-static hipError_t launch_axis0_ps(const Geo& g, const Item* items, int nitems, int mode, int sub, hipStream_t s)
+static hipError_t launch_axis0_ps(const Geo& g, const Item* items, int nitems, int mode, int sub, bool kpz,
+                                  hipStream_t s)
 {
     constexpr int TILE = tile_max<T>(N) / 2;
     constexpr int PAD = ((size_t)2 * TILE * lds_len<N, 3>() * 2 * sizeof(T) <= 65536) ? 3 : 0;
@@ -164,8 +172,12 @@ static hipError_t launch_axis0_ps(const Geo& g, const Item* items, int nitems, i
     a.per_item = a.ntiles * ((g.ndim == 3) ? g.kept[1] : 1);
     a.mode = mode;
     a.sub = sub;
-    hipLaunchKernelGGL((k_axis0<T, N, TILE, PAD, false, 1, true>), dim3(a.per_item * nitems), dim3(TILE * (N / 8)), lds,
-                       s, a);
+    if (kpz && g.ndim == 2)
+        hipLaunchKernelGGL((k_axis0<T, N, TILE, PAD, true, 1, true>), dim3(a.per_item * nitems), dim3(TILE * (N / 8)),
+                           lds, s, a);
+    else
+        hipLaunchKernelGGL((k_axis0<T, N, TILE, PAD, false, 1, true>), dim3(a.per_item * nitems), dim3(TILE * (N / 8)),
+                           lds, s, a);
     return hipGetLastError();
 }
 
@@ -271,7 +283,7 @@ static hipError_t launch_axis_n(const Geo& g, const Item* items, int nitems, int
         }
         if (var >= 4) var = (var >= 12 || (var - 4) % 2 == 0) ? 3 : 0;
         if (g.dealias == 2) {
-            hipError_t e = launch_axis0_ps<T, N>(g, items, nitems, mode, sub, s);
+            hipError_t e = launch_axis0_ps<T, N>(g, items, nitems, mode, sub, kpz, s);
             if (e == hipSuccess && (mode == MODE_STEP || mode == MODE_IC || mode == MODE_RSN))
                 e = launch_hermitian_t<T>(g, items, nitems, mode == MODE_RSN ? 2 : 0, sub, s);
             return e;

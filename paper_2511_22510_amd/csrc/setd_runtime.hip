@@ -58,9 +58,6 @@ setd_status validate(const setd_desc& d)
     if (d.precision != 32 && d.precision != 64) return fail(SETD_E_INVAL, "precision must be 32 or 64");
     if (d.realizations < 1) return fail(SETD_E_INVAL, "realizations must be >= 1");
     if (d.dealias < 0 || d.dealias > 2) return fail(SETD_E_INVAL, "dealias must be 0, 1 or 2");
-    if (d.dealias == 2 && d.ndim >= 2 && d.nl == NL_KPZ)
-        return fail(SETD_E_UNSUPPORTED, "phase-shift dealiasing on 2D/3D lattices is built for the phi^3 and CGL "
-                                        "terms (the 2/3 rule is already exact for the quadratic KPZ term)");
     if (d.dealias == 2 && d.noise_space == 1 && d.ndim == 1)
         return fail(SETD_E_UNSUPPORTED, "a 1D line does not combine phase-shift dealiasing with real-space noise");
     if (d.series_len != 0 && !pow2_in(d.series_len, 8, 1024))
@@ -236,6 +233,7 @@ setd_status Plan::init(const setd_desc& desc)
         lay.noise = take((size_t)R * Sb);
     }
     if (ps_grid()) lay.preb = take((size_t)R * Pb);
+    if (ps_grid() && d.nl == NL_KPZ) lay.pre1b = take((size_t)R * Pb);
     if (iso) {
         lay.boxn = 0;
         for (int l = 2; l <= d.n[0]; l *= 2) {
@@ -284,8 +282,11 @@ void Plan::pass_bytes(double* out) const
         const double pre = (double)g.n[0] * kl;
         if (ps_grid()) {
             // phase shifts: pre and its shifted copy in and out of both passes
-            out[0] = 4.0 * pre * e;
-            out[1] = (4.0 * pre + (2.0 + hist) * st) * e;
+            // (KPZ: the row pass also reads pre1 and pre1b, which the axis-0
+            // pass writes)
+            const double g2 = (d.nl == NL_KPZ) ? 2.0 : 0.0;
+            out[0] = (4.0 + g2) * pre * e;
+            out[1] = (4.0 + g2 + (2.0 + hist) * st / pre) * pre * e;
             return;
         }
         const double npre = (d.nl == NL_KPZ) ? 2.0 : 1.0;
@@ -455,6 +456,7 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
         it.npre = rsn_grid() ? ws + lay.npre + (size_t)r * Pb : nullptr;
         it.noise = rsn_grid() ? ws + lay.noise + (size_t)r * Sb : nullptr;
         it.preb = ps_grid() ? ws + lay.preb + (size_t)r * Pb : nullptr;
+        it.pre1b = (ps_grid() && d.nl == NL_KPZ) ? ws + lay.pre1b + (size_t)r * Pb : nullptr;
         it.coef = ws + ((d.precision == 32) ? lay.coef32 : lay.coef64);
         const size_t* tw = (d.precision == 32) ? lay.tw32 : lay.tw64;
         it.tw0 = ws + tw[0];
@@ -540,6 +542,10 @@ setd_status Plan::bind(void* dev, size_t bytes, hipStream_t s)
     if (d.order == 2 && (st = zero(lay.prev, (size_t)R * Sb)) != SETD_OK) return st;
     if ((st = zero(lay.pre0, (size_t)R * Pb)) != SETD_OK) return st;
     if (d.nl == NL_KPZ && (st = zero(lay.pre1, (size_t)R * Pb)) != SETD_OK) return st;
+    // the shifted intermediates of a phase-shift plan: a step reads them
+    // before writing them, and a zero initial field writes nothing at bind
+    if (ps_grid() && (st = zero(lay.preb, (size_t)R * Pb)) != SETD_OK) return st;
+    if (ps_grid() && d.nl == NL_KPZ && (st = zero(lay.pre1b, (size_t)R * Pb)) != SETD_OK) return st;
     if (B && (st = zero(lay.big, (size_t)R * Bb)) != SETD_OK) return st;
     if ((st = zero(lay.snap, (size_t)R * Sb)) != SETD_OK) return st;
 

@@ -30,7 +30,8 @@ struct Layout {
     size_t twm64 = 0, twm32 = 0, specacc = 0, series = 0, fdtacc = 0;   // time series (series_len > 0)
     size_t boxcls = 0, boxn = 0;  // box-width class sums and their count (equal n[i])
     size_t npre = 0, noise = 0;   // real-space noise on 2D/3D lattices: intermediate, eta_a
-    size_t preb = 0;              // phase-shift dealiasing (2D): the shifted intermediate
+    size_t preb = 0;              // phase-shift dealiasing: the shifted intermediate
+    size_t pre1b = 0;             // KPZ with phase shifts: the shifted gradient intermediate
     size_t total = 0;
 };
 

@@ -48,7 +48,8 @@ struct Item {
     void* snap;       // snapshot of phi for two-time correlations
     void* npre;       // real-space noise (2D/3D): its transform over the last axes, laid out as pre0
     void* noise;      // real-space noise (2D/3D): eta_a of the step in the stored layout of phi
-    void* preb;       // phase-shift dealiasing (2D): axis-0 inverse of e^{i pi a0/N0} phi, laid out as pre0
+    void* preb;       // phase-shift dealiasing: axis-0 inverse of e^{i pi a0/N0} phi, laid out as pre0
+    void* pre1b;      // KPZ with phase shifts: axis-0 inverse of e^{i pi a0/N0} i k0 phi, laid out as pre0
     const void* coef; // coefficient table in the state precision
     const void* tw0;  // twiddles exp(-2 pi i k / n_axis), state precision
     const void* tw1;
