@@ -189,9 +189,8 @@ typedef struct {
                                  per step).  On 2D/3D lattices each step first
                                  transforms its site noise into a noise array
                                  (more workspace, more bytes per step) and the
-                                 plan keeps phi and F_{n-1} (no carry).  A 1D
-                                 line does not take it with dealias 2.  The kick
-                                 estimators (SETD_OBS_KICK / RESPONSE /
+                                 plan keeps phi and F_{n-1} (no carry).  The
+                                 kick estimators (SETD_OBS_KICK / RESPONSE /
                                  SPECTRUM) need 0.                               */
 } setd_desc;
 

@@ -1949,7 +1949,6 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr bool DA = DM == 1, PS = DM == 2;   // 2/3 truncation, phase shift
-    static_assert(!(RS && PS), "real-space noise and phase shifts are not combined");
     constexpr int TPL = N / 8, M = N / 8;
     constexpr int LPB = 256 / TPL;
     constexpr int LL = lds_len<N, PAD>();
@@ -2154,9 +2153,19 @@ __global__ void __launch_bounds__(256) k_line1d_real(Line1dArgs a)
                 }
             }
             if constexpr (PS) {
+                // (the mean is already transformed; site noise, if drawn,
+                // goes through the forward stages alone into the second half)
+                cx<T> e[RS ? 8 : 1];
+                if constexpr (RS) {
+                    site_noise(e, s);
+                    fft_line<T, N, -1, PAD>(e, t, L, 1, tw);
+                }
                 __syncthreads();
 #pragma unroll
-                for (int q = 0; q < 8; q++) L[lds_slot<PAD>(t + q * M)] = z[q];
+                for (int q = 0; q < 8; q++) {
+                    L[lds_slot<PAD>(t + q * M)] = z[q];
+                    if constexpr (RS) L[LL + lds_slot<PAD>(t + q * M)] = e[q];
+                }
                 __syncthreads();
             } else if constexpr (RS) {
                 // the nonlinearity and the site noise of both realizations
@@ -2327,7 +2336,6 @@ __global__ void __launch_bounds__(256) k_line1d_cplx(Line1dArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr bool DA = DM == 1, PS = DM == 2;   // 2/3 truncation, phase shift
-    static_assert(!(RS && PS), "real-space noise and phase shifts are not combined");
     constexpr int TPL = N / 8, M = N / 8;
     constexpr int LPB = 256 / TPL;
     constexpr int LL = lds_len<N, PAD>();
@@ -2440,7 +2448,10 @@ __global__ void __launch_bounds__(256) k_line1d_cplx(Line1dArgs a)
                     z[0][q] = {m2 * x, m2 * y};
                 }
             }
-            if constexpr (RS) {
+            if constexpr (RS && PS) {
+                // the mean is already transformed: the site noise alone
+                fft_line<T, N, -1, PAD>(e, t, L, 1, tw);
+            } else if constexpr (RS) {
                 // the nonlinearity and the site noise through the forward
                 // stages together
 #pragma unroll

@@ -480,9 +480,10 @@ hipError_t launch_line1d(const Geo& g, const Item* items, int nitems, int mode, 
                          hipStream_t s)
 {
     if (g.ndim != 1 || nitems <= 0) return hipErrorInvalidValue;
-    // dealias 0 none, 1 the 2/3 rule, 2 phase shift (not with real-space noise)
-    if (g.dealias == 2 && g.rsn) return hipErrorInvalidValue;
-    if (g.dealias == 1 && g.rsn) {
+    // dealias 0 none, 1 the 2/3 rule, 2 phase shift
+    if (g.dealias == 2 && g.rsn) {
+        SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, 2, true>(g, items, nitems, mode, sub, nsteps, nl, s)));
+    } else if (g.dealias == 1 && g.rsn) {
         SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, 1, true>(g, items, nitems, mode, sub, nsteps, nl, s)));
     } else if (g.dealias == 1) {
         SETD_DISPATCH_N(g.n[0], return (launch_line1d_n<T, NN, 1, false>(g, items, nitems, mode, sub, nsteps, nl, s)));

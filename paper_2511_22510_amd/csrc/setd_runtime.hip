@@ -58,8 +58,6 @@ setd_status validate(const setd_desc& d)
     if (d.precision != 32 && d.precision != 64) return fail(SETD_E_INVAL, "precision must be 32 or 64");
     if (d.realizations < 1) return fail(SETD_E_INVAL, "realizations must be >= 1");
     if (d.dealias < 0 || d.dealias > 2) return fail(SETD_E_INVAL, "dealias must be 0, 1 or 2");
-    if (d.dealias == 2 && d.noise_space == 1 && d.ndim == 1)
-        return fail(SETD_E_UNSUPPORTED, "a 1D line does not combine phase-shift dealiasing with real-space noise");
     if (d.series_len != 0 && !pow2_in(d.series_len, 8, 1024))
         return fail(SETD_E_INVAL, "series_len must be 0 or a power of two in [8, 1024]");
     if (d.ic_kind != 0 && d.ic_kind != 1) return fail(SETD_E_INVAL, "ic_kind must be 0 or 1");

@@ -247,25 +247,24 @@ PS_CASES = [
     W.cgl([64], precision=64, order=2, realizations=2, dealias=2),
     W.cgl([256], precision=32, order=1, realizations=1, dealias=2),
     W.model_b([8], precision=64, order=2, realizations=3, dealias=2),
+    # with the noise drawn in real space
+    W.model_a([256], precision=64, order=2, realizations=3, dx=0.25, dealias=2, noise_space=1),
+    W.kpz([1024], precision=32, order=2, realizations=2, dx=0.5, lam=50.0, D=0.01, h=2e-3, dealias=2, noise_space=1),
+    W.cgl([64], precision=64, order=2, realizations=2, dealias=2, noise_space=1),
+    W.cgl([32], precision=32, order=1, realizations=1, dealias=2, noise_space=1),
+    W.model_a([128], precision=64, nl="none", u=0.0, r=0.5, realizations=3, dealias=2, noise_space=1),
 ]
 
 
-@pytest.mark.parametrize("p", PS_CASES, ids=lambda p: "ps-%s-%d-f%d-o%d-R%d" % (
-    p["nl"], p["n"][0], p["precision"], p["order"], p["realizations"]))
+@pytest.mark.parametrize("p", PS_CASES, ids=lambda p: "ps-%s-%d-f%d-o%d-R%d-n%d" % (
+    p["nl"], p["n"][0], p["precision"], p["order"], p["realizations"], p.get("noise_space", 0)))
 def test_line_phase_shift_parity(p):
     """Phase-shift dealiasing on a line: the grid and the grid moved by dx/2
-    through the same stages, their mean against the oracle's two transforms."""
+    through the same stages, their mean against the oracle's two transforms
+    (with real-space noise the site draws transformed on their own)."""
     err = run_pair(p, steps=60, every=30)
     say("max rel err", err)
     assert err <= TOL[p["precision"]]
-
-
-def test_phase_shift_limits():
-    S = _setd()
-    for bad in (W.model_a([64], precision=32, dealias=2, noise_space=1),):
-        with pytest.raises(S.SetdError) as e:
-            S.Plan(bad)
-        assert e.value.status == S.SETD_E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("name", ["LINE_MODEL_A", "LINE_KPZ"])

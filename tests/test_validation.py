@@ -59,7 +59,7 @@ def test_unsupported_combinations():
     assert _status(W.cgl([16, 16, 16], dealias=2))[0] == setd.SETD_OK
     assert _status(W.model_a([16, 16, 16], dealias=2, noise_space=1))[0] == setd.SETD_OK
     assert _status(W.cgl([32, 32], dealias=2, noise_space=1))[0] == setd.SETD_OK
-    assert _status(W.model_a([64], dealias=2, noise_space=1))[0] == setd.SETD_E_UNSUPPORTED
+    assert _status(W.model_a([64], dealias=2, noise_space=1))[0] == setd.SETD_OK
     assert _status(dict(W.cgl([32, 32]), nl="phi3"))[0] == setd.SETD_E_UNSUPPORTED
 
 
