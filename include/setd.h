@@ -7,7 +7,9 @@
  * stochastic exponential-time-differencing schemes SETD1 (Sec. 2 Eq. SETD1) and
  * SETD2 (Sec. 2 Eq. SETD2), evaluating F_a pseudo-spectrally (Sec. 4, the
  * algorithm box), drawing the noise directly in Fourier space (App. B) with the
- * lattice normalisation of App. A, and dealiasing by the 2/3 truncation rule.
+ * lattice normalisation of App. A, or per site in real space and transformed
+ * (Sec. 4 step 2), and dealiasing by the 2/3 truncation rule or by phase
+ * shifts (Sec. 4 step 1), on 1D, 2D and 3D periodic lattices.
  *
  * Conventions shared by every entry point:
  *  - Every call returns a setd_status.  No call aborts; setd_last_error()
