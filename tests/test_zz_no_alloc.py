@@ -108,3 +108,24 @@ def test_noalloc_rejects_a_plan_beyond_its_scratch():
         S.setd_run_noalloc(S.make_desc(small), 1, out.data_ptr(), out.numel(),
                            torch.cuda.current_stream().cuda_stream)
     assert e.value.status == S.SETD_E_INVAL
+
+
+def test_noalloc_phase_shift_plan_after_another_call():
+    """A phase-shift plan whose initial field is zero (no initial-condition
+    pass writes its shifted intermediates), run right after a call that left
+    other data in the scratch: binding clears them, so each matches its
+    bound plan."""
+    S = _setd()
+    S.run_noalloc(W.cgl([32, 32, 64], precision=32, realizations=3, seed=91), 5)   # fills the scratch
+    for p in (W.model_b([64, 64], precision=64, realizations=2, ic_kind=0, dealias=2, seed=5),
+              W.kpz([64, 64], precision=64, realizations=2, dealias=2, seed=6),
+              W.cgl([16, 16, 16], precision=64, realizations=1, ic_kind=0, dealias=2, seed=7)):
+        say("noalloc phase-shift case", p["nl"], p["n"])
+        got = S.run_noalloc(p, 20)
+        g = S.Plan(p)
+        g.step(20)
+        ref = g.get_all()
+        g.close()
+        err = relerr(got, ref)
+        say("  rel err %.3g" % err)
+        assert err <= 1e-10
