@@ -223,7 +223,8 @@ typedef struct {
     int streams;              /* 2 when setd_step runs the two halves of the
                                  realizations on the bound stream and an
                                  auxiliary one of the plan (joined again before
-                                 setd_step returns), else 1                      */
+                                 setd_step returns; calls of four or more
+                                 steps), else 1                                  */
     int graph_steps;          /* setd_step runs whole chunks of this many steps
                                  as one HIP graph captured at the first such
                                  call (environment SETD_GRAPH at bind time;

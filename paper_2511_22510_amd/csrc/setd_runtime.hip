@@ -773,7 +773,7 @@ setd_status Plan::build_graph()
 {
     if (!cap) SETD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     SETD_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
-    const setd_status st = run_steps_on(graph_chunk, tune.split, cap);
+    const setd_status st = run_steps_on(graph_chunk, graph_chunk >= 4 ? tune.split : 1, cap);
     hipGraph_t g0 = nullptr;
     const hipError_t e = hipStreamEndCapture(cap, &g0);
     if (st != SETD_OK) {
@@ -829,7 +829,7 @@ setd_status Plan::step(int64_t n)
     if (n > 0) phi_valid = !lean;
     // an open time-series window takes a sample after every step
     while (n > 0 && series_pos >= 0 && series_pos < d.series_len) {
-        setd_status st = run_steps(1, profiling ? 1 : tune.split);
+        setd_status st = run_steps(1, 1);
         if (st != SETD_OK) return st;
         phi_valid = !lean;
         step_host += 1;
@@ -846,7 +846,9 @@ setd_status Plan::step(int64_t n)
             }
             for (; left >= graph_chunk; left -= graph_chunk) SETD_HIP(hipGraphLaunch(gexec, stream));
         }
-        setd_status st = run_steps(left, tune.split);
+        // the two-stream split pays for its fork and join from about four
+        // steps per call on (one step per call measured 20% slower split)
+        setd_status st = run_steps(left, left >= 4 ? tune.split : 1);
         if (st != SETD_OK) return st;
         step_host += n;
         return SETD_OK;
